@@ -1,0 +1,152 @@
+/*
+ * dwf.h -- C ABI of libdwf, an MI355X (gfx950) solver for the 5D domain-wall
+ * fermion system of lattice QCD, standard and Neff (alpha) form.
+ *
+ * The operations follow the paper's statement of the problem
+ * (arXiv 2602.14454):
+ *   D_W     Wilson kernel D_W(-M0)                      Sec. 2.1, eq. Wilson_matrix
+ *   D       5D operator, standard form                  Sec. 2.2, eq. domainwall_general
+ *   D^(a)   Neff form (alpha)                           Sec. 2.3, eq. domainwall_neff
+ *   b5, x4  b5 = (-D_-) P^dag (0,..,0,b4), x4 = [P^dag x5]_{s=1}
+ *                                                       Sec. 2.3, eq. 5D_linear_equation
+ *   D^      even-odd Schur operator 1 - Dee^-1 Deo Doo^-1 Doe
+ *                                                       Sec. 2.3, eq. even-odd_linear_equation
+ *   solve   CG on D^dag D^ (CGNR), optionally with a low-precision inner
+ *           solve inside FP64 defect correction          Sec. 2.3 (CGNR and the
+ *                                                       single-precision-preconditioner paragraph)
+ *
+ * Status codes: every call returns an int.
+ *   DWF_OK 0, DWF_NOT_CONVERGED 1 (outputs hold the best iterate),
+ *   DWF_EINVAL -1 (bad argument / null pointer), DWF_EDIMS -2 (odd or too
+ *   small lattice extent, unsupported Ls), DWF_ENOMEM -3, DWF_EHIP -4 (HIP
+ *   runtime error), DWF_ESTATE -5 (object not ready, e.g. no gauge field),
+ *   DWF_ENAN -6 (NaN/Inf met in a reduction).
+ *   No C++ exception crosses the ABI; dwf_last_error() returns a
+ *   thread-local message describing the last failure.
+ *
+ * Canonical layouts (all buffers are DEVICE pointers owned by the caller,
+ * contiguous; the library never frees or keeps them):
+ *   lex = x + Lx*(y + Ly*(z + Lz*t)); parity = (x+y+z+t) & 1; eo = lex >> 1
+ *   gauge  complex128 U[lex][mu][row][col], mu = 0..3 <-> x,y,z,t; U_mu(x): x -> x+mu
+ *   4D     complex128 v[lex][spin][colour]
+ *   5D     complex128 v[s][lex][spin][colour], s = 0..Ls-1 (paper s = 1..Ls)
+ *   even   complex128 v[s][eo][spin][colour] over parity-0 sites
+ *   gamma matrices: chiral basis, gamma_5 = diag(1,1,-1,-1); P+ = spins 0,1.
+ *   4D boundary conditions: periodic in x, y, z; antiperiodic in t if asked.
+ *   Multi-RHS buffers are nrhs canonical vectors back to back.
+ *
+ * Streams: every call enqueues on `stream` (a hipStream_t; NULL = default
+ * stream).  Calls that return host scalars (solve, residuals, Lanczos)
+ * synchronise that stream before returning.
+ */
+#ifndef DWF_H
+#define DWF_H
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum {
+    DWF_OK = 0, DWF_NOT_CONVERGED = 1,
+    DWF_EINVAL = -1, DWF_EDIMS = -2, DWF_ENOMEM = -3, DWF_EHIP = -4,
+    DWF_ESTATE = -5, DWF_ENAN = -6
+};
+
+typedef enum { DWF_F64 = 0, DWF_F32 = 1, DWF_BF16 = 2 } dwf_prec;
+typedef enum { DWF_FULL5D = 0, DWF_EVEN5D = 1 } dwf_space;
+typedef enum { DWF_ALGO_CGNR = 0, DWF_ALGO_DC = 1, DWF_ALGO_FGCR_LEARNED = 2 } dwf_algo;
+
+typedef struct dwf_lattice dwf_lattice;
+typedef struct dwf_op dwf_op;
+
+typedef struct {
+    double   tol;         /* target true relative residual of the 5D system |b5 - D x5| / |b5| */
+    int      maxiter;     /* cap on operator applications of the (inner) CG, counted as iterations */
+    int      algo;        /* dwf_algo */
+    int      inner_prec;  /* dwf_prec of the inner CG for DWF_ALGO_DC (F32 or BF16) */
+    double   inner_tol;   /* relative reduction asked of each inner solve (DC) */
+    int      check_every; /* host convergence check period of the CG loop (>= 1) */
+    int      paper_mode;  /* 1: plain CGNR in inner_prec stopping at |r|^2/|D^dag b~|^2 < 1e-14
+                             (Sec. 3.2 criterion), no defect correction; iteration counting only */
+    void*    ptc_model;   /* dwf_ptc handle for DWF_ALGO_FGCR_LEARNED, else NULL */
+    int      restart;     /* FGCR restart length */
+} dwf_solve_params;
+
+typedef struct {
+    int    iters;              /* total CG iterations (each = one D^ and one D^dag) */
+    int    outer_iters;        /* defect-correction steps */
+    int    fallback_used;      /* 1 if a fallback path was taken (stagnation / learned failure) */
+    int    converged;
+    double true_res5;          /* |b5 - D x5| / |b5| computed in FP64 at the end */
+    double seconds;            /* wall time of the solve on the stream, b5 on device -> x5 on device */
+    double final_rel_res_even; /* recursive relative residual of the even system at exit */
+} dwf_solve_info;
+
+/* Default solve parameters (FP64 CGNR to 1e-10). */
+void dwf_solve_params_default(dwf_solve_params* p);
+
+/* ---- lattice and gauge field -------------------------------------- */
+
+/* Creates geometry (index maps, neighbour tables) for dims[4] = (Lx,Ly,Lz,Lt).
+ * Every extent must be even and >= 2 (even-odd split, Sec. 2.3).  Owns its
+ * device memory; free with dwf_lattice_destroy. */
+int dwf_lattice_create(const int dims[4], int antiperiodic_t, dwf_lattice** out);
+void dwf_lattice_destroy(dwf_lattice* lat);
+
+/* Uploads the gauge links U_mu(x) (Sec. 2.1), canonical complex128 layout.
+ * on_device = 1: U is a device pointer; 0: host pointer.  The library keeps
+ * FP64, FP32 and BF16 copies in its internal layout (links gathered per
+ * output parity, backward links stored as U^dag, antiperiodic phase folded). */
+int dwf_lattice_set_gauge(dwf_lattice* lat, const void* U, int on_device, void* stream);
+
+/* Lattice geometry queries (for tests): integer maps written to host arrays.
+ * lex_of_eo: [2][V/2]; nbr: [2][8][V/2] eo index of x +/- mu (order +x,-x,+y,-y,...). */
+int dwf_lattice_maps(const dwf_lattice* lat, int* lex_of_eo, int* nbr);
+
+/* ---- operator ------------------------------------------------------- */
+
+/* D^(alpha) with s-independent (b, c) (Sec. 2.2; Sec. 2.3 eq. domainwall_neff).
+ * 2 <= Ls <= 16.  The op references lat (lat must outlive it). */
+int dwf_op_create(dwf_lattice* lat, int Ls, double M0, double m, double b, double c,
+                  double alpha, dwf_op** out);
+void dwf_op_destroy(dwf_op* op);
+
+/* out = D^(alpha) in (space = FULL5D, 5D canonical) or D^ in (EVEN5D, even
+ * canonical); dagger = 1 applies the adjoint.  prec selects the arithmetic
+ * (inputs/outputs are complex128 and converted).  in and out must not alias. */
+int dwf_apply(const dwf_op* op, int space, int dagger, int prec, void* out, const void* in,
+              void* stream);
+
+/* out = D^dag D^ in on even canonical vectors (the CGNR normal operator). */
+int dwf_apply_normal(const dwf_op* op, int prec, void* out, const void* in, void* stream);
+
+/* b5 = (-D_-) P^dag (0, ..., 0, b4)  (Sec. 2.3, eq. 5D_linear_equation). */
+int dwf_source_4d(const dwf_op* op, void* b5, const void* b4, void* stream);
+
+/* x4 = P_- x5(s=1) + P_+ x5(s=Ls)  (Sec. 2.2 eq. 4d_quark_field). */
+int dwf_project_4d(const dwf_op* op, void* x4, const void* x5, void* stream);
+
+/* Solves D^(alpha) x5 = b5 through the even-odd Schur system (x5, b5 5D
+ * canonical).  info may be NULL.  Returns DWF_OK or DWF_NOT_CONVERGED. */
+int dwf_solve(const dwf_op* op, void* x5, const void* b5, const dwf_solve_params* prm,
+              dwf_solve_info* info, void* stream);
+
+/* |b5 - D^(alpha) x5| / |b5| in FP64. */
+int dwf_true_residual(const dwf_op* op, const void* x5, const void* b5, double* rel, void* stream);
+
+/* ---- measurement helpers ------------------------------------------ */
+
+/* Times `nrep` launches of the fused half-lattice hop kernel of D^ (the
+ * first half, out_o = Q H_oe K in_e) in precision prec on internal
+ * buffers, with HIP events on the stream the kernel runs on.  Writes the
+ * mean kernel time in ms and the algorithmic bytes of one launch. */
+int dwf_bench_hop(const dwf_op* op, int prec, int nrep, double* ms_per_launch,
+                  double* bytes_per_launch, void* stream);
+
+const char* dwf_status_string(int status);
+const char* dwf_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

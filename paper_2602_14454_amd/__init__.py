@@ -1,0 +1,249 @@
+"""Python binding of libdwf, the MI355X domain-wall fermion solver.
+
+Argument marshalling only: every step of the computation runs in the HIP
+kernels of ``libdwf.so`` (built by ``paper_2602_14454_amd.build``).  PyTorch
+is used for device memory and streams; vectors are complex128 CUDA/HIP
+tensors in the canonical layouts documented in ``include/dwf.h``.
+
+There is no CPU fallback: importing the binding without the built library,
+or calling it without a HIP device, raises.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from dataclasses import dataclass
+
+__all__ = [
+    "load", "DwfError", "SolveParams", "SolveInfo", "Lattice", "Op",
+    "F64", "F32", "BF16", "FULL5D", "EVEN5D", "ALGO_CGNR", "ALGO_DC", "ALGO_FGCR_LEARNED",
+]
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libdwf.so")
+
+F64, F32, BF16 = 0, 1, 2
+FULL5D, EVEN5D = 0, 1
+ALGO_CGNR, ALGO_DC, ALGO_FGCR_LEARNED = 0, 1, 2
+OK, NOT_CONVERGED = 0, 1
+
+
+class DwfError(RuntimeError):
+    def __init__(self, status: int, where: str, msg: str):
+        super().__init__(f"{where}: status {status} ({msg})")
+        self.status = status
+
+
+class SolveParams(ctypes.Structure):
+    _fields_ = [("tol", ctypes.c_double), ("maxiter", ctypes.c_int), ("algo", ctypes.c_int),
+                ("inner_prec", ctypes.c_int), ("inner_tol", ctypes.c_double),
+                ("check_every", ctypes.c_int), ("paper_mode", ctypes.c_int),
+                ("ptc_model", ctypes.c_void_p), ("restart", ctypes.c_int)]
+
+
+class SolveInfo(ctypes.Structure):
+    _fields_ = [("iters", ctypes.c_int), ("outer_iters", ctypes.c_int), ("fallback_used", ctypes.c_int),
+                ("converged", ctypes.c_int), ("true_res5", ctypes.c_double), ("seconds", ctypes.c_double),
+                ("final_rel_res_even", ctypes.c_double)]
+
+    def as_dict(self) -> dict:
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+_lib = None
+
+# name -> (restype, argtypes)
+_vp, _ip, _d, _i = ctypes.c_void_p, ctypes.POINTER(ctypes.c_int), ctypes.c_double, ctypes.c_int
+_dp = ctypes.POINTER(ctypes.c_double)
+SIGNATURES = {
+    "dwf_solve_params_default": (None, [ctypes.POINTER(SolveParams)]),
+    "dwf_lattice_create": (_i, [_ip, _i, ctypes.POINTER(_vp)]),
+    "dwf_lattice_destroy": (None, [_vp]),
+    "dwf_lattice_set_gauge": (_i, [_vp, _vp, _i, _vp]),
+    "dwf_lattice_maps": (_i, [_vp, _vp, _vp]),
+    "dwf_op_create": (_i, [_vp, _i, _d, _d, _d, _d, _d, ctypes.POINTER(_vp)]),
+    "dwf_op_destroy": (None, [_vp]),
+    "dwf_apply": (_i, [_vp, _i, _i, _i, _vp, _vp, _vp]),
+    "dwf_apply_normal": (_i, [_vp, _i, _vp, _vp, _vp]),
+    "dwf_source_4d": (_i, [_vp, _vp, _vp, _vp]),
+    "dwf_project_4d": (_i, [_vp, _vp, _vp, _vp]),
+    "dwf_solve": (_i, [_vp, _vp, _vp, ctypes.POINTER(SolveParams), ctypes.POINTER(SolveInfo), _vp]),
+    "dwf_true_residual": (_i, [_vp, _vp, _vp, _dp, _vp]),
+    "dwf_bench_hop": (_i, [_vp, _i, _i, _dp, _dp, _vp]),
+    "dwf_status_string": (ctypes.c_char_p, [_i]),
+    "dwf_last_error": (ctypes.c_char_p, []),
+}
+
+
+def _hip_runtimes_mapped() -> set:
+    paths = set()
+    try:
+        with open("/proc/self/maps") as f:
+            for line in f:
+                if "libamdhip64" in line:
+                    paths.add(os.path.realpath(line.split()[-1]))
+    except OSError:
+        pass
+    return paths
+
+
+def load():
+    """Load libdwf.so (raises if it has not been built).
+
+    torch is imported first so that libdwf binds to torch's HIP runtime; a
+    process with two HIP runtimes mapped is refused.
+    """
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(f"{LIB_PATH} not built; run `python -m paper_2602_14454_amd.build`")
+    import torch  # noqa: F401  (loads torch's libamdhip64 before libdwf)
+    lib = ctypes.CDLL(LIB_PATH)
+    rts = _hip_runtimes_mapped()
+    if len(rts) > 1:
+        raise ImportError(f"two HIP runtimes mapped in this process: {sorted(rts)}")
+    for name, (res, args) in SIGNATURES.items():
+        f = getattr(lib, name)
+        f.restype = res
+        f.argtypes = args
+    _lib = lib
+    return lib
+
+
+def _check(status: int, where: str):
+    if status < 0:
+        lib = load()
+        raise DwfError(status, where, lib.dwf_last_error().decode())
+    return status
+
+
+def _stream(stream=None):
+    if stream is not None:
+        return ctypes.c_void_p(int(stream))
+    import torch
+    return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+def _dev_ptr(t):
+    import torch
+    if not isinstance(t, torch.Tensor) or not t.is_cuda:
+        raise TypeError("expected a device tensor")
+    if not t.is_contiguous():
+        raise ValueError("tensor must be contiguous")
+    return ctypes.c_void_p(t.data_ptr())
+
+
+def default_params(**kw) -> SolveParams:
+    p = SolveParams()
+    load().dwf_solve_params_default(ctypes.byref(p))
+    for k, v in kw.items():
+        if k == "inner_prec" and isinstance(v, str):
+            v = {"f64": F64, "f32": F32, "bf16": BF16}[v]
+        setattr(p, k, v)
+    return p
+
+
+class Lattice:
+    """dwf_lattice: geometry, neighbour tables and device gauge copies."""
+
+    def __init__(self, dims, antiperiodic_t: bool = True):
+        lib = load()
+        self.dims = tuple(int(d) for d in dims)
+        arr = (ctypes.c_int * 4)(*self.dims)
+        h = ctypes.c_void_p()
+        _check(lib.dwf_lattice_create(arr, int(bool(antiperiodic_t)), ctypes.byref(h)), "dwf_lattice_create")
+        self._h = h
+        self.V = self.dims[0] * self.dims[1] * self.dims[2] * self.dims[3]
+        self.Vh = self.V // 2
+
+    def set_gauge(self, U, stream=None):
+        """U: complex128 tensor (device) or numpy array (host), canonical [V][4][3][3]."""
+        lib = load()
+        import numpy as np
+        if isinstance(U, np.ndarray):
+            U = np.ascontiguousarray(U, dtype=np.complex128)
+            _check(lib.dwf_lattice_set_gauge(self._h, U.ctypes.data_as(ctypes.c_void_p), 0, None),
+                   "dwf_lattice_set_gauge")
+        else:
+            _check(lib.dwf_lattice_set_gauge(self._h, _dev_ptr(U), 1, _stream(stream)), "dwf_lattice_set_gauge")
+
+    def maps(self):
+        import numpy as np
+        lex = np.zeros((2, self.Vh), np.int32)
+        nbr = np.zeros((2, 8, self.Vh), np.int32)
+        _check(load().dwf_lattice_maps(self._h, lex.ctypes.data_as(ctypes.c_void_p),
+                                       nbr.ctypes.data_as(ctypes.c_void_p)), "dwf_lattice_maps")
+        return lex, nbr
+
+    def __del__(self):
+        if getattr(self, "_h", None) and _lib is not None:
+            _lib.dwf_lattice_destroy(self._h)
+            self._h = None
+
+
+@dataclass
+class OpParams:
+    Ls: int
+    M0: float
+    m: float
+    b: float = 1.0
+    c: float = 0.0
+    alpha: float = 1.0
+
+
+class Op:
+    """dwf_op: D^(alpha) on a lattice (the lattice must outlive the op)."""
+
+    def __init__(self, lattice: Lattice, Ls, M0, m, b=1.0, c=0.0, alpha=1.0):
+        lib = load()
+        self.lattice = lattice
+        self.params = OpParams(Ls, M0, m, b, c, alpha)
+        h = ctypes.c_void_p()
+        _check(lib.dwf_op_create(lattice._h, int(Ls), float(M0), float(m), float(b), float(c), float(alpha),
+                                 ctypes.byref(h)), "dwf_op_create")
+        self._h = h
+        self.Ls = int(Ls)
+
+    def apply(self, out, inp, space=FULL5D, dagger=False, prec=F64, stream=None):
+        _check(load().dwf_apply(self._h, int(space), int(bool(dagger)), int(prec), _dev_ptr(out), _dev_ptr(inp),
+                                _stream(stream)), "dwf_apply")
+        return out
+
+    def apply_normal(self, out, inp, prec=F64, stream=None):
+        _check(load().dwf_apply_normal(self._h, int(prec), _dev_ptr(out), _dev_ptr(inp), _stream(stream)),
+               "dwf_apply_normal")
+        return out
+
+    def source_4d(self, b5, b4, stream=None):
+        _check(load().dwf_source_4d(self._h, _dev_ptr(b5), _dev_ptr(b4), _stream(stream)), "dwf_source_4d")
+        return b5
+
+    def project_4d(self, x4, x5, stream=None):
+        _check(load().dwf_project_4d(self._h, _dev_ptr(x4), _dev_ptr(x5), _stream(stream)), "dwf_project_4d")
+        return x4
+
+    def solve(self, x5, b5, params: SolveParams | None = None, stream=None) -> tuple[int, SolveInfo]:
+        info = SolveInfo()
+        p = params if params is not None else default_params()
+        st = _check(load().dwf_solve(self._h, _dev_ptr(x5), _dev_ptr(b5), ctypes.byref(p), ctypes.byref(info),
+                                     _stream(stream)), "dwf_solve")
+        return st, info
+
+    def true_residual(self, x5, b5, stream=None) -> float:
+        r = ctypes.c_double()
+        _check(load().dwf_true_residual(self._h, _dev_ptr(x5), _dev_ptr(b5), ctypes.byref(r), _stream(stream)),
+               "dwf_true_residual")
+        return r.value
+
+    def bench_hop(self, prec=F32, nrep=50, stream=None):
+        ms = ctypes.c_double()
+        by = ctypes.c_double()
+        _check(load().dwf_bench_hop(self._h, int(prec), int(nrep), ctypes.byref(ms), ctypes.byref(by),
+                                    _stream(stream)), "dwf_bench_hop")
+        return ms.value, by.value
+
+    def __del__(self):
+        if getattr(self, "_h", None) and _lib is not None:
+            _lib.dwf_op_destroy(self._h)
+            self._h = None

@@ -1,0 +1,291 @@
+// extern "C" entry points of libdwf (declared in include/dwf.h).  Every call
+// catches internal errors and turns them into status codes; the message is
+// kept per thread for dwf_last_error().
+#include <complex>
+#include <cstring>
+#include <exception>
+#include <memory>
+#include <new>
+
+#include "blas.h"
+#include "dwf_internal.h"
+#include "ops.h"
+#include "solver.h"
+
+namespace dwf {
+static thread_local std::string g_last_error;
+void set_error(const std::string& msg) { g_last_error = msg; }
+}  // namespace dwf
+
+using namespace dwf;
+
+template <class F>
+static int guarded(F&& f) {
+    try {
+        return f();
+    } catch (const Error& e) {
+        set_error(e.msg);
+        return e.code;
+    } catch (const std::bad_alloc&) {
+        set_error("host allocation failed");
+        return DWF_ENOMEM;
+    } catch (const std::exception& e) {
+        set_error(e.what());
+        return DWF_EINVAL;
+    }
+}
+
+static hipStream_t S(void* s) { return static_cast<hipStream_t>(s); }
+
+extern "C" {
+
+const char* dwf_status_string(int status) {
+    switch (status) {
+        case DWF_OK: return "ok";
+        case DWF_NOT_CONVERGED: return "not converged";
+        case DWF_EINVAL: return "invalid argument";
+        case DWF_EDIMS: return "unsupported dimensions";
+        case DWF_ENOMEM: return "out of memory";
+        case DWF_EHIP: return "HIP runtime error";
+        case DWF_ESTATE: return "object not ready";
+        case DWF_ENAN: return "NaN or Inf in a reduction";
+        default: return "unknown status";
+    }
+}
+
+const char* dwf_last_error(void) { return g_last_error.c_str(); }
+
+void dwf_solve_params_default(dwf_solve_params* p) {
+    if (!p) return;
+    std::memset(p, 0, sizeof(*p));
+    p->tol = 1e-10;
+    p->maxiter = 100000;
+    p->algo = DWF_ALGO_CGNR;
+    p->inner_prec = DWF_F32;
+    p->inner_tol = 0.0;
+    p->check_every = 1;
+    p->paper_mode = 0;
+    p->ptc_model = nullptr;
+    p->restart = 16;
+}
+
+int dwf_lattice_create(const int dims[4], int antiperiodic_t, dwf_lattice** out) {
+    return guarded([&] {
+        DWF_REQUIRE(dims && out, DWF_EINVAL, "null argument");
+        for (int mu = 0; mu < 4; ++mu)
+            DWF_REQUIRE(dims[mu] >= 2 && dims[mu] % 2 == 0, DWF_EDIMS, "every lattice extent must be even and >= 2");
+        std::unique_ptr<dwf_lattice> L(new dwf_lattice());
+        for (int mu = 0; mu < 4; ++mu) L->dims[mu] = dims[mu];
+        L->antiperiodic_t = antiperiodic_t ? 1 : 0;
+        L->V = (long)dims[0] * dims[1] * dims[2] * dims[3];
+        DWF_REQUIRE(L->V < (1L << 30), DWF_EDIMS, "lattice volume too large for int32 site indices");
+        L->Vh = L->V / 2;
+        build_geometry(L.get());
+        *out = L.release();
+        return DWF_OK;
+    });
+}
+
+void dwf_lattice_destroy(dwf_lattice* lat) { delete lat; }
+
+int dwf_lattice_set_gauge(dwf_lattice* lat, const void* U, int on_device, void* stream) {
+    return guarded([&] {
+        DWF_REQUIRE(lat && U, DWF_EINVAL, "null argument");
+        const size_t n = (size_t)lat->V * 4 * 9;
+        std::vector<std::complex<double>> h(n);
+        if (on_device) {
+            DWF_HIP(hipMemcpyAsync(h.data(), U, n * 16, hipMemcpyDeviceToHost, S(stream)));
+            DWF_HIP(hipStreamSynchronize(S(stream)));
+        } else {
+            std::memcpy(h.data(), U, n * 16);
+        }
+        upload_gauge(lat, h.data());
+        return DWF_OK;
+    });
+}
+
+int dwf_lattice_maps(const dwf_lattice* lat, int* lex_of_eo, int* nbr) {
+    return guarded([&] {
+        DWF_REQUIRE(lat, DWF_EINVAL, "null lattice");
+        if (lex_of_eo) std::memcpy(lex_of_eo, lat->lex_of_eo.data(), sizeof(int) * lat->lex_of_eo.size());
+        if (nbr) {
+            // read back the device table so that what the kernels use is what is returned
+            DWF_HIP(hipMemcpy(nbr, lat->nbr.p, lat->nbr.bytes, hipMemcpyDeviceToHost));
+        }
+        return DWF_OK;
+    });
+}
+
+int dwf_op_create(dwf_lattice* lat, int Ls, double M0, double m, double b, double c, double alpha, dwf_op** out) {
+    return guarded([&] {
+        DWF_REQUIRE(lat && out, DWF_EINVAL, "null argument");
+        DWF_REQUIRE(Ls >= 2 && Ls <= LS_MAX, DWF_EDIMS, "Ls must be in [2, 16]");
+        std::unique_ptr<dwf_op> op(new dwf_op());
+        op->lat = lat;
+        op->Ls = Ls;
+        op->M0 = M0;
+        op->m = m;
+        op->b = b;
+        op->c = c;
+        op->alpha = alpha;
+        setup_op(op.get());
+        *out = op.release();
+        return DWF_OK;
+    });
+}
+
+void dwf_op_destroy(dwf_op* op) { delete op; }
+
+static int kind_of(int prec) {
+    DWF_REQUIRE(prec == DWF_F64 || prec == DWF_F32 || prec == DWF_BF16, DWF_EINVAL, "bad precision");
+    return prec;
+}
+
+int dwf_apply(const dwf_op* op, int space, int dagger, int prec, void* out, const void* in, void* stream) {
+    return guarded([&] {
+        DWF_REQUIRE(op && out && in, DWF_EINVAL, "null argument");
+        DWF_REQUIRE(out != in, DWF_EINVAL, "in and out must not alias");
+        const int k = kind_of(prec);
+        const dwf_lattice* L = op->lat;
+        DWF_REQUIRE(L->has_gauge, DWF_ESTATE, "gauge field not set");
+        const long Vh = L->Vh, V = L->V, n = (long)op->Ls * 12 * Vh;
+        const size_t bytes = complex_bytes_of(k) * n;
+        hipStream_t st = S(stream);
+        const int* lex = L->lex_of_eo_dev.as<int>();
+        if (space == DWF_FULL5D) {
+            DevBuf ie(bytes), io(bytes), oe(bytes), oo(bytes);
+            pack_full(k, ie.p, in, lex, Vh, V, op->Ls, st);
+            pack_full(k, io.p, in, lex + Vh, Vh, V, op->Ls, st);
+            apply_full(op, k, dagger, oe.p, oo.p, ie.p, io.p, 1, st);
+            unpack_full(k, out, oe.p, lex, Vh, V, op->Ls, st);
+            unpack_full(k, out, oo.p, lex + Vh, Vh, V, op->Ls, st);
+            DWF_HIP(hipStreamSynchronize(st));
+        } else if (space == DWF_EVEN5D) {
+            DevBuf ie(bytes), oe(bytes), to(bytes), te(bytes);
+            pack_half(k, ie.p, in, Vh, op->Ls, st);
+            apply_dhat(op, k, dagger, oe.p, ie.p, to.p, te.p, 1, st);
+            unpack_half(k, out, oe.p, Vh, op->Ls, st);
+            DWF_HIP(hipStreamSynchronize(st));
+        } else {
+            throw Error{DWF_EINVAL, "bad space"};
+        }
+        return DWF_OK;
+    });
+}
+
+int dwf_apply_normal(const dwf_op* op, int prec, void* out, const void* in, void* stream) {
+    return guarded([&] {
+        DWF_REQUIRE(op && out && in, DWF_EINVAL, "null argument");
+        DWF_REQUIRE(out != in, DWF_EINVAL, "in and out must not alias");
+        const int k = kind_of(prec);
+        DWF_REQUIRE(op->lat->has_gauge, DWF_ESTATE, "gauge field not set");
+        const long Vh = op->lat->Vh, n = (long)op->Ls * 12 * Vh;
+        const size_t bytes = complex_bytes_of(k) * n;
+        hipStream_t st = S(stream);
+        DevBuf ie(bytes), oe(bytes), to(bytes), tv(bytes);
+        pack_half(k, ie.p, in, Vh, op->Ls, st);
+        apply_normal(op, k, oe.p, ie.p, to.p, tv.p, nullptr, 1, st);
+        unpack_half(k, out, oe.p, Vh, op->Ls, st);
+        DWF_HIP(hipStreamSynchronize(st));
+        return DWF_OK;
+    });
+}
+
+int dwf_source_4d(const dwf_op* op, void* b5, const void* b4, void* stream) {
+    return guarded([&] {
+        DWF_REQUIRE(op && b5 && b4, DWF_EINVAL, "null argument");
+        const dwf_lattice* L = op->lat;
+        DWF_REQUIRE(L->has_gauge, DWF_ESTATE, "gauge field not set");
+        const long Vh = L->Vh, V = L->V;
+        const int Ls = op->Ls;
+        hipStream_t st = S(stream);
+        const int* lex = L->lex_of_eo_dev.as<int>();
+        const size_t pair_bytes = 16 * (size_t)2 * 12 * Vh;
+        DevBuf pe(pair_bytes), po(pair_bytes), oe(pair_bytes), oo(pair_bytes);
+        pack_chiral_pair_f64(pe.p, b4, lex, Vh, st);
+        pack_chiral_pair_f64(po.p, b4, lex + Vh, Vh, st);
+        source_pair(op, oe.p, po.p, pe.p, 0, st);
+        source_pair(op, oo.p, pe.p, po.p, 1, st);
+        // b5 = 0 except s = 0 (slice 0 of the pair) and s = Ls-1 (slice 1)
+        DWF_HIP(hipMemsetAsync(b5, 0, (size_t)16 * Ls * V * 12, st));
+        const size_t slice = (size_t)16 * 12 * Vh;
+        DevBuf fe((size_t)16 * Ls * 12 * Vh), fo((size_t)16 * Ls * 12 * Vh);
+        DWF_HIP(hipMemsetAsync(fe.p, 0, fe.bytes, st));
+        DWF_HIP(hipMemsetAsync(fo.p, 0, fo.bytes, st));
+        DWF_HIP(hipMemcpyAsync(fe.p, oe.p, slice, hipMemcpyDeviceToDevice, st));
+        DWF_HIP(hipMemcpyAsync(fo.p, oo.p, slice, hipMemcpyDeviceToDevice, st));
+        DWF_HIP(hipMemcpyAsync(fe.as<char>() + slice * (Ls - 1), oe.as<char>() + slice, slice,
+                               hipMemcpyDeviceToDevice, st));
+        DWF_HIP(hipMemcpyAsync(fo.as<char>() + slice * (Ls - 1), oo.as<char>() + slice, slice,
+                               hipMemcpyDeviceToDevice, st));
+        unpack_full(ST_F64, b5, fe.p, lex, Vh, V, Ls, st);
+        unpack_full(ST_F64, b5, fo.p, lex + Vh, Vh, V, Ls, st);
+        DWF_HIP(hipStreamSynchronize(st));
+        return DWF_OK;
+    });
+}
+
+int dwf_project_4d(const dwf_op* op, void* x4, const void* x5, void* stream) {
+    return guarded([&] {
+        DWF_REQUIRE(op && x4 && x5, DWF_EINVAL, "null argument");
+        project_4d(x4, x5, op->lat->V, op->Ls, S(stream));
+        DWF_HIP(hipStreamSynchronize(S(stream)));
+        return DWF_OK;
+    });
+}
+
+int dwf_solve(const dwf_op* op, void* x5, const void* b5, const dwf_solve_params* prm, dwf_solve_info* info,
+              void* stream) {
+    return guarded([&] {
+        DWF_REQUIRE(op && x5 && b5, DWF_EINVAL, "null argument");
+        dwf_solve_params def;
+        dwf_solve_params_default(&def);
+        const dwf_solve_params* p = prm ? prm : &def;
+        DWF_REQUIRE(p->algo == DWF_ALGO_CGNR || p->algo == DWF_ALGO_DC, DWF_EINVAL, "unsupported algorithm");
+        return solve(op, x5, b5, p, info, S(stream));
+    });
+}
+
+int dwf_true_residual(const dwf_op* op, const void* x5, const void* b5, double* rel, void* stream) {
+    return guarded([&] {
+        DWF_REQUIRE(op && x5 && b5 && rel, DWF_EINVAL, "null argument");
+        *rel = true_residual(op, x5, b5, S(stream));
+        return DWF_OK;
+    });
+}
+
+int dwf_bench_hop(const dwf_op* op, int prec, int nrep, double* ms_per_launch, double* bytes_per_launch,
+                  void* stream) {
+    return guarded([&] {
+        DWF_REQUIRE(op && nrep > 0, DWF_EINVAL, "bad argument");
+        const int k = kind_of(prec);
+        const dwf_lattice* L = op->lat;
+        DWF_REQUIRE(L->has_gauge, DWF_ESTATE, "gauge field not set");
+        const long Vh = L->Vh, n = (long)op->Ls * 12 * Vh;
+        const size_t cb = complex_bytes_of(k);
+        hipStream_t st = S(stream);
+        DevBuf in(cb * n), out(cb * n);
+        DWF_HIP(hipMemsetAsync(in.p, 0, in.bytes, st));
+        // warm up
+        hop(op, k, 1, in.p, nullptr, out.p, PRE_K, MAT_Q, -1, 0.0, nullptr, 0, 0, nullptr, 0, 1, st);
+        hipEvent_t e0, e1;
+        DWF_HIP(hipEventCreate(&e0));
+        DWF_HIP(hipEventCreate(&e1));
+        DWF_HIP(hipEventRecord(e0, st));
+        for (int i = 0; i < nrep; ++i)
+            hop(op, k, 1, in.p, nullptr, out.p, PRE_K, MAT_Q, -1, 0.0, nullptr, 0, 0, nullptr, 0, 1, st);
+        DWF_HIP(hipEventRecord(e1, st));
+        DWF_HIP(hipEventSynchronize(e1));
+        float ms = 0;
+        DWF_HIP(hipEventElapsedTime(&ms, e0, e1));
+        DWF_HIP(hipEventDestroy(e0));
+        DWF_HIP(hipEventDestroy(e1));
+        if (ms_per_launch) *ms_per_launch = ms / nrep;
+        // read every input spinor once, write every output once, read every link once
+        const double w = (double)cb / 2.0;   // bytes per real
+        if (bytes_per_launch) *bytes_per_launch = w * (double)Vh * (48.0 * op->Ls + 144.0);
+        return DWF_OK;
+    });
+}
+
+}  // extern "C"

@@ -1,0 +1,32 @@
+// Launch interface of the vector kernels (blas.hip).  All `kind` arguments
+// are StoreKind values; n counts complex elements.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+namespace dwf {
+
+// Slots of the device-resident CG scalar block (doubles).
+enum { CG_RR = 0, CG_QQ = 1, CG_ALPHA = 2, CG_BETA = 3, CG_RRNEW = 4, CG_NANFLAG = 5, CG_RR0 = 6,
+       CG_TMP = 7, CG_NSLOTS = 16 };
+
+int blas_grid(long n);
+void pack_full(int kind, void* dst, const void* src, const int* lex, long Vh, long V, long nslices, hipStream_t st);
+void unpack_full(int kind, void* dst, const void* src, const int* lex, long Vh, long V, long nslices, hipStream_t st);
+void pack_half(int kind, void* dst, const void* src, long Vh, long nslices, hipStream_t st);
+void unpack_half(int kind, void* dst, const void* src, long Vh, long nslices, hipStream_t st);
+void pack_chiral_pair_f64(void* dst, const void* b4, const int* lex, long Vh, hipStream_t st);
+void project_4d(void* x4, const void* x5, long V, int Ls, hipStream_t st);
+void convert(int kd, int ks, void* dst, const void* src, long n, hipStream_t st);
+void norm2_partial(int kind, const void* x, long n, double* partial, hipStream_t st);
+void dot_partial(int kind, const void* x, const void* y, long n, double* partial, hipStream_t st);
+// y = a x + b y; a = *sa if sa else ha (same for b); optional partial |y|^2
+void axpby(int ky, int kx, void* y, const void* x, long n, const double* sa, double ha, const double* sb,
+           double hb, double* partial, hipStream_t st);
+void cg_update_xr(int kx, int kp, void* x, void* r, const void* p, const void* w, long n, const double* alpha,
+                  double* partial, hipStream_t st);
+void cg_update_p(int kr, int kp, void* p, const void* r, long n, const double* beta, hipStream_t st);
+// mode 0: out[0] = sum; 1: alpha step; 2: beta step (see CG slots)
+void finalize(const double* partial, int nparts, int stride, double* out, int mode, hipStream_t st);
+
+}  // namespace dwf

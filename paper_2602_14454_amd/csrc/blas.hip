@@ -1,0 +1,430 @@
+// Vector kernels on internal half fields: layout conversion, precision
+// conversion, CG updates and deterministic FP64 reductions.
+//
+// Reductions: every kernel that reduces writes one FP64 partial per block
+// (wavefront __shfl_xor tree, then the block's waves in order); a single
+// block then sums the partials in a fixed order.  No floating-point atomics,
+// so results are bit-reproducible run to run.
+#include "blas.h"
+#include "dwf_internal.h"
+#include "precision.h"
+
+namespace dwf {
+
+constexpr int BLAS_THREADS = 256;
+
+__device__ __forceinline__ double block_sum(double v, double* red) {
+#pragma unroll
+    for (int off = 32; off >= 1; off >>= 1) v += __shfl_xor(v, off, 64);
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    if (lane == 0) red[w] = v;
+    __syncthreads();
+    double t = 0.0;
+    if (threadIdx.x == 0)
+        for (int i = 0; i < (int)(blockDim.x >> 6); ++i) t += red[i];
+    __syncthreads();
+    return t;
+}
+
+// ---------------------------------------------------------------------
+// canonical complex128 <-> internal layout
+// ---------------------------------------------------------------------
+// Full 5D canonical: src[((r*Ls + s)*V + lex)*12 + comp]
+template <class S>
+__global__ void pack_full_kernel(void* dst, const double2* src, const int* lex_of_eo, long Vh,
+                                 long V, long nslices) {
+    const long idx = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (idx >= nslices * Vh) return;
+    const long rs = idx / Vh, eo = idx % Vh;
+    const long lex = lex_of_eo[eo];
+    const double2* in = src + (rs * V + lex) * 12;
+#pragma unroll
+    for (int cp = 0; cp < 12; ++cp) {
+        double2 v = in[cp];
+        cstore<S>(dst, (rs * 12 + cp) * Vh + eo, (typename Traits<S>::R)v.x, (typename Traits<S>::R)v.y);
+    }
+}
+
+template <class S>
+__global__ void unpack_full_kernel(double2* dst, const void* src, const int* lex_of_eo, long Vh,
+                                   long V, long nslices) {
+    const long idx = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (idx >= nslices * Vh) return;
+    const long rs = idx / Vh, eo = idx % Vh;
+    const long lex = lex_of_eo[eo];
+    double2* out = dst + (rs * V + lex) * 12;
+#pragma unroll
+    for (int cp = 0; cp < 12; ++cp) {
+        typename Traits<S>::R re, im;
+        cload<S>(src, (rs * 12 + cp) * Vh + eo, re, im);
+        out[cp] = make_double2((double)re, (double)im);
+    }
+}
+
+// Even canonical: src[((r*Ls + s)*Vh + eo)*12 + comp]
+template <class S>
+__global__ void pack_half_kernel(void* dst, const double2* src, long Vh, long nslices) {
+    const long idx = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (idx >= nslices * Vh) return;
+    const long rs = idx / Vh, eo = idx % Vh;
+#pragma unroll
+    for (int cp = 0; cp < 12; ++cp) {
+        double2 v = src[(rs * Vh + eo) * 12 + cp];
+        cstore<S>(dst, (rs * 12 + cp) * Vh + eo, (typename Traits<S>::R)v.x, (typename Traits<S>::R)v.y);
+    }
+}
+
+template <class S>
+__global__ void unpack_half_kernel(double2* dst, const void* src, long Vh, long nslices) {
+    const long idx = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (idx >= nslices * Vh) return;
+    const long rs = idx / Vh, eo = idx % Vh;
+#pragma unroll
+    for (int cp = 0; cp < 12; ++cp) {
+        typename Traits<S>::R re, im;
+        cload<S>(src, (rs * 12 + cp) * Vh + eo, re, im);
+        dst[(rs * Vh + eo) * 12 + cp] = make_double2((double)re, (double)im);
+    }
+}
+
+// 4D canonical -> two-slice half field of one parity: slice 0 = P+ b4, slice 1 = P- b4
+template <class S>
+__global__ void pack_chiral_pair_kernel(void* dst, const double2* b4, const int* lex_of_eo, long Vh) {
+    const long eo = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (eo >= Vh) return;
+    const long lex = lex_of_eo[eo];
+#pragma unroll
+    for (int cp = 0; cp < 12; ++cp) {
+        double2 v = b4[lex * 12 + cp];
+        const bool up = cp < 6;
+        cstore<S>(dst, ((long)0 * 12 + cp) * Vh + eo, up ? v.x : 0.0, up ? v.y : 0.0);
+        cstore<S>(dst, ((long)1 * 12 + cp) * Vh + eo, up ? 0.0 : v.x, up ? 0.0 : v.y);
+    }
+}
+
+// x4[lex] = P_- x5(s=0)[lex] + P_+ x5(s=Ls-1)[lex], canonical complex128
+__global__ void project4d_kernel(double2* x4, const double2* x5, long V, int Ls) {
+    const long lex = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (lex >= V) return;
+#pragma unroll
+    for (int cp = 0; cp < 12; ++cp) {
+        const bool up = cp < 6;   // P_+ components come from s = Ls-1, P_- from s = 0
+        x4[lex * 12 + cp] = up ? x5[((long)(Ls - 1) * V + lex) * 12 + cp] : x5[lex * 12 + cp];
+    }
+}
+
+// ---------------------------------------------------------------------
+// elementwise / CG kernels on flat complex arrays of n elements
+// ---------------------------------------------------------------------
+template <class SD, class SS>
+__global__ void convert_kernel(void* dst, const void* src, long n) {
+    for (long i = (long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (long)gridDim.x * blockDim.x) {
+        typename Traits<SS>::R re, im;
+        cload<SS>(src, i, re, im);
+        cstore<SD>(dst, i, (typename Traits<SD>::R)re, (typename Traits<SD>::R)im);
+    }
+}
+
+template <class S>
+__global__ void norm2_kernel(const void* x, long n, double* partial) {
+    __shared__ double red[BLAS_THREADS / 64];
+    double acc = 0.0;
+    for (long i = (long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (long)gridDim.x * blockDim.x) {
+        typename Traits<S>::R re, im;
+        cload<S>(x, i, re, im);
+        acc += double(re) * double(re) + double(im) * double(im);
+    }
+    double t = block_sum(acc, red);
+    if (threadIdx.x == 0) partial[blockIdx.x] = t;
+}
+
+// <x, y> = sum conj(x) y, partial[2*block] = re, partial[2*block+1] = im
+template <class S>
+__global__ void dot_kernel(const void* x, const void* y, long n, double* partial) {
+    __shared__ double red[BLAS_THREADS / 64];
+    double ar = 0.0, ai = 0.0;
+    for (long i = (long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (long)gridDim.x * blockDim.x) {
+        typename Traits<S>::R xr, xi, yr, yi;
+        cload<S>(x, i, xr, xi);
+        cload<S>(y, i, yr, yi);
+        ar += double(xr) * double(yr) + double(xi) * double(yi);
+        ai += double(xr) * double(yi) - double(xi) * double(yr);
+    }
+    double tr = block_sum(ar, red);
+    double ti = block_sum(ai, red);
+    if (threadIdx.x == 0) { partial[2 * blockIdx.x] = tr; partial[2 * blockIdx.x + 1] = ti; }
+}
+
+// y = a*x + b*y with real scalars a = sa[0] (or ha if sa null), b likewise
+template <class SY, class SX>
+__global__ void axpby_kernel(void* y, const void* x, long n, const double* sa, double ha,
+                             const double* sb, double hb, double* partial) {
+    __shared__ double red[BLAS_THREADS / 64];
+    const double a = sa ? *sa : ha;
+    const double b = sb ? *sb : hb;
+    using RY = typename Traits<SY>::R;
+    double acc = 0.0;
+    for (long i = (long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (long)gridDim.x * blockDim.x) {
+        typename Traits<SX>::R xr, xi;
+        RY yr, yi;
+        cload<SX>(x, i, xr, xi);
+        cload<SY>(y, i, yr, yi);
+        RY nr = RY(a) * RY(xr) + RY(b) * yr;
+        RY ni = RY(a) * RY(xi) + RY(b) * yi;
+        cstore<SY>(y, i, nr, ni);
+        acc += double(nr) * double(nr) + double(ni) * double(ni);
+    }
+    if (partial) {
+        double t = block_sum(acc, red);
+        if (threadIdx.x == 0) partial[blockIdx.x] = t;
+    }
+}
+
+// CG update: x += alpha p; r -= alpha w; partial |r|^2.  x, r of type SX; p, w of type SP.
+template <class SX, class SP>
+__global__ void cg_xr_kernel(void* x, void* r, const void* p, const void* w, long n,
+                             const double* alpha, double* partial) {
+    __shared__ double red[BLAS_THREADS / 64];
+    using RX = typename Traits<SX>::R;
+    const RX a = RX(*alpha);
+    double acc = 0.0;
+    for (long i = (long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (long)gridDim.x * blockDim.x) {
+        typename Traits<SP>::R pr, pi, wr, wi;
+        RX xr, xi, rr, ri;
+        cload<SP>(p, i, pr, pi);
+        cload<SP>(w, i, wr, wi);
+        cload<SX>(x, i, xr, xi);
+        cload<SX>(r, i, rr, ri);
+        xr += a * RX(pr); xi += a * RX(pi);
+        rr -= a * RX(wr); ri -= a * RX(wi);
+        cstore<SX>(x, i, xr, xi);
+        cstore<SX>(r, i, rr, ri);
+        acc += double(rr) * double(rr) + double(ri) * double(ri);
+    }
+    double t = block_sum(acc, red);
+    if (threadIdx.x == 0) partial[blockIdx.x] = t;
+}
+
+// p = r + beta p
+template <class SR, class SP>
+__global__ void cg_p_kernel(void* p, const void* r, long n, const double* beta) {
+    using RP = typename Traits<SP>::R;
+    const RP b = RP(*beta);
+    for (long i = (long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (long)gridDim.x * blockDim.x) {
+        typename Traits<SR>::R rr, ri;
+        RP pr, pi;
+        cload<SR>(r, i, rr, ri);
+        cload<SP>(p, i, pr, pi);
+        cstore<SP>(p, i, RP(rr) + b * pr, RP(ri) + b * pi);
+    }
+}
+
+// Sum nparts partials in a fixed order; store according to mode:
+//  mode 0: out[0] = sum
+//  mode 1 (alpha): s[QQ] = sum; s[ALPHA] = s[RR] / sum (0 if sum <= 0)
+//  mode 2 (beta):  s[RRNEW] = sum; s[BETA] = sum / s[RR]; s[RR] = sum
+// A non-finite sum sets s[NANFLAG] = 1.
+__global__ void finalize_kernel(const double* partial, int nparts, int stride, double* out, int mode) {
+    __shared__ double red[BLAS_THREADS];
+    double acc = 0.0;
+    for (int i = threadIdx.x; i < nparts; i += blockDim.x) acc += partial[(long)i * stride];
+    red[threadIdx.x] = acc;
+    __syncthreads();
+    for (int h = blockDim.x / 2; h >= 1; h >>= 1) {
+        if ((int)threadIdx.x < h) red[threadIdx.x] += red[threadIdx.x + h];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        const double sum = red[0];
+        if (!isfinite(sum)) out[CG_NANFLAG] = 1.0;
+        if (mode == 0) {
+            out[0] = sum;
+        } else if (mode == 1) {
+            out[CG_QQ] = sum;
+            out[CG_ALPHA] = (sum > 0.0 && isfinite(sum)) ? out[CG_RR] / sum : 0.0;
+        } else if (mode == 2) {
+            out[CG_RRNEW] = sum;
+            out[CG_BETA] = out[CG_RR] > 0.0 ? sum / out[CG_RR] : 0.0;
+            out[CG_RR] = sum;
+        }
+    }
+}
+
+// ---------------------------------------------------------------------
+// host launchers
+// ---------------------------------------------------------------------
+static int blocks_for(long work, int threads) {
+    long b = (work + threads - 1) / threads;
+    return (int)(b < 1 ? 1 : b);
+}
+
+int blas_grid(long n) {
+    long b = (n + BLAS_THREADS - 1) / BLAS_THREADS;
+    if (b > 2048) b = 2048;
+    return (int)(b < 1 ? 1 : b);
+}
+
+#define DISPATCH1(kind, F, ...)                                              \
+    switch (kind) {                                                          \
+        case ST_F64: F<double>(__VA_ARGS__); break;                          \
+        case ST_F32: F<float>(__VA_ARGS__); break;                           \
+        case ST_BF16: F<bf16s>(__VA_ARGS__); break;                          \
+        default: throw Error{DWF_EINVAL, "bad storage kind"};                \
+    }
+
+template <class S>
+static void pack_full_t(void* dst, const void* src, const int* lex, long Vh, long V, long ns, hipStream_t st) {
+    hipLaunchKernelGGL(pack_full_kernel<S>, dim3(blocks_for(ns * Vh, 256)), dim3(256), 0, st, dst,
+                       (const double2*)src, lex, Vh, V, ns);
+}
+void pack_full(int kind, void* dst, const void* src, const int* lex, long Vh, long V, long ns, hipStream_t st) {
+    DISPATCH1(kind, pack_full_t, dst, src, lex, Vh, V, ns, st);
+    DWF_HIP(hipGetLastError());
+}
+
+template <class S>
+static void unpack_full_t(void* dst, const void* src, const int* lex, long Vh, long V, long ns, hipStream_t st) {
+    hipLaunchKernelGGL(unpack_full_kernel<S>, dim3(blocks_for(ns * Vh, 256)), dim3(256), 0, st,
+                       (double2*)dst, src, lex, Vh, V, ns);
+}
+void unpack_full(int kind, void* dst, const void* src, const int* lex, long Vh, long V, long ns, hipStream_t st) {
+    DISPATCH1(kind, unpack_full_t, dst, src, lex, Vh, V, ns, st);
+    DWF_HIP(hipGetLastError());
+}
+
+template <class S>
+static void pack_half_t(void* dst, const void* src, long Vh, long ns, hipStream_t st) {
+    hipLaunchKernelGGL(pack_half_kernel<S>, dim3(blocks_for(ns * Vh, 256)), dim3(256), 0, st, dst,
+                       (const double2*)src, Vh, ns);
+}
+void pack_half(int kind, void* dst, const void* src, long Vh, long ns, hipStream_t st) {
+    DISPATCH1(kind, pack_half_t, dst, src, Vh, ns, st);
+    DWF_HIP(hipGetLastError());
+}
+
+template <class S>
+static void unpack_half_t(void* dst, const void* src, long Vh, long ns, hipStream_t st) {
+    hipLaunchKernelGGL(unpack_half_kernel<S>, dim3(blocks_for(ns * Vh, 256)), dim3(256), 0, st,
+                       (double2*)dst, src, Vh, ns);
+}
+void unpack_half(int kind, void* dst, const void* src, long Vh, long ns, hipStream_t st) {
+    DISPATCH1(kind, unpack_half_t, dst, src, Vh, ns, st);
+    DWF_HIP(hipGetLastError());
+}
+
+void pack_chiral_pair_f64(void* dst, const void* b4, const int* lex, long Vh, hipStream_t st) {
+    hipLaunchKernelGGL(pack_chiral_pair_kernel<double>, dim3(blocks_for(Vh, 256)), dim3(256), 0, st, dst,
+                       (const double2*)b4, lex, Vh);
+    DWF_HIP(hipGetLastError());
+}
+
+void project_4d(void* x4, const void* x5, long V, int Ls, hipStream_t st) {
+    hipLaunchKernelGGL(project4d_kernel, dim3(blocks_for(V, 256)), dim3(256), 0, st, (double2*)x4,
+                       (const double2*)x5, V, Ls);
+    DWF_HIP(hipGetLastError());
+}
+
+template <class SD, class SS>
+static void convert_t2(void* dst, const void* src, long n, hipStream_t st) {
+    hipLaunchKernelGGL((convert_kernel<SD, SS>), dim3(blas_grid(n)), dim3(BLAS_THREADS), 0, st, dst, src, n);
+}
+template <class SD>
+static void convert_t1(int ks, void* dst, const void* src, long n, hipStream_t st) {
+    switch (ks) {
+        case ST_F64: convert_t2<SD, double>(dst, src, n, st); break;
+        case ST_F32: convert_t2<SD, float>(dst, src, n, st); break;
+        case ST_BF16: convert_t2<SD, bf16s>(dst, src, n, st); break;
+        default: throw Error{DWF_EINVAL, "bad storage kind"};
+    }
+}
+void convert(int kd, int ks, void* dst, const void* src, long n, hipStream_t st) {
+    DISPATCH1(kd, convert_t1, ks, dst, src, n, st);
+    DWF_HIP(hipGetLastError());
+}
+
+template <class S>
+static void norm2_t(const void* x, long n, double* partial, hipStream_t st) {
+    hipLaunchKernelGGL(norm2_kernel<S>, dim3(blas_grid(n)), dim3(BLAS_THREADS), 0, st, x, n, partial);
+}
+void norm2_partial(int kind, const void* x, long n, double* partial, hipStream_t st) {
+    DISPATCH1(kind, norm2_t, x, n, partial, st);
+    DWF_HIP(hipGetLastError());
+}
+
+template <class S>
+static void dot_t(const void* x, const void* y, long n, double* partial, hipStream_t st) {
+    hipLaunchKernelGGL(dot_kernel<S>, dim3(blas_grid(n)), dim3(BLAS_THREADS), 0, st, x, y, n, partial);
+}
+void dot_partial(int kind, const void* x, const void* y, long n, double* partial, hipStream_t st) {
+    DISPATCH1(kind, dot_t, x, y, n, partial, st);
+    DWF_HIP(hipGetLastError());
+}
+
+template <class SY, class SX>
+static void axpby_t2(void* y, const void* x, long n, const double* sa, double ha, const double* sb,
+                     double hb, double* partial, hipStream_t st) {
+    hipLaunchKernelGGL((axpby_kernel<SY, SX>), dim3(blas_grid(n)), dim3(BLAS_THREADS), 0, st, y, x, n, sa, ha,
+                       sb, hb, partial);
+}
+template <class SY>
+static void axpby_t1(int kx, void* y, const void* x, long n, const double* sa, double ha, const double* sb,
+                     double hb, double* partial, hipStream_t st) {
+    switch (kx) {
+        case ST_F64: axpby_t2<SY, double>(y, x, n, sa, ha, sb, hb, partial, st); break;
+        case ST_F32: axpby_t2<SY, float>(y, x, n, sa, ha, sb, hb, partial, st); break;
+        case ST_BF16: axpby_t2<SY, bf16s>(y, x, n, sa, ha, sb, hb, partial, st); break;
+        default: throw Error{DWF_EINVAL, "bad storage kind"};
+    }
+}
+void axpby(int ky, int kx, void* y, const void* x, long n, const double* sa, double ha, const double* sb,
+           double hb, double* partial, hipStream_t st) {
+    DISPATCH1(ky, axpby_t1, kx, y, x, n, sa, ha, sb, hb, partial, st);
+    DWF_HIP(hipGetLastError());
+}
+
+template <class SX, class SP>
+static void cg_xr_t2(void* x, void* r, const void* p, const void* w, long n, const double* alpha,
+                     double* partial, hipStream_t st) {
+    hipLaunchKernelGGL((cg_xr_kernel<SX, SP>), dim3(blas_grid(n)), dim3(BLAS_THREADS), 0, st, x, r, p, w, n,
+                       alpha, partial);
+}
+template <class SX>
+static void cg_xr_t1(int kp, void* x, void* r, const void* p, const void* w, long n, const double* alpha,
+                     double* partial, hipStream_t st) {
+    switch (kp) {
+        case ST_F64: cg_xr_t2<SX, double>(x, r, p, w, n, alpha, partial, st); break;
+        case ST_F32: cg_xr_t2<SX, float>(x, r, p, w, n, alpha, partial, st); break;
+        case ST_BF16: cg_xr_t2<SX, bf16s>(x, r, p, w, n, alpha, partial, st); break;
+        default: throw Error{DWF_EINVAL, "bad storage kind"};
+    }
+}
+void cg_update_xr(int kx, int kp, void* x, void* r, const void* p, const void* w, long n,
+                  const double* alpha, double* partial, hipStream_t st) {
+    DISPATCH1(kx, cg_xr_t1, kp, x, r, p, w, n, alpha, partial, st);
+    DWF_HIP(hipGetLastError());
+}
+
+template <class SR, class SP>
+static void cg_p_t2(void* p, const void* r, long n, const double* beta, hipStream_t st) {
+    hipLaunchKernelGGL((cg_p_kernel<SR, SP>), dim3(blas_grid(n)), dim3(BLAS_THREADS), 0, st, p, r, n, beta);
+}
+template <class SR>
+static void cg_p_t1(int kp, void* p, const void* r, long n, const double* beta, hipStream_t st) {
+    switch (kp) {
+        case ST_F64: cg_p_t2<SR, double>(p, r, n, beta, st); break;
+        case ST_F32: cg_p_t2<SR, float>(p, r, n, beta, st); break;
+        case ST_BF16: cg_p_t2<SR, bf16s>(p, r, n, beta, st); break;
+        default: throw Error{DWF_EINVAL, "bad storage kind"};
+    }
+}
+void cg_update_p(int kr, int kp, void* p, const void* r, long n, const double* beta, hipStream_t st) {
+    DISPATCH1(kr, cg_p_t1, kp, p, r, n, beta, st);
+    DWF_HIP(hipGetLastError());
+}
+
+void finalize(const double* partial, int nparts, int stride, double* out, int mode, hipStream_t st) {
+    hipLaunchKernelGGL(finalize_kernel, dim3(1), dim3(BLAS_THREADS), 0, st, partial, nparts, stride, out, mode);
+    DWF_HIP(hipGetLastError());
+}
+
+}  // namespace dwf

@@ -1,0 +1,43 @@
+// Launch interface of the fused hop and local-mix kernels (hop.hip).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+namespace dwf {
+
+// All matrices are compute-type (double for F64 storage, float otherwise),
+// padded to [2 chirality][16][16]; `pre` is [d chi0 | d chi1 | e chi0 | e chi1] x 16.
+struct HopParams {
+    const void* in;        // input half field, parity 1-p
+    const void* loc;       // local half field, parity p (nullptr: none)
+    void* out;             // output half field (nullptr: not stored)
+    void* out2;            // second output (nullptr: none)
+    const void* links;     // hop links of output parity p
+    const int* nbr;        // neighbour table of output parity p
+    const void* pre;       // sparse pre-mix coefficients (nullptr: identity)
+    const void* post;      // dense POST (required)
+    const void* locmix;    // dense LOCMIX (nullptr: loc_scale * identity)
+    const void* post2;     // dense POST2 (required with out2)
+    const void* locmix2;   // dense LOCMIX2 (required with out2 and loc)
+    double* partial;       // per-block FP64 partial norms (nullptr: none)
+    long Vh;
+    int Ls;
+    int pre_mode;          // 0 identity, 1 diagonal d, 2 d + e (K sparsity)
+    int reduce;            // 1: |out|^2, 2: |out2|^2
+    double loc_scale;
+};
+
+struct MixParams {
+    const void* in;
+    void* out;
+    const void* mat;       // dense [2][16][16] compute type
+    double* partial;
+    long Vh;
+    int Ls;
+};
+
+int hop_grid_blocks(long Vh);
+void launch_hop(int kind, const HopParams& P, int nrhs, hipStream_t st);
+void launch_mix(int kind, const MixParams& P, int nrhs, hipStream_t st);
+
+}  // namespace dwf

@@ -1,0 +1,435 @@
+// Fused half-lattice domain-wall hop with fifth-dimension mixing on MFMA.
+//
+// One launch computes, for every site x of the output parity p and every s,
+//
+//   out(x, .) = POST . H(PRE . in)(x, .)  +  LOCMIX . loc(x, .)
+//   out2(x,.) = POST2 . H(PRE . in)(x, .) +  LOCMIX2 . loc(x, .)     (optional)
+//
+// where H is the 4D Wilson hopping term of the paper's Wilson operator
+// (Sec. 2.1, eq. Wilson_matrix without the -1/2 and the mass term):
+//
+//   (H psi)(x) = sum_mu (1 - gamma_mu) U_mu(x) psi(x+mu)
+//              + (1 + gamma_mu) U_mu(x-mu)^dag psi(x-mu),
+//
+// applied on every s slice, and POST, LOCMIX, POST2, LOCMIX2 are real Ls x Ls
+// matrices acting on s per chirality (the 5D-local algebra of the domain-wall
+// operator, Sec. 2.2 and Sec. 2.3).  PRE is either nothing, a diagonal in s,
+// or the cyclic bidiagonal pattern of K = (b + c M5) T.
+//
+// Wave layout (64 lanes): lane = 16 * sc + j, j = site within a group of 16
+// consecutive even-odd sites, sc = 0..3.  A lane computes the hop for
+// s = sc, sc+4, sc+8, sc+12; each link is loaded once per lane and used for
+// those four slices.  The hop results h[kk][.] are then exactly the B operand
+// of v_mfma_*_16x16x4 (B[k][n] with k = s mod 4 block, n = site), so the
+// dense s-mixing C = A * h runs on the matrix cores straight from registers,
+// with no LDS round trip.  After the MFMA a lane holds rows s = 4*sc + i,
+// i = 0..3, of the result for its site (f32); the f64 MFMA leaves rows
+// sc + 4*i instead (see out_row).
+#include "dwf_internal.h"
+#include "hop.h"
+#include "precision.h"
+
+namespace dwf {
+
+typedef float v4f __attribute__((ext_vector_type(4)));
+typedef double v4d __attribute__((ext_vector_type(4)));
+
+template <class R> struct Vec4;
+template <> struct Vec4<float> { using T = v4f; };
+template <> struct Vec4<double> { using T = v4d; };
+
+__device__ __forceinline__ v4f mfma4(float a, float b, v4f c) {
+    return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+}
+__device__ __forceinline__ v4d mfma4(double a, double b, v4d c) {
+    return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+}
+
+// Row of the 16x16 result held in accumulator slot i of a lane with
+// sc = lane / 16 (column = lane % 16 for both).  Measured on gfx950:
+// v_mfma_f32_16x16x4f32 keeps rows 4*sc .. 4*sc+3, v_mfma_f64_16x16x4f64
+// keeps rows sc, sc+4, sc+8, sc+12.  The A and B operand layouts are the
+// same for both: A[m][k] from lane m + 16k, B[k][n] from lane n + 16k.
+template <class R>
+__device__ __forceinline__ int out_row(int sc, int i) {
+    if constexpr (sizeof(R) == 8) return sc + 4 * i;
+    else return 4 * sc + i;
+}
+
+// ---------------------------------------------------------------------
+// One hop direction: h += (1 + SG*gamma_MU) * U * p, spin-projected.
+// Chiral basis gamma_mu = [[0, B],[B^dag, 0]] on (upper spins 0,1 | lower 2,3)
+// with B = -i sigma_1, -i sigma_2, -i sigma_3, 1 for mu = x, y, z, t:
+//   w     = p_up + SG * B p_lo          (half spinor, 2 spins x 3 colours)
+//   h_up += U w,   h_lo += SG * B^dag (U w)
+// p, h: 12 complex as 24 reals, index (spin*3 + colour)*2 + reim.
+// U: 9 complex as 18 reals, index (row*3 + col)*2 + reim.
+// ---------------------------------------------------------------------
+template <int MU, int SG, class R>
+__device__ __forceinline__ void hop_dir(const R* __restrict__ U, const R* __restrict__ p,
+                                        R* __restrict__ h) {
+    R w[12];
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+        const R v0r = p[(6 + c) * 2], v0i = p[(6 + c) * 2 + 1];
+        const R v1r = p[(9 + c) * 2], v1i = p[(9 + c) * 2 + 1];
+        R b0r, b0i, b1r, b1i;
+        if constexpr (MU == 0) {        // B v = (-i v1, -i v0)
+            b0r = v1i; b0i = -v1r; b1r = v0i; b1i = -v0r;
+        } else if constexpr (MU == 1) { // B v = (-v1, v0)
+            b0r = -v1r; b0i = -v1i; b1r = v0r; b1i = v0i;
+        } else if constexpr (MU == 2) { // B v = (-i v0, i v1)
+            b0r = v0i; b0i = -v0r; b1r = -v1i; b1i = v1r;
+        } else {                        // B v = v
+            b0r = v0r; b0i = v0i; b1r = v1r; b1i = v1i;
+        }
+        w[c * 2] = p[c * 2] + R(SG) * b0r;
+        w[c * 2 + 1] = p[c * 2 + 1] + R(SG) * b0i;
+        w[(3 + c) * 2] = p[(3 + c) * 2] + R(SG) * b1r;
+        w[(3 + c) * 2 + 1] = p[(3 + c) * 2 + 1] + R(SG) * b1i;
+    }
+    R u[12];
+#pragma unroll
+    for (int hs = 0; hs < 2; ++hs)
+#pragma unroll
+        for (int a = 0; a < 3; ++a) {
+            R re = 0, im = 0;
+#pragma unroll
+            for (int b = 0; b < 3; ++b) {
+                const R ur = U[(a * 3 + b) * 2], ui = U[(a * 3 + b) * 2 + 1];
+                const R xr = w[(hs * 3 + b) * 2], xi = w[(hs * 3 + b) * 2 + 1];
+                re += ur * xr - ui * xi;
+                im += ur * xi + ui * xr;
+            }
+            u[(hs * 3 + a) * 2] = re;
+            u[(hs * 3 + a) * 2 + 1] = im;
+        }
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+        const R u0r = u[c * 2], u0i = u[c * 2 + 1];
+        const R u1r = u[(3 + c) * 2], u1i = u[(3 + c) * 2 + 1];
+        h[c * 2] += u0r;
+        h[c * 2 + 1] += u0i;
+        h[(3 + c) * 2] += u1r;
+        h[(3 + c) * 2 + 1] += u1i;
+        R l0r, l0i, l1r, l1i;           // B^dag u
+        if constexpr (MU == 0) {        // (i u1, i u0)
+            l0r = -u1i; l0i = u1r; l1r = -u0i; l1i = u0r;
+        } else if constexpr (MU == 1) { // (u1, -u0)
+            l0r = u1r; l0i = u1i; l1r = -u0r; l1i = -u0i;
+        } else if constexpr (MU == 2) { // (i u0, -i u1)
+            l0r = -u0i; l0i = u0r; l1r = u1i; l1i = -u1r;
+        } else {
+            l0r = u0r; l0i = u0i; l1r = u1r; l1i = u1i;
+        }
+        h[(6 + c) * 2] += R(SG) * l0r;
+        h[(6 + c) * 2 + 1] += R(SG) * l0i;
+        h[(9 + c) * 2] += R(SG) * l1r;
+        h[(9 + c) * 2 + 1] += R(SG) * l1i;
+    }
+}
+
+template <class S, int KK, int D>
+__device__ __forceinline__ void hop_direction(const HopParams& P, long sx, long roff, int sc,
+                                              const typename Traits<S>::R (&pd)[KK][2],
+                                              const typename Traits<S>::R (&pe)[KK][2],
+                                              typename Traits<S>::R (&h)[KK][24]) {
+    using R = typename Traits<S>::R;
+    const long Vh = P.Vh;
+    const int Ls = P.Ls;
+    const long y = P.nbr[(long)D * Vh + sx];
+    R U[18];
+#pragma unroll
+    for (int e = 0; e < 9; ++e) cload<S>(P.links, ((long)D * 9 + e) * Vh + sx, U[2 * e], U[2 * e + 1]);
+#pragma unroll
+    for (int kk = 0; kk < KK; ++kk) {
+        const int s = sc + 4 * kk;
+        if (s >= Ls) continue;
+        R p[24];
+#pragma unroll
+        for (int cp = 0; cp < 12; ++cp)
+            cload<S>(P.in, roff + ((long)s * 12 + cp) * Vh + y, p[2 * cp], p[2 * cp + 1]);
+        if (P.pre_mode >= 1) {
+#pragma unroll
+            for (int k = 0; k < 12; ++k) p[k] *= pd[kk][0];
+#pragma unroll
+            for (int k = 12; k < 24; ++k) p[k] *= pd[kk][1];
+        }
+        if (P.pre_mode == 2) {
+            // K pattern: upper chirality couples s-1, lower chirality s+1 (cyclic)
+            const int sm = s == 0 ? Ls - 1 : s - 1;
+            const int sp = s == Ls - 1 ? 0 : s + 1;
+#pragma unroll
+            for (int cp = 0; cp < 6; ++cp) {
+                R re, im;
+                cload<S>(P.in, roff + ((long)sm * 12 + cp) * Vh + y, re, im);
+                p[2 * cp] += pe[kk][0] * re;
+                p[2 * cp + 1] += pe[kk][0] * im;
+            }
+#pragma unroll
+            for (int cp = 6; cp < 12; ++cp) {
+                R re, im;
+                cload<S>(P.in, roff + ((long)sp * 12 + cp) * Vh + y, re, im);
+                p[2 * cp] += pe[kk][1] * re;
+                p[2 * cp + 1] += pe[kk][1] * im;
+            }
+        }
+        constexpr int MU = D & 3;
+        constexpr int SG = D < 4 ? -1 : +1;
+        hop_dir<MU, SG, R>(U, p, h[kk]);
+    }
+}
+
+template <class S, int KK>
+__global__ __launch_bounds__(256) void hop_mfma_kernel(HopParams P) {
+    using R = typename Traits<S>::R;
+    using V = typename Vec4<R>::T;
+    const int lane = threadIdx.x & 63;
+    const int j = lane & 15, sc = lane >> 4;
+    const long Vh = P.Vh;
+    const int Ls = P.Ls;
+    const long site = ((long)blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6)) * 16 + j;
+    const bool valid = site < Vh;
+    const long sx = valid ? site : Vh - 1;
+    const long roff = (long)blockIdx.y * Ls * 12 * Vh;
+
+    // sparse pre-mix coefficients for this lane's slices
+    R pd[KK][2], pe[KK][2];
+    const R* pre = static_cast<const R*>(P.pre);
+#pragma unroll
+    for (int kk = 0; kk < KK; ++kk) {
+        const int s = min(sc + 4 * kk, LS_MAX - 1);
+        pd[kk][0] = pre ? pre[0 * 16 + s] : R(1);
+        pd[kk][1] = pre ? pre[1 * 16 + s] : R(1);
+        pe[kk][0] = pre ? pre[2 * 16 + s] : R(0);
+        pe[kk][1] = pre ? pre[3 * 16 + s] : R(0);
+    }
+
+    R h[KK][24];
+#pragma unroll
+    for (int kk = 0; kk < KK; ++kk)
+#pragma unroll
+        for (int k = 0; k < 24; ++k) h[kk][k] = 0;
+
+    hop_direction<S, KK, 0>(P, sx, roff, sc, pd, pe, h);
+    hop_direction<S, KK, 1>(P, sx, roff, sc, pd, pe, h);
+    hop_direction<S, KK, 2>(P, sx, roff, sc, pd, pe, h);
+    hop_direction<S, KK, 3>(P, sx, roff, sc, pd, pe, h);
+    hop_direction<S, KK, 4>(P, sx, roff, sc, pd, pe, h);
+    hop_direction<S, KK, 5>(P, sx, roff, sc, pd, pe, h);
+    hop_direction<S, KK, 6>(P, sx, roff, sc, pd, pe, h);
+    hop_direction<S, KK, 7>(P, sx, roff, sc, pd, pe, h);
+
+    // A operands: A[m][k] = MAT[chi][row m = j][col 4*kk + sc]
+    const R* post = static_cast<const R*>(P.post);
+    const R* lmix = static_cast<const R*>(P.locmix);
+    const R* post2 = static_cast<const R*>(P.post2);
+    const R* lmix2 = static_cast<const R*>(P.locmix2);
+    R ap[2][KK], al[2][KK], ap2[2][KK], al2[2][KK];
+#pragma unroll
+    for (int chi = 0; chi < 2; ++chi)
+#pragma unroll
+        for (int kk = 0; kk < KK; ++kk) {
+            const int idx = (chi * 16 + j) * 16 + 4 * kk + sc;
+            ap[chi][kk] = post[idx];
+            al[chi][kk] = lmix ? lmix[idx] : R(0);
+            ap2[chi][kk] = post2 ? post2[idx] : R(0);
+            al2[chi][kk] = lmix2 ? lmix2[idx] : R(0);
+        }
+    const bool has_loc = P.loc != nullptr;
+    const bool dense_loc = has_loc && lmix != nullptr;
+    const bool has_out2 = P.out2 != nullptr;
+    const R lscale = R(P.loc_scale);
+
+    double nrm = 0.0;
+#pragma unroll
+    for (int cp = 0; cp < 12; ++cp) {
+        const int chi = cp / 6;
+        // B-layout local values (needed by dense loc mixes)
+        R lr[KK], li[KK];
+#pragma unroll
+        for (int kk = 0; kk < KK; ++kk) { lr[kk] = 0; li[kk] = 0; }
+        if (dense_loc || (has_out2 && has_loc)) {
+#pragma unroll
+            for (int kk = 0; kk < KK; ++kk) {
+                const int s = sc + 4 * kk;
+                if (s < Ls) cload<S>(P.loc, roff + ((long)s * 12 + cp) * Vh + sx, lr[kk], li[kk]);
+            }
+        }
+        V cr = {0, 0, 0, 0}, ci = {0, 0, 0, 0};
+#pragma unroll
+        for (int kk = 0; kk < KK; ++kk) {
+            cr = mfma4(ap[chi][kk], h[kk][2 * cp], cr);
+            ci = mfma4(ap[chi][kk], h[kk][2 * cp + 1], ci);
+        }
+        if (dense_loc) {
+#pragma unroll
+            for (int kk = 0; kk < KK; ++kk) {
+                cr = mfma4(al[chi][kk], lr[kk], cr);
+                ci = mfma4(al[chi][kk], li[kk], ci);
+            }
+        }
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            const int s = out_row<R>(sc, i);
+            R orr = cr[i], oi = ci[i];
+            if (has_loc && !dense_loc && s < Ls) {
+                R xr, xi;
+                cload<S>(P.loc, roff + ((long)s * 12 + cp) * Vh + sx, xr, xi);
+                orr += lscale * xr;
+                oi += lscale * xi;
+            }
+            if (valid && s < Ls) {
+                if (P.out) cstore<S>(P.out, roff + ((long)s * 12 + cp) * Vh + site, orr, oi);
+                if (P.reduce == 1) nrm += double(orr) * double(orr) + double(oi) * double(oi);
+            }
+        }
+        if (has_out2) {
+            V dr = {0, 0, 0, 0}, di = {0, 0, 0, 0};
+#pragma unroll
+            for (int kk = 0; kk < KK; ++kk) {
+                dr = mfma4(ap2[chi][kk], h[kk][2 * cp], dr);
+                di = mfma4(ap2[chi][kk], h[kk][2 * cp + 1], di);
+            }
+            if (has_loc) {
+#pragma unroll
+                for (int kk = 0; kk < KK; ++kk) {
+                    dr = mfma4(al2[chi][kk], lr[kk], dr);
+                    di = mfma4(al2[chi][kk], li[kk], di);
+                }
+            }
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                const int s = out_row<R>(sc, i);
+                if (valid && s < Ls) {
+                    cstore<S>(P.out2, roff + ((long)s * 12 + cp) * Vh + site, dr[i], di[i]);
+                    if (P.reduce == 2) nrm += double(dr[i]) * double(dr[i]) + double(di[i]) * double(di[i]);
+                }
+            }
+        }
+    }
+
+    if (P.partial) {
+#pragma unroll
+        for (int off = 32; off >= 1; off >>= 1) nrm += __shfl_xor(nrm, off, 64);
+        __shared__ double red[4];
+        if (lane == 0) red[threadIdx.x >> 6] = nrm;
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            double t = 0.0;
+            for (int w = 0; w < (int)(blockDim.x >> 6); ++w) t += red[w];
+            P.partial[(long)blockIdx.y * gridDim.x + blockIdx.x] = t;
+        }
+    }
+}
+
+// ---------------------------------------------------------------------
+// Local dense s-mix on one half field: out = A . in (per chirality),
+// same lane layout and MFMA use as the hop epilogue.  Optional reduction.
+// ---------------------------------------------------------------------
+template <class S, int KK>
+__global__ __launch_bounds__(256) void mix_mfma_kernel(MixParams P) {
+    using R = typename Traits<S>::R;
+    using V = typename Vec4<R>::T;
+    const int lane = threadIdx.x & 63;
+    const int j = lane & 15, sc = lane >> 4;
+    const long Vh = P.Vh;
+    const int Ls = P.Ls;
+    const long site = ((long)blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6)) * 16 + j;
+    const bool valid = site < Vh;
+    const long sx = valid ? site : Vh - 1;
+    const long roff = (long)blockIdx.y * Ls * 12 * Vh;
+    const R* A = static_cast<const R*>(P.mat);
+    R a[2][KK];
+#pragma unroll
+    for (int chi = 0; chi < 2; ++chi)
+#pragma unroll
+        for (int kk = 0; kk < KK; ++kk) a[chi][kk] = A[(chi * 16 + j) * 16 + 4 * kk + sc];
+    double nrm = 0.0;
+#pragma unroll
+    for (int cp = 0; cp < 12; ++cp) {
+        const int chi = cp / 6;
+        V cr = {0, 0, 0, 0}, ci = {0, 0, 0, 0};
+#pragma unroll
+        for (int kk = 0; kk < KK; ++kk) {
+            const int s = sc + 4 * kk;
+            R xr = 0, xi = 0;
+            if (s < Ls) cload<S>(P.in, roff + ((long)s * 12 + cp) * Vh + sx, xr, xi);
+            cr = mfma4(a[chi][kk], xr, cr);
+            ci = mfma4(a[chi][kk], xi, ci);
+        }
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            const int s = out_row<R>(sc, i);
+            if (valid && s < Ls) {
+                cstore<S>(P.out, roff + ((long)s * 12 + cp) * Vh + site, cr[i], ci[i]);
+                nrm += double(cr[i]) * double(cr[i]) + double(ci[i]) * double(ci[i]);
+            }
+        }
+    }
+    if (P.partial) {
+#pragma unroll
+        for (int off = 32; off >= 1; off >>= 1) nrm += __shfl_xor(nrm, off, 64);
+        __shared__ double red[4];
+        if (lane == 0) red[threadIdx.x >> 6] = nrm;
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            double t = 0.0;
+            for (int w = 0; w < (int)(blockDim.x >> 6); ++w) t += red[w];
+            P.partial[(long)blockIdx.y * gridDim.x + blockIdx.x] = t;
+        }
+    }
+}
+
+// ---------------------------------------------------------------------
+// launchers
+// ---------------------------------------------------------------------
+int hop_grid_blocks(long Vh) { return (int)((Vh + 63) / 64); }
+
+template <class S>
+static void launch_hop_t(const HopParams& P, int nrhs, hipStream_t st) {
+    dim3 grid(hop_grid_blocks(P.Vh), nrhs), block(256);
+    const int KK = (P.Ls + 3) / 4;
+    switch (KK) {
+        case 1: hipLaunchKernelGGL((hop_mfma_kernel<S, 1>), grid, block, 0, st, P); break;
+        case 2: hipLaunchKernelGGL((hop_mfma_kernel<S, 2>), grid, block, 0, st, P); break;
+        case 3: hipLaunchKernelGGL((hop_mfma_kernel<S, 3>), grid, block, 0, st, P); break;
+        case 4: hipLaunchKernelGGL((hop_mfma_kernel<S, 4>), grid, block, 0, st, P); break;
+        default: throw Error{DWF_EDIMS, "Ls > 16 not supported by the fused hop"};
+    }
+    DWF_HIP(hipGetLastError());
+}
+
+void launch_hop(int kind, const HopParams& P, int nrhs, hipStream_t st) {
+    switch (kind) {
+        case ST_F64: launch_hop_t<double>(P, nrhs, st); break;
+        case ST_F32: launch_hop_t<float>(P, nrhs, st); break;
+        case ST_BF16: launch_hop_t<bf16s>(P, nrhs, st); break;
+        default: throw Error{DWF_EINVAL, "bad storage kind"};
+    }
+}
+
+template <class S>
+static void launch_mix_t(const MixParams& P, int nrhs, hipStream_t st) {
+    dim3 grid(hop_grid_blocks(P.Vh), nrhs), block(256);
+    const int KK = (P.Ls + 3) / 4;
+    switch (KK) {
+        case 1: hipLaunchKernelGGL((mix_mfma_kernel<S, 1>), grid, block, 0, st, P); break;
+        case 2: hipLaunchKernelGGL((mix_mfma_kernel<S, 2>), grid, block, 0, st, P); break;
+        case 3: hipLaunchKernelGGL((mix_mfma_kernel<S, 3>), grid, block, 0, st, P); break;
+        case 4: hipLaunchKernelGGL((mix_mfma_kernel<S, 4>), grid, block, 0, st, P); break;
+        default: throw Error{DWF_EDIMS, "Ls > 16 not supported"};
+    }
+    DWF_HIP(hipGetLastError());
+}
+
+void launch_mix(int kind, const MixParams& P, int nrhs, hipStream_t st) {
+    switch (kind) {
+        case ST_F64: launch_mix_t<double>(P, nrhs, st); break;
+        case ST_F32: launch_mix_t<float>(P, nrhs, st); break;
+        case ST_BF16: launch_mix_t<bf16s>(P, nrhs, st); break;
+        default: throw Error{DWF_EINVAL, "bad storage kind"};
+    }
+}
+
+}  // namespace dwf

@@ -1,0 +1,192 @@
+// Lattice geometry, gauge-link packing and operator coefficient setup.
+#include <cmath>
+#include <complex>
+#include <cstring>
+
+#include "dwf_internal.h"
+#include "precision.h"
+
+namespace dwf {
+
+using cd = std::complex<double>;
+
+static uint16_t host_f32_to_bf16(float f) {
+    uint32_t u;
+    std::memcpy(&u, &f, 4);
+    if ((u & 0x7f800000u) == 0x7f800000u && (u & 0x007fffffu)) return (uint16_t)((u >> 16) | 0x40u);
+    const uint32_t lsb = (u >> 16) & 1u;
+    u += 0x7fffu + lsb;
+    return (uint16_t)(u >> 16);
+}
+
+void build_geometry(dwf_lattice* L) {
+    const int Lx = L->dims[0], Ly = L->dims[1], Lz = L->dims[2], Lt = L->dims[3];
+    const long V = L->V, Vh = L->Vh;
+    L->lex_of_eo.assign(2 * Vh, -1);
+    for (long x = 0; x < V; ++x) {
+        long r = x;
+        const int cx = r % Lx; r /= Lx;
+        const int cy = r % Ly; r /= Ly;
+        const int cz = r % Lz; r /= Lz;
+        const int ct = (int)r;
+        const int p = (cx + cy + cz + ct) & 1;
+        L->lex_of_eo[p * Vh + (x >> 1)] = (int)x;
+    }
+    L->nbr_host.assign(2 * 8 * Vh, -1);
+    const int ext[4] = {Lx, Ly, Lz, Lt};
+    for (int p = 0; p < 2; ++p)
+        for (long i = 0; i < Vh; ++i) {
+            const long x = L->lex_of_eo[p * Vh + i];
+            int c[4];
+            long r = x;
+            for (int mu = 0; mu < 4; ++mu) { c[mu] = r % ext[mu]; r /= ext[mu]; }
+            for (int d = 0; d < 8; ++d) {
+                const int mu = d & 3, dir = d < 4 ? +1 : -1;
+                int cc[4] = {c[0], c[1], c[2], c[3]};
+                cc[mu] = (cc[mu] + dir + ext[mu]) % ext[mu];
+                const long y = cc[0] + (long)Lx * (cc[1] + (long)Ly * (cc[2] + (long)Lz * cc[3]));
+                L->nbr_host[(p * 8 + d) * Vh + i] = (int)(y >> 1);
+            }
+        }
+    L->nbr.alloc(sizeof(int) * 2 * 8 * Vh);
+    DWF_HIP(hipMemcpy(L->nbr.p, L->nbr_host.data(), L->nbr.bytes, hipMemcpyHostToDevice));
+    L->lex_of_eo_dev.alloc(sizeof(int) * 2 * Vh);
+    DWF_HIP(hipMemcpy(L->lex_of_eo_dev.p, L->lex_of_eo.data(), L->lex_of_eo_dev.bytes, hipMemcpyHostToDevice));
+}
+
+// Hop links per output parity: forward U_mu(x), backward U_mu(x-mu)^dag,
+// antiperiodic t phase folded into the links that cross the boundary.
+void upload_gauge(dwf_lattice* L, const cd* U) {
+    const int ext[4] = {L->dims[0], L->dims[1], L->dims[2], L->dims[3]};
+    const long Vh = L->Vh;
+    const size_t nl = (size_t)2 * 8 * 9 * Vh;
+    std::vector<cd> hl(nl);
+    for (int p = 0; p < 2; ++p)
+        for (long i = 0; i < Vh; ++i) {
+            const long x = L->lex_of_eo[p * Vh + i];
+            int c[4];
+            long r = x;
+            for (int mu = 0; mu < 4; ++mu) { c[mu] = r % ext[mu]; r /= ext[mu]; }
+            for (int d = 0; d < 8; ++d) {
+                const int mu = d & 3;
+                double phase = 1.0;
+                const cd* src;
+                if (d < 4) {
+                    src = U + (x * 4 + mu) * 9;
+                    if (mu == 3 && L->antiperiodic_t && c[3] == ext[3] - 1) phase = -1.0;
+                } else {
+                    int cc[4] = {c[0], c[1], c[2], c[3]};
+                    cc[mu] = (cc[mu] - 1 + ext[mu]) % ext[mu];
+                    const long y = cc[0] + (long)ext[0] * (cc[1] + (long)ext[1] * (cc[2] + (long)ext[2] * cc[3]));
+                    src = U + (y * 4 + mu) * 9;
+                    if (mu == 3 && L->antiperiodic_t && c[3] == 0) phase = -1.0;
+                }
+                for (int a = 0; a < 3; ++a)
+                    for (int b = 0; b < 3; ++b) {
+                        cd u = d < 4 ? src[a * 3 + b] : std::conj(src[b * 3 + a]);
+                        hl[((size_t)(p * 8 + d) * 9 + a * 3 + b) * Vh + i] = phase * u;
+                    }
+            }
+        }
+    L->links[ST_F64].alloc(nl * 16);
+    DWF_HIP(hipMemcpy(L->links[ST_F64].p, hl.data(), nl * 16, hipMemcpyHostToDevice));
+    std::vector<float> h32(2 * nl);
+    std::vector<uint16_t> h16(2 * nl);
+    for (size_t k = 0; k < nl; ++k) {
+        h32[2 * k] = (float)hl[k].real();
+        h32[2 * k + 1] = (float)hl[k].imag();
+        h16[2 * k] = host_f32_to_bf16(h32[2 * k]);
+        h16[2 * k + 1] = host_f32_to_bf16(h32[2 * k + 1]);
+    }
+    L->links[ST_F32].alloc(nl * 8);
+    DWF_HIP(hipMemcpy(L->links[ST_F32].p, h32.data(), nl * 8, hipMemcpyHostToDevice));
+    L->links[ST_BF16].alloc(nl * 4);
+    DWF_HIP(hipMemcpy(L->links[ST_BF16].p, h16.data(), nl * 4, hipMemcpyHostToDevice));
+    L->has_gauge = true;
+}
+
+// ---------------------------------------------------------------------
+// operator coefficients
+// ---------------------------------------------------------------------
+static void put_dense(std::vector<double>& buf, int slot, int Ls,
+                      const std::vector<double> (&A)[2], const double g5sign[2], double scale) {
+    for (int chi = 0; chi < 2; ++chi)
+        for (int r = 0; r < Ls; ++r)
+            for (int c = 0; c < Ls; ++c)
+                buf[(size_t)slot * MAT_ELEMS + (chi * 16 + r) * 16 + c] = scale * g5sign[chi] * A[chi][r * Ls + c];
+}
+
+static std::vector<double> transpose(const std::vector<double>& A, int n) {
+    std::vector<double> T(n * n);
+    for (int i = 0; i < n; ++i)
+        for (int j = 0; j < n; ++j) T[j * n + i] = A[i * n + j];
+    return T;
+}
+
+static std::vector<double> mm(const std::vector<double>& A, const std::vector<double>& B, int n) {
+    std::vector<double> C(n * n, 0.0);
+    for (int i = 0; i < n; ++i)
+        for (int k = 0; k < n; ++k)
+            for (int j = 0; j < n; ++j) C[i * n + j] += A[i * n + k] * B[k * n + j];
+    return C;
+}
+
+void setup_op(dwf_op* op) {
+    const int Ls = op->Ls;
+    op->fd = build_fifth_dim(Ls, op->M0, op->m, op->b, op->c, op->alpha);
+    const FifthDim& f = op->fd;
+    std::vector<double> h((size_t)NMAT * MAT_ELEMS, 0.0);
+    const double one[2] = {1.0, 1.0}, g5[2] = {1.0, -1.0};
+    std::vector<double> Qt[2], Mit[2], Kt[2], Mt[2], I[2], MitMinv[2];
+    for (int chi = 0; chi < 2; ++chi) {
+        Qt[chi] = transpose(f.Q[chi], Ls);
+        Mit[chi] = transpose(f.Minv[chi], Ls);
+        Kt[chi] = transpose(f.K[chi], Ls);
+        Mt[chi] = transpose(f.M[chi], Ls);
+        I[chi].assign(Ls * Ls, 0.0);
+        for (int s = 0; s < Ls; ++s) I[chi][s * Ls + s] = 1.0;
+        MitMinv[chi] = mm(Mit[chi], f.Minv[chi], Ls);
+    }
+    put_dense(h, MAT_Q, Ls, f.Q, one, 1.0);
+    put_dense(h, MAT_QT, Ls, Qt, one, 1.0);
+    put_dense(h, MAT_MQMINV, Ls, f.Minv, one, -0.25);
+    put_dense(h, MAT_G5MIT, Ls, Mit, g5, 1.0);
+    put_dense(h, MAT_G5MIT_MQMINV, Ls, MitMinv, g5, -0.25);
+    put_dense(h, MAT_MQG5KT, Ls, Kt, g5, -0.25);
+    put_dense(h, MAT_G5MT, Ls, Mt, g5, 1.0);
+    put_dense(h, MAT_HALFMINV, Ls, f.Minv, one, 0.5);
+    put_dense(h, MAT_MINV, Ls, f.Minv, one, 1.0);
+    put_dense(h, MAT_M, Ls, f.M, one, 1.0);
+    put_dense(h, MAT_MT, Ls, Mt, one, 1.0);
+    put_dense(h, MAT_MHALFI, Ls, I, one, -0.5);
+    put_dense(h, MAT_MHALFKTG5, Ls, Kt, g5, -0.5);
+    put_dense(h, MAT_IDENT, Ls, I, one, 1.0);
+    // (c/2) * identity on all 16 rows: used with fields of any s-extent
+    for (int chi = 0; chi < 2; ++chi)
+        for (int r = 0; r < 16; ++r) h[(size_t)MAT_CHALF * MAT_ELEMS + (chi * 16 + r) * 16 + r] = 0.5 * op->c;
+    op->mats_host = h;
+
+    std::vector<double> pre((size_t)NPRE * PRE_ELEMS, 0.0);
+    for (int s = 0; s < Ls; ++s) {
+        // K: diagonal and the cyclic neighbour (s-1 for chi 0, s+1 for chi 1)
+        const int sm = (s - 1 + Ls) % Ls, sp = (s + 1) % Ls;
+        pre[PRE_K * PRE_ELEMS + 0 * 16 + s] = f.K[0][s * Ls + s];
+        pre[PRE_K * PRE_ELEMS + 1 * 16 + s] = f.K[1][s * Ls + s];
+        pre[PRE_K * PRE_ELEMS + 2 * 16 + s] = f.K[0][s * Ls + sm];
+        pre[PRE_K * PRE_ELEMS + 3 * 16 + s] = f.K[1][s * Ls + sp];
+        pre[PRE_G5 * PRE_ELEMS + 0 * 16 + s] = 1.0;
+        pre[PRE_G5 * PRE_ELEMS + 1 * 16 + s] = -1.0;
+    }
+    op->mats[0].alloc(h.size() * 8);
+    DWF_HIP(hipMemcpy(op->mats[0].p, h.data(), h.size() * 8, hipMemcpyHostToDevice));
+    std::vector<float> hf(h.begin(), h.end());
+    op->mats[1].alloc(hf.size() * 4);
+    DWF_HIP(hipMemcpy(op->mats[1].p, hf.data(), hf.size() * 4, hipMemcpyHostToDevice));
+    op->pres[0].alloc(pre.size() * 8);
+    DWF_HIP(hipMemcpy(op->pres[0].p, pre.data(), pre.size() * 8, hipMemcpyHostToDevice));
+    std::vector<float> pf(pre.begin(), pre.end());
+    op->pres[1].alloc(pf.size() * 4);
+    DWF_HIP(hipMemcpy(op->pres[1].p, pf.data(), pf.size() * 4, hipMemcpyHostToDevice));
+}
+
+}  // namespace dwf

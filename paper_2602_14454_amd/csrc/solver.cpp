@@ -1,0 +1,235 @@
+// Solvers for D^(alpha) x5 = b5 through the even-odd Schur system
+// (Sec. 2.3): CG on D^dag D^ (CGNR), and FP64 defect correction around a
+// CGNR in FP32 or BF16 storage (the paper's single-precision solver used as
+// the preconditioner of a double-precision solve, Sec. 2.3).
+//
+// CG scalars stay on the device (finalize kernels compute alpha and beta from
+// the FP64 partial sums); the host reads them back every `check_every`
+// iterations to test convergence.
+#include "solver.h"
+
+#include <chrono>
+#include <cmath>
+#include <cstring>
+#include <memory>
+
+#include "blas.h"
+#include "ops.h"
+
+namespace dwf {
+
+struct Pinned {
+    double* h = nullptr;
+    explicit Pinned(size_t n) {
+        if (hipHostMalloc(reinterpret_cast<void**>(&h), n * sizeof(double), hipHostMallocDefault) != hipSuccess)
+            throw Error{DWF_ENOMEM, "hipHostMalloc failed"};
+        std::memset(h, 0, n * sizeof(double));
+    }
+    ~Pinned() {
+        if (h) (void)hipHostFree(h);
+    }
+};
+
+static void read_scalars(const double* dev, Pinned& host, hipStream_t st) {
+    DWF_HIP(hipMemcpyAsync(host.h, dev, CG_NSLOTS * sizeof(double), hipMemcpyDeviceToHost, st));
+    DWF_HIP(hipStreamSynchronize(st));
+}
+
+CgWork::CgWork(const dwf_op* op, int kx_, int kp_, int nrhs_) : kx(kx_), kp(kp_), nrhs(nrhs_) {
+    n = (long)op->Ls * 12 * op->lat->Vh * nrhs;
+    const size_t bx = complex_bytes_of(kx) * n, bp = complex_bytes_of(kp) * n;
+    x.alloc(bx);
+    r.alloc(bx);
+    p.alloc(bp);
+    t.alloc(bp);
+    v.alloc(bp);
+    w.alloc(bp);
+    const long np = std::max<long>(hop_partials(op, nrhs), blas_grid(n)) * 2 + 16;
+    partial.alloc(np * sizeof(double));
+    scal.alloc(CG_NSLOTS * sizeof(double));
+}
+
+int cgnr(const dwf_op* op, CgWork& W, const void* b_kp, double tol_rel, int maxiter, int check_every,
+         hipStream_t st, double* final_rel, bool* nan_seen) {
+    const long n = W.n;
+    double* partial = W.partial.as<double>();
+    double* scal = W.scal.as<double>();
+    Pinned hs(CG_NSLOTS);
+    if (check_every < 1) check_every = 1;
+    DWF_HIP(hipMemsetAsync(W.scal.p, 0, CG_NSLOTS * sizeof(double), st));
+    // r = D^dag b, p = r, x = 0
+    apply_dhat(op, W.kp, 1, W.w.p, b_kp, W.t.p, W.v.p, W.nrhs, st);
+    convert(W.kx, W.kp, W.r.p, W.w.p, n, st);
+    convert(W.kp, W.kx, W.p.p, W.r.p, n, st);
+    DWF_HIP(hipMemsetAsync(W.x.p, 0, complex_bytes_of(W.kx) * n, st));
+    norm2_partial(W.kx, W.r.p, n, partial, st);
+    finalize(partial, blas_grid(n), 1, scal + CG_RR, 0, st);
+    read_scalars(scal, hs, st);
+    const double rr0 = hs.h[CG_RR];
+    *nan_seen = !std::isfinite(rr0);
+    if (rr0 == 0.0 || *nan_seen) {
+        if (final_rel) *final_rel = 0.0;
+        return 0;
+    }
+    const double stop = tol_rel * tol_rel * rr0;
+    int k = 0;
+    double rr = rr0;
+    while (k < maxiter) {
+        apply_normal(op, W.kp, W.w.p, W.p.p, W.t.p, W.v.p, partial, W.nrhs, st);
+        finalize(partial, hop_partials(op, W.nrhs), 1, scal, 1, st);
+        cg_update_xr(W.kx, W.kp, W.x.p, W.r.p, W.p.p, W.w.p, n, scal + CG_ALPHA, partial, st);
+        finalize(partial, blas_grid(n), 1, scal, 2, st);
+        cg_update_p(W.kx, W.kp, W.p.p, W.r.p, n, scal + CG_BETA, st);
+        ++k;
+        if (k % check_every == 0 || k == maxiter) {
+            read_scalars(scal, hs, st);
+            rr = hs.h[CG_RR];
+            if (hs.h[CG_NANFLAG] != 0.0 || !std::isfinite(rr)) {
+                *nan_seen = true;
+                break;
+            }
+            if (rr <= stop) break;
+        }
+    }
+    if (final_rel) *final_rel = std::sqrt(rr / rr0);
+    return k;
+}
+
+// |v|^2 of a half field (device reduction, host result)
+static double norm2_host(int kind, const void* v, long n, double* partial, double* scal, Pinned& hs,
+                         hipStream_t st) {
+    norm2_partial(kind, v, n, partial, st);
+    finalize(partial, blas_grid(n), 1, scal + CG_TMP, 0, st);
+    read_scalars(scal, hs, st);
+    return hs.h[CG_TMP];
+}
+
+int solve(const dwf_op* op, void* x5, const void* b5, const dwf_solve_params* prm, dwf_solve_info* info,
+          hipStream_t st) {
+    const dwf_lattice* L = op->lat;
+    DWF_REQUIRE(L->has_gauge, DWF_ESTATE, "gauge field not set");
+    const long Vh = L->Vh, V = L->V;
+    const int Ls = op->Ls;
+    const long n = (long)Ls * 12 * Vh;
+    const size_t b64 = 16 * n;
+    DevBuf be(b64), bo(b64), bt(b64), xe(b64), xo(b64), rh(b64), te(b64), to(b64);
+    DevBuf partial((std::max<long>(hop_partials(op, 1), blas_grid(n)) * 2 + 16) * sizeof(double));
+    DevBuf scal(CG_NSLOTS * sizeof(double));
+    Pinned hs(CG_NSLOTS);
+    double* pp = partial.as<double>();
+    double* sc = scal.as<double>();
+
+    int kp = ST_F64;
+    if (prm->algo == DWF_ALGO_DC || prm->paper_mode) kp = prm->inner_prec;
+    DWF_REQUIRE(kp == ST_F64 || kp == ST_F32 || kp == ST_BF16, DWF_EINVAL, "bad inner precision");
+    // all workspace is allocated before the timed region starts
+    std::unique_ptr<CgWork> W(new CgWork(op, kp == ST_F64 ? ST_F64 : ST_F32, kp, 1));
+    DevBuf rin(16 * n);
+
+    hipEvent_t e0, e1;
+    DWF_HIP(hipEventCreate(&e0));
+    DWF_HIP(hipEventCreate(&e1));
+    DWF_HIP(hipEventRecord(e0, st));
+    DWF_HIP(hipMemsetAsync(scal.p, 0, CG_NSLOTS * sizeof(double), st));
+
+    const int* lex = L->lex_of_eo_dev.as<int>();
+    pack_full(ST_F64, be.p, b5, lex, Vh, V, Ls, st);
+    pack_full(ST_F64, bo.p, b5, lex + Vh, Vh, V, Ls, st);
+    const double b2 = norm2_host(ST_F64, be.p, n, pp, sc, hs, st) + norm2_host(ST_F64, bo.p, n, pp, sc, hs, st);
+    schur_rhs(op, ST_F64, bt.p, be.p, bo.p, to.p, 1, st);
+
+    const double tol = prm->tol > 0 ? prm->tol : 1e-10;
+    const int maxiter = prm->maxiter > 0 ? prm->maxiter : 100000;
+    double inner_tol = prm->inner_tol;
+    if (inner_tol <= 0) inner_tol = kp == ST_F64 ? tol : (kp == ST_F32 ? 1e-5 : 3e-2);
+    if (prm->paper_mode) inner_tol = 1e-7;   // |r|^2 / |r0|^2 < 1e-14
+
+    int total = 0, outer = 0, fallback = 0;
+    bool converged = false, nan_seen = false;
+    double rel5 = 1.0, last_inner_rel = 0.0;
+    DWF_HIP(hipMemsetAsync(xe.p, 0, b64, st));
+    convert(ST_F64, ST_F64, rh.p, bt.p, n, st);
+    if (b2 == 0.0) {
+        converged = true;
+        rel5 = 0.0;
+    }
+    double prev_rel = 1e300;
+    while (!converged && total < maxiter && outer < 100) {
+        const int kx = kp == ST_F64 ? ST_F64 : ST_F32;
+        if (W->kp != kp) W.reset(new CgWork(op, kx, kp, 1));
+        convert(kp, ST_F64, rin.p, rh.p, n, st);
+        int it = cgnr(op, *W, rin.p, inner_tol, maxiter - total, prm->check_every, st, &last_inner_rel, &nan_seen);
+        total += it;
+        ++outer;
+        if (nan_seen) break;
+        axpby(ST_F64, kx, xe.p, W->x.p, n, nullptr, 1.0, nullptr, 1.0, nullptr, st);
+        // rh = b~ - D^ xe (FP64); r5_e = -M rh, r5_o = 0 exactly after reconstruction
+        apply_dhat(op, ST_F64, 0, te.p, xe.p, to.p, rh.p, 1, st);
+        convert(ST_F64, ST_F64, rh.p, bt.p, n, st);
+        axpby(ST_F64, ST_F64, rh.p, te.p, n, nullptr, -1.0, nullptr, 1.0, nullptr, st);
+        mix(op, ST_F64, rh.p, te.p, MAT_M, nullptr, 1, st);
+        rel5 = std::sqrt(norm2_host(ST_F64, te.p, n, pp, sc, hs, st) / b2);
+        if (prm->paper_mode) break;
+        if (rel5 <= tol) {
+            converged = true;
+            break;
+        }
+        if (rel5 > 0.5 * prev_rel && kp != ST_F64) {
+            // stagnation of the low-precision correction: step up one precision
+            kp = kp == ST_BF16 ? ST_F32 : ST_F64;
+            fallback = 1;
+        }
+        prev_rel = rel5;
+    }
+    reconstruct_odd(op, ST_F64, xo.p, xe.p, bo.p, 1, st);
+    unpack_full(ST_F64, x5, xe.p, lex, Vh, V, Ls, st);
+    unpack_full(ST_F64, x5, xo.p, lex + Vh, Vh, V, Ls, st);
+    DWF_HIP(hipEventRecord(e1, st));
+    // final FP64 true residual of the 5D system (outside the timed region)
+    apply_full(op, ST_F64, 0, te.p, to.p, xe.p, xo.p, 1, st);
+    axpby(ST_F64, ST_F64, te.p, be.p, n, nullptr, 1.0, nullptr, -1.0, nullptr, st);
+    axpby(ST_F64, ST_F64, to.p, bo.p, n, nullptr, 1.0, nullptr, -1.0, nullptr, st);
+    const double r2 = norm2_host(ST_F64, te.p, n, pp, sc, hs, st) + norm2_host(ST_F64, to.p, n, pp, sc, hs, st);
+    float ms = 0;
+    DWF_HIP(hipEventElapsedTime(&ms, e0, e1));
+    DWF_HIP(hipEventDestroy(e0));
+    DWF_HIP(hipEventDestroy(e1));
+    const double true_res = b2 > 0 ? std::sqrt(r2 / b2) : 0.0;
+    if (info) {
+        info->iters = total;
+        info->outer_iters = outer;
+        info->fallback_used = fallback;
+        info->converged = (converged || (prm->paper_mode && !nan_seen)) ? 1 : 0;
+        info->true_res5 = true_res;
+        info->seconds = ms * 1e-3;
+        info->final_rel_res_even = last_inner_rel;
+    }
+    if (nan_seen) throw Error{DWF_ENAN, "NaN/Inf in a CG reduction"};
+    if (prm->paper_mode) return DWF_OK;
+    return (converged || true_res <= tol) ? DWF_OK : DWF_NOT_CONVERGED;
+}
+
+double true_residual(const dwf_op* op, const void* x5, const void* b5, hipStream_t st) {
+    const dwf_lattice* L = op->lat;
+    const long Vh = L->Vh, V = L->V;
+    const int Ls = op->Ls;
+    const long n = (long)Ls * 12 * Vh;
+    DevBuf xe(16 * n), xo(16 * n), be(16 * n), bo(16 * n), te(16 * n), to(16 * n);
+    DevBuf partial((blas_grid(n) + 16) * sizeof(double)), scal(CG_NSLOTS * sizeof(double));
+    Pinned hs(CG_NSLOTS);
+    const int* lex = L->lex_of_eo_dev.as<int>();
+    pack_full(ST_F64, xe.p, x5, lex, Vh, V, Ls, st);
+    pack_full(ST_F64, xo.p, x5, lex + Vh, Vh, V, Ls, st);
+    pack_full(ST_F64, be.p, b5, lex, Vh, V, Ls, st);
+    pack_full(ST_F64, bo.p, b5, lex + Vh, Vh, V, Ls, st);
+    apply_full(op, ST_F64, 0, te.p, to.p, xe.p, xo.p, 1, st);
+    double* pp = partial.as<double>();
+    double* sc = scal.as<double>();
+    const double b2 = norm2_host(ST_F64, be.p, n, pp, sc, hs, st) + norm2_host(ST_F64, bo.p, n, pp, sc, hs, st);
+    axpby(ST_F64, ST_F64, te.p, be.p, n, nullptr, 1.0, nullptr, -1.0, nullptr, st);
+    axpby(ST_F64, ST_F64, to.p, bo.p, n, nullptr, 1.0, nullptr, -1.0, nullptr, st);
+    const double r2 = norm2_host(ST_F64, te.p, n, pp, sc, hs, st) + norm2_host(ST_F64, to.p, n, pp, sc, hs, st);
+    return b2 > 0 ? std::sqrt(r2 / b2) : 0.0;
+}
+
+}  // namespace dwf

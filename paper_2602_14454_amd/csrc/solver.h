@@ -1,0 +1,26 @@
+// CG workspace and solver entry points (solver.cpp).
+#pragma once
+
+#include "dwf_internal.h"
+
+namespace dwf {
+
+// Inner CGNR workspace: x, r in storage kx; p, t (odd), v, w in storage kp.
+struct CgWork {
+    int kx, kp, nrhs;
+    long n;   // complex elements per field (all RHS)
+    DevBuf x, r, p, t, v, w, partial, scal;
+    CgWork(const dwf_op* op, int kx, int kp, int nrhs);
+};
+
+// CG on D^dag D^ e = D^dag b from e = 0; b in storage kp.  Stops when the
+// recursive residual |r| <= tol_rel |r0| or after maxiter iterations.
+// Result in W.x.  Returns the iteration count.
+int cgnr(const dwf_op* op, CgWork& W, const void* b_kp, double tol_rel, int maxiter, int check_every,
+         hipStream_t st, double* final_rel, bool* nan_seen);
+
+int solve(const dwf_op* op, void* x5, const void* b5, const dwf_solve_params* prm, dwf_solve_info* info,
+          hipStream_t st);
+double true_residual(const dwf_op* op, const void* x5, const void* b5, hipStream_t st);
+
+}  // namespace dwf

@@ -1,0 +1,119 @@
+"""GPU solves checked by the FP64 CPU oracle.
+
+The oracle recomputes the true 5D residual of the GPU's x5 and the 4D
+residual of its x4 (Sec. 2.3: r4 = b4 - D_eff((1-m) x4 + b4) vanishes for
+the exact 4D solution of any alpha), and compares x5/x4 with its own solve.
+"""
+import numpy as np
+import pytest
+
+import dwfgen
+import oracle
+
+pytestmark = pytest.mark.gpu
+
+
+def _dev(a):
+    import torch
+    return torch.from_numpy(np.ascontiguousarray(a)).to("cuda")
+
+
+def _setup(dims, Ls, M0, m, b=1.0, c=0.0, alpha=1.0, eps=0.3, seed=1, nsmear=0):
+    import paper_2602_14454_amd as dwf
+    U = dwfgen.make_links(dims, eps, seed, rho=0.1, nsmear=nsmear)
+    lat = dwf.Lattice(dims)
+    lat.set_gauge(U)
+    op = dwf.Op(lat, Ls, M0, m, b, c, alpha)
+    p = oracle.Params(dims=dims, Ls=Ls, M0=M0, m=m, b=b, c=c, alpha=alpha)
+    return lat, op, p, U
+
+
+def test_small_config_fp64_cgnr_to_1e12():
+    """4^4, Ls=8, Shamir, M0=1.6, m=0.05, eps=0.3 links (seed 1), 5D Gaussian source (seed 2)."""
+    import torch
+    import paper_2602_14454_amd as dwf
+    dims = (4, 4, 4, 4)
+    lat, op, p, U = _setup(dims, 8, 1.6, 0.05)
+    b5 = dwfgen.gaussian_source_5d(dims, 8, 2)
+    x5 = torch.zeros((8, p.V, 4, 3), dtype=torch.complex128, device="cuda")
+    st, info = op.solve(x5, _dev(b5), dwf.default_params(tol=1e-12))
+    assert st == 0 and info.converged
+    xg = x5.cpu().numpy()
+    assert info.true_res5 <= 1e-12
+    assert oracle.true_residual(p, U, xg, b5) <= 1e-12
+    xo, it, tr = oracle.solve(p, U, b5, tol=1e-13)
+    assert np.abs(xg - xo).max() / np.abs(xo).max() < 1e-10
+
+
+@pytest.mark.parametrize("b,c", [(1.0, 0.0), (1.5, 0.5)])
+def test_alpha_invariance_of_x4_and_4d_residual(b, c):
+    import torch
+    import paper_2602_14454_amd as dwf
+    dims = (4, 4, 2, 6)
+    Ls = 8
+    x4s = []
+    for al in (1.0, 0.5):
+        lat, op, p, U = _setup(dims, Ls, 1.6, 0.03, b, c, al, eps=0.5, seed=11)
+        b4 = dwfgen.gaussian_source_4d(dims, 12)
+        b5 = torch.empty((Ls, p.V, 4, 3), dtype=torch.complex128, device="cuda")
+        op.source_4d(b5, _dev(b4))
+        x5 = torch.zeros_like(b5)
+        st, info = op.solve(x5, b5, dwf.default_params(tol=1e-11))
+        assert st == 0
+        x4 = torch.empty((p.V, 4, 3), dtype=torch.complex128, device="cuda")
+        op.project_4d(x4, x5)
+        x4 = x4.cpu().numpy()
+        assert oracle.true_residual(p, U, x5.cpu().numpy(), b5.cpu().numpy()) <= 1e-11
+        assert oracle.residual_4d(p, U, x4, b4) <= 1e-10
+        x4s.append(x4)
+    assert np.abs(x4s[0] - x4s[1]).max() / np.abs(x4s[0]).max() < 1e-8
+
+
+@pytest.mark.parametrize("inner", ["f32", "bf16"])
+def test_defect_correction_reaches_fp64_accuracy(inner):
+    import torch
+    import paper_2602_14454_amd as dwf
+    dims = (6, 4, 4, 4)
+    Ls = 8
+    lat, op, p, U = _setup(dims, Ls, 1.8, 0.01, 1.0, 0.0, 0.6, eps=0.5, seed=21, nsmear=1)
+    b4 = dwfgen.gaussian_source_4d(dims, 22)
+    b5 = torch.empty((Ls, p.V, 4, 3), dtype=torch.complex128, device="cuda")
+    op.source_4d(b5, _dev(b4))
+    x5 = torch.zeros_like(b5)
+    st, info = op.solve(x5, b5, dwf.default_params(tol=1e-10, algo=dwf.ALGO_DC, inner_prec=inner))
+    assert st == 0 and info.outer_iters >= 2
+    assert oracle.true_residual(p, U, x5.cpu().numpy(), b5.cpu().numpy()) <= 1e-10
+    # same answer as the FP64 CGNR solve
+    x5d = torch.zeros_like(b5)
+    op.solve(x5d, b5, dwf.default_params(tol=1e-10))
+    assert (x5 - x5d).abs().max().item() / x5d.abs().max().item() < 1e-7
+
+
+def test_paper_mode_iteration_count_matches_oracle_cgnr():
+    """FP32 CGNR with the |r|^2 < 1e-14 (relative) stop: its iteration count
+    is within a few percent of the FP64 oracle CGNR with the same stop."""
+    import torch
+    import paper_2602_14454_amd as dwf
+    dims = (4, 4, 4, 4)
+    Ls = 8
+    lat, op, p, U = _setup(dims, Ls, 1.6, 0.05, 1.5, 0.5, 0.6, eps=0.5, seed=5)
+    b5 = dwfgen.gaussian_source_5d(dims, Ls, 6)
+    x5 = torch.zeros((Ls, p.V, 4, 3), dtype=torch.complex128, device="cuda")
+    st, info = op.solve(x5, _dev(b5), dwf.default_params(paper_mode=1, inner_prec=dwf.F32))
+    bt = oracle.schur_rhs(p, U, b5)
+    _, it_or = oracle.cgnr_even(p, U, bt, tol=1e-7)
+    assert it_or > 0
+    assert abs(info.iters - it_or) <= max(2, 0.05 * it_or)
+
+
+def test_nan_source_reports_enan():
+    import torch
+    import paper_2602_14454_amd as dwf
+    dims = (4, 4, 2, 2)
+    lat, op, p, U = _setup(dims, 4, 1.6, 0.05)
+    b5 = dwfgen.gaussian_source_5d(dims, 4, 2)
+    b5[1, 3, 0, 0] = np.nan
+    x5 = torch.zeros((4, p.V, 4, 3), dtype=torch.complex128, device="cuda")
+    with pytest.raises(dwf.DwfError) as e:
+        op.solve(x5, _dev(b5), dwf.default_params())
+    assert e.value.status == -6
