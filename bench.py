@@ -1,0 +1,241 @@
+#!/usr/bin/env python3
+"""Benchmark of the domain-wall solve on one MI355X.
+
+A step is one full solve of the 5D domain-wall system for a 4D source that is
+already resident in HBM: b5 = (-D_-) P^dag (0,..,b4) on the device, even-odd
+Schur RHS, CG on D^dag D^ (FP32 inner CG inside FP64 defect correction by
+default), reconstruction, 4D projection.  The timed region is exactly K such
+solves bracketed by torch.cuda.synchronize().
+
+Workload (default): 16^3 x 32 lattice, Ls = 16, M0 = 1.6, m = 0.01, Shamir
+(b, c) = (1, 0), Neff form alpha = 0.5; links U = exp(i 0.5 H) (seed 11) then
+3 stout steps rho = 0.1; Gaussian 4D source (seed 12).  Synthetic inputs stand
+in for the paper's quenched ensembles.
+
+Besides the headline line this script measures, once each: the FP64 CGNR
+solve (standard and Neff form) it is compared with, the BF16-inner solve,
+the 4D residual of every x4 (on the GPU), the roofline of the fused hop
+kernel (HIP events on the stream it runs on), and the FP64 CPU oracle on a
+bounded sample (a few CG iterations on the full lattice).
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import platform
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0   # MI355X HBM3E, published
+
+CONFIGS = {
+    "c2": dict(dims=(16, 16, 16, 32), Ls=16, M0=1.6, m=0.01, b=1.0, c=0.0, alpha=0.5, eps=0.5,
+               seed=11, src_seed=12, nsmear=3, rho=0.1),
+    "c3": dict(dims=(24, 24, 24, 48), Ls=16, M0=1.8, m=0.005, b=1.0, c=0.0, alpha=0.5, eps=0.5,
+               seed=21, src_seed=22, nsmear=3, rho=0.1),
+    "c1": dict(dims=(4, 4, 4, 4), Ls=8, M0=1.6, m=0.05, b=1.0, c=0.0, alpha=1.0, eps=0.3,
+               seed=1, src_seed=2, nsmear=0, rho=0.0),
+}
+MODES = {"dc_f32": ("DC", 1), "dc_bf16": ("DC", 2), "fp64": ("CGNR", 0)}
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def workload_name(c):
+    d = c["dims"]
+    return (f"{d[0]}^3x{d[3]} Ls={c['Ls']} M0={c['M0']} m={c['m']} (b,c)=({c['b']},{c['c']}) "
+            f"Neff alpha={c['alpha']}; links exp(i*{c['eps']}*H) + {c['nsmear']} stout rho={c['rho']}; "
+            f"Gaussian 4D source")
+
+
+def source_hash():
+    h = hashlib.sha256()
+    for f in ("hop.hip", "hop.h", "precision.h"):
+        with open(os.path.join(ROOT, "paper_2602_14454_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--config", default="c2", choices=sorted(CONFIGS))
+    ap.add_argument("--mode", default="dc_f32", choices=sorted(MODES))
+    ap.add_argument("--skip-cpu", action="store_true", help="skip the oracle CPU baseline")
+    ap.add_argument("--skip-variants", action="store_true", help="skip the comparison solves")
+    ap.add_argument("--hop-only", action="store_true", help="only time the fused hop (for counter runs)")
+    ap.add_argument("--cpu-iters", type=int, default=3)
+    ap.add_argument("--hop-reps", type=int, default=200)
+    args = ap.parse_args()
+
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1"}))
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    import dwfgen
+    import paper_2602_14454_amd as dwf
+
+    torch.cuda.set_device(0)
+    dev = "cuda:0"
+    cfg = dict(CONFIGS[args.config])
+    dims, Ls = cfg["dims"], cfg["Ls"]
+    V = int(np.prod(dims))
+
+    t0 = time.time()
+    U = dwfgen.make_links(dims, cfg["eps"], cfg["seed"], rho=cfg["rho"], nsmear=cfg["nsmear"])
+    plaq = dwfgen.plaquette(U, dims)
+    b4h = dwfgen.gaussian_source_4d(dims, cfg["src_seed"])
+    log(f"inputs generated in {time.time() - t0:.1f}s, plaquette {plaq:.6f}")
+
+    lat = dwf.Lattice(dims)
+    lat.set_gauge(U)
+    op = dwf.Op(lat, Ls, cfg["M0"], cfg["m"], cfg["b"], cfg["c"], cfg["alpha"])
+    b4 = torch.from_numpy(b4h).to(dev)
+    b5 = torch.empty((Ls, V, 4, 3), dtype=torch.complex128, device=dev)
+    x5 = torch.zeros_like(b5)
+    x4 = torch.empty((V, 4, 3), dtype=torch.complex128, device=dev)
+
+    hop_prec = {"dc_f32": dwf.F32, "dc_bf16": dwf.BF16, "fp64": dwf.F64}[args.mode]
+    if args.hop_only:
+        ms, nbytes = op.bench_hop(prec=hop_prec, nrep=args.hop_reps)
+        copy_bytes = 1 << 30
+        cms = dwf.bench_copy(copy_bytes, nrep=20)
+        print(json.dumps({"hop_ms": ms, "hop_bytes": nbytes, "hop_GBps": nbytes / ms / 1e6,
+                          "copy_bytes": copy_bytes, "copy_ms": cms}))
+        return
+
+    algo, inner = MODES[args.mode]
+    params = dwf.default_params(tol=1e-10, check_every=8)
+    if algo == "DC":
+        params.algo = dwf.ALGO_DC
+        params.inner_prec = inner
+
+    def one_solve(p, o=op):
+        o.source_4d(b5, b4)
+        x5.zero_()
+        st, info = o.solve(x5, b5, p)
+        o.project_4d(x4, x5)
+        return st, info
+
+    for _ in range(args.warmup):
+        one_solve(params)
+    torch.cuda.synchronize()
+    t_start = time.perf_counter()
+    infos = []
+    for _ in range(args.steps):
+        st, info = one_solve(params)
+        infos.append(info.as_dict())
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t_start
+    t_solve = elapsed / args.steps
+    res4 = op.residual_4d(x4, b4)
+    x4_head = x4.clone()
+    log(f"{args.mode}: {t_solve:.4f} s/solve, iters {infos[-1]['iters']}, outer {infos[-1]['outer_iters']}, "
+        f"true_res5 {infos[-1]['true_res5']:.2e}, res4 {res4:.2e}")
+
+    variants = {}
+    if not args.skip_variants:
+        def run_variant(name, p, o):
+            torch.cuda.synchronize()
+            t = time.perf_counter()
+            st, info = one_solve(p, o)
+            torch.cuda.synchronize()
+            dt = time.perf_counter() - t
+            r4 = o.residual_4d(x4, b4)
+            variants[name] = {"seconds": dt, "iters": info.iters, "outer_iters": info.outer_iters,
+                              "true_res5": info.true_res5, "res4": r4, "status": st,
+                              "fallback": info.fallback_used}
+            log(f"{name}: {dt:.3f}s iters {info.iters} true_res5 {info.true_res5:.2e} res4 {r4:.2e}")
+            return x4.clone()
+
+        p64 = dwf.default_params(tol=1e-10, check_every=8)
+        x4_64 = run_variant("fp64_cgnr_neff", p64, op)
+        op_std = dwf.Op(lat, Ls, cfg["M0"], cfg["m"], cfg["b"], cfg["c"], 1.0)
+        x4_std = run_variant("fp64_cgnr_standard", p64, op_std)
+        pbf = dwf.default_params(tol=1e-10, check_every=8, algo=dwf.ALGO_DC, inner_prec=dwf.BF16)
+        x4_bf = run_variant("dc_bf16_neff", pbf, op)
+        pf = dwf.default_params(tol=1e-10, check_every=8, algo=dwf.ALGO_DC, inner_prec=dwf.F32)
+        x4_f = run_variant("dc_f32_neff", pf, op)
+        pp = dwf.default_params(check_every=8, paper_mode=1, inner_prec=dwf.F32)
+        for name, o in (("paper_mode_f32_neff", op), ("paper_mode_f32_standard", op_std)):
+            st, info = one_solve(pp, o)
+            variants[name] = {"iters": info.iters, "true_res5": info.true_res5}
+        nrm = torch.linalg.vector_norm(x4_64).item()
+        for name, xv in (("fp64_cgnr_standard", x4_std), ("dc_bf16_neff", x4_bf), ("dc_f32_neff", x4_f)):
+            variants[name]["x4_rel_err_vs_fp64"] = torch.linalg.vector_norm(xv - x4_64).item() / nrm
+        variants["headline_x4_rel_err_vs_fp64"] = torch.linalg.vector_norm(x4_head - x4_64).item() / nrm
+        it_n, it_s = variants["paper_mode_f32_neff"]["iters"], variants["paper_mode_f32_standard"]["iters"]
+        variants["paper_mode_iteration_reduction"] = 1.0 - it_n / it_s
+
+    # fused hop roofline (the dominant kernel), HIP events on its stream
+    hop = {}
+    for pname, pk in (("f64", dwf.F64), ("f32", dwf.F32), ("bf16", dwf.BF16)):
+        ms, nbytes = op.bench_hop(prec=pk, nrep=args.hop_reps)
+        hop[pname] = {"ms": ms, "bytes": nbytes, "GBps": nbytes / ms / 1e6}
+        log(f"hop {pname}: {ms * 1e3:.1f} us, {nbytes / ms / 1e6:.0f} GB/s")
+    hp = {"dc_f32": "f32", "dc_bf16": "bf16", "fp64": "f64"}[args.mode]
+    achieved = hop[hp]["GBps"]
+    traffic = None
+    cpath = os.path.join(ROOT, "profiles", "hop_counters.json")
+    if os.path.exists(cpath):
+        with open(cpath) as fh:
+            cnt = json.load(fh)
+        key = f"{args.config}_{hp}"
+        if cnt.get("source_hash") == source_hash() and key in cnt.get("traffic_bytes", {}):
+            traffic = cnt["traffic_bytes"][key]
+    roofline = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
+                "kernel": f"hop_mfma_kernel<{hp}> (bench instance), out_o = Q H_oe K in_e",
+                "algorithmic_bytes_per_launch": hop[hp]["bytes"], "ms_per_launch": hop[hp]["ms"]}
+
+    cpu = None
+    if not args.skip_cpu:
+        import oracle
+        p = oracle.Params(dims=dims, Ls=Ls, M0=cfg["M0"], m=cfg["m"], b=cfg["b"], c=cfg["c"],
+                          alpha=cfg["alpha"])
+        xe = dwfgen.gaussian_source_5d(dims, Ls, 3)[:, : V // 2].copy()
+        t = time.perf_counter()
+        y = xe
+        for _ in range(args.cpu_iters):
+            q = oracle.dhat(p, U, y)
+            y = oracle.dhat(p, U, q, dagger=True)
+        t_iter = (time.perf_counter() - t) / args.cpu_iters
+        n_it = variants.get("fp64_cgnr_neff", {}).get("iters") or infos[-1]["iters"]
+        cpu = {"value": t_iter * n_it, "unit": "s", "cores": oracle.num_threads(), "kind": "oracle",
+               "sample": (f"{args.cpu_iters} FP64 oracle CGNR iterations (D^ then D^dag, full 4x4 spin "
+                          f"matrices, restriction-based Schur) on the full lattice: {t_iter:.2f} s/iteration, "
+                          f"scaled by the {n_it} iterations of the GPU FP64 CGNR solve"),
+               "cpu": platform.processor() or platform.machine()}
+        log(f"oracle: {t_iter:.2f} s/iter on {cpu['cores']} threads -> {cpu['value']:.0f} s/solve")
+
+    out = {
+        "metric": ("time to 1e-10 4D residual (one solve, b4 resident -> x4 resident): "
+                   f"{args.mode} Neff-form CGNR; D_dw hop HBM GB/s in roofline"),
+        "value": t_solve, "unit": "s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": t_solve * 1e3, "higher_is_better": False, "scaling": "weak", "vs_baseline": None,
+        "dtype": {"dc_f32": "f32", "dc_bf16": "bf16", "fp64": "f64"}[args.mode], "data": "synthetic",
+        "config": {"workload": workload_name(cfg), "lattice": list(dims), "Ls": Ls, "mode": args.mode,
+                   "tol_true_res5": 1e-10, "plaquette": plaq},
+        "roofline": roofline, "cpu_baseline": cpu,
+        "solve": {"iters": infos[-1]["iters"], "outer_iters": infos[-1]["outer_iters"],
+                  "true_res5": infos[-1]["true_res5"], "res4": res4,
+                  "gpu_event_seconds": infos[-1]["seconds"]},
+        "variants": variants, "hop": hop,
+    }
+    print(json.dumps(out))
+
+
+if __name__ == "__main__":
+    main()

@@ -42,6 +42,8 @@
 #ifndef DWF_H
 #define DWF_H
 
+#include <stddef.h>
+
 #ifdef __cplusplus
 extern "C" {
 #endif
@@ -99,9 +101,13 @@ void dwf_lattice_destroy(dwf_lattice* lat);
  * output parity, backward links stored as U^dag, antiperiodic phase folded). */
 int dwf_lattice_set_gauge(dwf_lattice* lat, const void* U, int on_device, void* stream);
 
-/* Lattice geometry queries (for tests): integer maps written to host arrays.
- * lex_of_eo: [2][V/2]; nbr: [2][8][V/2] eo index of x +/- mu (order +x,-x,+y,-y,...). */
-int dwf_lattice_maps(const dwf_lattice* lat, int* lex_of_eo, int* nbr);
+/* Lattice geometry queries (for tests), read back from the device tables the
+ * kernels use and written to host arrays.  The library keeps each parity's
+ * sites in an internal order (spatial bricks swept in t, for cache reuse):
+ * lex_of_site [2][V/2] gives the lexicographic index of internal site i of
+ * parity p; nbr [2][8][V/2] the lexicographic index of its neighbour in
+ * direction d (d = 0..3: x+mu for mu = x,y,z,t; d = 4..7: x-mu). */
+int dwf_lattice_maps(const dwf_lattice* lat, int* lex_of_site, int* nbr);
 
 /* ---- operator ------------------------------------------------------- */
 
@@ -134,6 +140,15 @@ int dwf_solve(const dwf_op* op, void* x5, const void* b5, const dwf_solve_params
 /* |b5 - D^(alpha) x5| / |b5| in FP64. */
 int dwf_true_residual(const dwf_op* op, const void* x5, const void* b5, double* rel, void* stream);
 
+/* 4D residual |r4| / |b4| of a 4D solution x4 for source b4 (both 4D
+ * canonical, device).  With D_eff(m) y = [P^dag D(1)^-1 D(m) P (y,0,..,0)]_{s=1}
+ * at alpha = 1, the exact x4 of any alpha satisfies (1-m) x4 + b4 =
+ * D_eff^-1 b4 (the 4D solution is alpha independent, Sec. 2.3), so
+ * r4 = b4 - D_eff((1-m) x4 + b4).  Costs one D(m) and one m = 1 FP64
+ * solve to tol_inner (<= 0: 1e-13).  Synchronises the stream. */
+int dwf_residual_4d(const dwf_op* op, const void* x4, const void* b4, double tol_inner, double* rel,
+                    void* stream);
+
 /* ---- measurement helpers ------------------------------------------ */
 
 /* Times `nrep` launches of the fused half-lattice hop kernel of D^ (the
@@ -142,6 +157,10 @@ int dwf_true_residual(const dwf_op* op, const void* x5, const void* b5, double* 
  * mean kernel time in ms and the algorithmic bytes of one launch. */
 int dwf_bench_hop(const dwf_op* op, int prec, int nrep, double* ms_per_launch,
                   double* bytes_per_launch, void* stream);
+
+/* Times `nrep` launches of a plain 16-byte-vector copy of `bytes` bytes
+ * (device buffers owned by the library); used to calibrate memory counters. */
+int dwf_bench_copy(size_t bytes, int nrep, double* ms_per_launch, void* stream);
 
 const char* dwf_status_string(int status);
 const char* dwf_last_error(void);

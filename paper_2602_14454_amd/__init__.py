@@ -20,7 +20,8 @@ __all__ = [
 ]
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(_HERE, "libdwf.so")
+# DWF_LIB selects another build of the same library (kernel-variant tuning).
+LIB_PATH = os.environ.get("DWF_LIB") or os.path.join(_HERE, "libdwf.so")
 
 F64, F32, BF16 = 0, 1, 2
 FULL5D, EVEN5D = 0, 1
@@ -70,6 +71,8 @@ SIGNATURES = {
     "dwf_solve": (_i, [_vp, _vp, _vp, ctypes.POINTER(SolveParams), ctypes.POINTER(SolveInfo), _vp]),
     "dwf_true_residual": (_i, [_vp, _vp, _vp, _dp, _vp]),
     "dwf_bench_hop": (_i, [_vp, _i, _i, _dp, _dp, _vp]),
+    "dwf_residual_4d": (_i, [_vp, _vp, _vp, _d, _dp, _vp]),
+    "dwf_bench_copy": (_i, [ctypes.c_size_t, _i, _dp, _vp]),
     "dwf_status_string": (ctypes.c_char_p, [_i]),
     "dwf_last_error": (ctypes.c_char_p, []),
 }
@@ -236,6 +239,12 @@ class Op:
                "dwf_true_residual")
         return r.value
 
+    def residual_4d(self, x4, b4, tol_inner=1e-13, stream=None) -> float:
+        r = ctypes.c_double()
+        _check(load().dwf_residual_4d(self._h, _dev_ptr(x4), _dev_ptr(b4), float(tol_inner), ctypes.byref(r),
+                                      _stream(stream)), "dwf_residual_4d")
+        return r.value
+
     def bench_hop(self, prec=F32, nrep=50, stream=None):
         ms = ctypes.c_double()
         by = ctypes.c_double()
@@ -247,3 +256,10 @@ class Op:
         if getattr(self, "_h", None) and _lib is not None:
             _lib.dwf_op_destroy(self._h)
             self._h = None
+
+
+def bench_copy(nbytes: int, nrep: int = 20, stream=None) -> float:
+    """Mean time (ms) of a plain device copy of nbytes (counter calibration)."""
+    ms = ctypes.c_double()
+    _check(load().dwf_bench_copy(int(nbytes), int(nrep), ctypes.byref(ms), _stream(stream)), "dwf_bench_copy")
+    return ms.value

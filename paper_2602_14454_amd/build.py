@@ -60,31 +60,33 @@ def _flags():
             "-Wall", "-Wno-unused-result", "-I" + os.path.join(HERE, "..", "include")]
 
 
-def _compile(src: str) -> str:
-    obj = os.path.join(BUILD_DIR, os.path.splitext(src)[0] + ".o")
-    cmd = [_hipcc()] + _flags() + ["-x", "hip", "-c", os.path.join(CSRC, src), "-o", obj]
+def _compile(src: str, defines=(), build_dir=None) -> str:
+    obj = os.path.join(build_dir or BUILD_DIR, os.path.splitext(src)[0] + ".o")
+    cmd = [_hipcc()] + _flags() + [f"-D{d}" for d in defines] + ["-x", "hip", "-c", os.path.join(CSRC, src), "-o", obj]
     r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode != 0:
         raise RuntimeError(f"compile failed: {' '.join(cmd)}\n{r.stdout}\n{r.stderr}")
     return obj
 
 
-def build(verbose: bool = False) -> str:
-    os.makedirs(BUILD_DIR, exist_ok=True)
+def build(verbose: bool = False, out: str = LIB, defines=()) -> str:
+    """Compile and link libdwf.so; `defines` are extra -D macros (tuning variants)."""
+    bdir = BUILD_DIR if not defines else os.path.join(BUILD_DIR, "v_" + "_".join(d.replace("=", "") for d in defines))
+    os.makedirs(bdir, exist_ok=True)
     jobs = min(len(SOURCES), max(1, (os.cpu_count() or 2) // 2))
     with cf.ThreadPoolExecutor(jobs) as ex:
-        objs = list(ex.map(_compile, SOURCES))
-    tmp = LIB + ".tmp"
+        objs = list(ex.map(lambda src: _compile(src, defines, bdir), SOURCES))
+    tmp = out + ".tmp"
     rt = _hip_runtime_dir()
     cmd = [_hipcc(), "-shared", "-fPIC", f"--offload-arch={ARCH}", "-no-hip-rt", "-o", tmp] + objs + [
         os.path.join(rt, "libamdhip64.so")]
     r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode != 0:
         raise RuntimeError(f"link failed: {' '.join(cmd)}\n{r.stdout}\n{r.stderr}")
-    os.replace(tmp, LIB)
+    os.replace(tmp, out)
     if verbose:
-        print("built", LIB)
-    return LIB
+        print("built", out)
+    return out
 
 
 if __name__ == "__main__":

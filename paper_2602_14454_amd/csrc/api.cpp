@@ -9,6 +9,7 @@
 
 #include "blas.h"
 #include "dwf_internal.h"
+#include "hop.h"
 #include "ops.h"
 #include "solver.h"
 
@@ -80,6 +81,7 @@ int dwf_lattice_create(const int dims[4], int antiperiodic_t, dwf_lattice** out)
         L->V = (long)dims[0] * dims[1] * dims[2] * dims[3];
         DWF_REQUIRE(L->V < (1L << 30), DWF_EDIMS, "lattice volume too large for int32 site indices");
         L->Vh = L->V / 2;
+        L->Vhp = L->Vh;
         build_geometry(L.get());
         *out = L.release();
         return DWF_OK;
@@ -104,14 +106,19 @@ int dwf_lattice_set_gauge(dwf_lattice* lat, const void* U, int on_device, void* 
     });
 }
 
-int dwf_lattice_maps(const dwf_lattice* lat, int* lex_of_eo, int* nbr) {
+int dwf_lattice_maps(const dwf_lattice* lat, int* lex_of_site, int* nbr) {
     return guarded([&] {
         DWF_REQUIRE(lat, DWF_EINVAL, "null lattice");
-        if (lex_of_eo) std::memcpy(lex_of_eo, lat->lex_of_eo.data(), sizeof(int) * lat->lex_of_eo.size());
-        if (nbr) {
-            // read back the device table so that what the kernels use is what is returned
-            DWF_HIP(hipMemcpy(nbr, lat->nbr.p, lat->nbr.bytes, hipMemcpyDeviceToHost));
-        }
+        // read back the device tables, so that what the kernels use is what is returned
+        std::vector<int> lx(2 * lat->Vh), nb(2 * 8 * lat->Vhp);
+        DWF_HIP(hipMemcpy(lx.data(), lat->lex_of_site_dev.p, lat->lex_of_site_dev.bytes, hipMemcpyDeviceToHost));
+        DWF_HIP(hipMemcpy(nb.data(), lat->nbr.p, lat->nbr.bytes, hipMemcpyDeviceToHost));
+        if (lex_of_site) std::memcpy(lex_of_site, lx.data(), sizeof(int) * lx.size());
+        if (nbr)
+            for (int p = 0; p < 2; ++p)
+                for (int d = 0; d < 8; ++d)
+                    for (long i = 0; i < lat->Vh; ++i)
+                        nbr[(p * 8 + d) * lat->Vh + i] = lx[(1 - p) * lat->Vh + nb[(p * 8 + d) * lat->Vhp + i]];
         return DWF_OK;
     });
 }
@@ -148,23 +155,23 @@ int dwf_apply(const dwf_op* op, int space, int dagger, int prec, void* out, cons
         const int k = kind_of(prec);
         const dwf_lattice* L = op->lat;
         DWF_REQUIRE(L->has_gauge, DWF_ESTATE, "gauge field not set");
-        const long Vh = L->Vh, V = L->V, n = (long)op->Ls * 12 * Vh;
+        const long Vh = L->Vh, Vhp = L->Vhp, V = L->V, n = (long)op->Ls * 12 * Vhp;
         const size_t bytes = complex_bytes_of(k) * n;
         hipStream_t st = S(stream);
-        const int* lex = L->lex_of_eo_dev.as<int>();
+        const int* lex = L->lex_of_site_dev.as<int>();
         if (space == DWF_FULL5D) {
             DevBuf ie(bytes), io(bytes), oe(bytes), oo(bytes);
-            pack_full(k, ie.p, in, lex, Vh, V, op->Ls, st);
-            pack_full(k, io.p, in, lex + Vh, Vh, V, op->Ls, st);
+            pack_full(k, ie.p, in, lex, Vh, Vhp, V, op->Ls, st);
+            pack_full(k, io.p, in, lex + Vh, Vh, Vhp, V, op->Ls, st);
             apply_full(op, k, dagger, oe.p, oo.p, ie.p, io.p, 1, st);
-            unpack_full(k, out, oe.p, lex, Vh, V, op->Ls, st);
-            unpack_full(k, out, oo.p, lex + Vh, Vh, V, op->Ls, st);
+            unpack_full(k, out, oe.p, lex, Vh, Vhp, V, op->Ls, st);
+            unpack_full(k, out, oo.p, lex + Vh, Vh, Vhp, V, op->Ls, st);
             DWF_HIP(hipStreamSynchronize(st));
         } else if (space == DWF_EVEN5D) {
             DevBuf ie(bytes), oe(bytes), to(bytes), te(bytes);
-            pack_half(k, ie.p, in, Vh, op->Ls, st);
+            pack_half(k, ie.p, in, lex, Vh, Vhp, op->Ls, st);
             apply_dhat(op, k, dagger, oe.p, ie.p, to.p, te.p, 1, st);
-            unpack_half(k, out, oe.p, Vh, op->Ls, st);
+            unpack_half(k, out, oe.p, lex, Vh, Vhp, op->Ls, st);
             DWF_HIP(hipStreamSynchronize(st));
         } else {
             throw Error{DWF_EINVAL, "bad space"};
@@ -179,13 +186,14 @@ int dwf_apply_normal(const dwf_op* op, int prec, void* out, const void* in, void
         DWF_REQUIRE(out != in, DWF_EINVAL, "in and out must not alias");
         const int k = kind_of(prec);
         DWF_REQUIRE(op->lat->has_gauge, DWF_ESTATE, "gauge field not set");
-        const long Vh = op->lat->Vh, n = (long)op->Ls * 12 * Vh;
+        const long Vh = op->lat->Vh, Vhp = op->lat->Vhp, n = (long)op->Ls * 12 * Vhp;
         const size_t bytes = complex_bytes_of(k) * n;
         hipStream_t st = S(stream);
         DevBuf ie(bytes), oe(bytes), to(bytes), tv(bytes);
-        pack_half(k, ie.p, in, Vh, op->Ls, st);
+        const int* lex = op->lat->lex_of_site_dev.as<int>();
+        pack_half(k, ie.p, in, lex, Vh, Vhp, op->Ls, st);
         apply_normal(op, k, oe.p, ie.p, to.p, tv.p, nullptr, 1, st);
-        unpack_half(k, out, oe.p, Vh, op->Ls, st);
+        unpack_half(k, out, oe.p, lex, Vh, Vhp, op->Ls, st);
         DWF_HIP(hipStreamSynchronize(st));
         return DWF_OK;
     });
@@ -196,20 +204,20 @@ int dwf_source_4d(const dwf_op* op, void* b5, const void* b4, void* stream) {
         DWF_REQUIRE(op && b5 && b4, DWF_EINVAL, "null argument");
         const dwf_lattice* L = op->lat;
         DWF_REQUIRE(L->has_gauge, DWF_ESTATE, "gauge field not set");
-        const long Vh = L->Vh, V = L->V;
+        const long Vh = L->Vh, Vhp = L->Vhp, V = L->V;
         const int Ls = op->Ls;
         hipStream_t st = S(stream);
-        const int* lex = L->lex_of_eo_dev.as<int>();
-        const size_t pair_bytes = 16 * (size_t)2 * 12 * Vh;
+        const int* lex = L->lex_of_site_dev.as<int>();
+        const size_t pair_bytes = 16 * (size_t)2 * 12 * Vhp;
         DevBuf pe(pair_bytes), po(pair_bytes), oe(pair_bytes), oo(pair_bytes);
-        pack_chiral_pair_f64(pe.p, b4, lex, Vh, st);
-        pack_chiral_pair_f64(po.p, b4, lex + Vh, Vh, st);
+        pack_chiral_pair_f64(pe.p, b4, lex, Vh, Vhp, st);
+        pack_chiral_pair_f64(po.p, b4, lex + Vh, Vh, Vhp, st);
         source_pair(op, oe.p, po.p, pe.p, 0, st);
         source_pair(op, oo.p, pe.p, po.p, 1, st);
         // b5 = 0 except s = 0 (slice 0 of the pair) and s = Ls-1 (slice 1)
         DWF_HIP(hipMemsetAsync(b5, 0, (size_t)16 * Ls * V * 12, st));
-        const size_t slice = (size_t)16 * 12 * Vh;
-        DevBuf fe((size_t)16 * Ls * 12 * Vh), fo((size_t)16 * Ls * 12 * Vh);
+        const size_t slice = (size_t)16 * 12 * Vhp;
+        DevBuf fe((size_t)16 * Ls * 12 * Vhp), fo((size_t)16 * Ls * 12 * Vhp);
         DWF_HIP(hipMemsetAsync(fe.p, 0, fe.bytes, st));
         DWF_HIP(hipMemsetAsync(fo.p, 0, fo.bytes, st));
         DWF_HIP(hipMemcpyAsync(fe.p, oe.p, slice, hipMemcpyDeviceToDevice, st));
@@ -218,8 +226,8 @@ int dwf_source_4d(const dwf_op* op, void* b5, const void* b4, void* stream) {
                                hipMemcpyDeviceToDevice, st));
         DWF_HIP(hipMemcpyAsync(fo.as<char>() + slice * (Ls - 1), oo.as<char>() + slice, slice,
                                hipMemcpyDeviceToDevice, st));
-        unpack_full(ST_F64, b5, fe.p, lex, Vh, V, Ls, st);
-        unpack_full(ST_F64, b5, fo.p, lex + Vh, Vh, V, Ls, st);
+        unpack_full(ST_F64, b5, fe.p, lex, Vh, Vhp, V, Ls, st);
+        unpack_full(ST_F64, b5, fo.p, lex + Vh, Vh, Vhp, V, Ls, st);
         DWF_HIP(hipStreamSynchronize(st));
         return DWF_OK;
     });
@@ -261,19 +269,19 @@ int dwf_bench_hop(const dwf_op* op, int prec, int nrep, double* ms_per_launch, d
         const int k = kind_of(prec);
         const dwf_lattice* L = op->lat;
         DWF_REQUIRE(L->has_gauge, DWF_ESTATE, "gauge field not set");
-        const long Vh = L->Vh, n = (long)op->Ls * 12 * Vh;
+        const long Vh = L->Vh, n = (long)op->Ls * 12 * L->Vhp;
         const size_t cb = complex_bytes_of(k);
         hipStream_t st = S(stream);
         DevBuf in(cb * n), out(cb * n);
         DWF_HIP(hipMemsetAsync(in.p, 0, in.bytes, st));
         // warm up
-        hop(op, k, 1, in.p, nullptr, out.p, PRE_K, MAT_Q, -1, 0.0, nullptr, 0, 0, nullptr, 0, 1, st);
+        hop(op, k, 1, in.p, nullptr, out.p, PRE_K, MAT_Q, -1, 0.0, nullptr, 0, 0, nullptr, 0, 1, st, 0, 1);
         hipEvent_t e0, e1;
         DWF_HIP(hipEventCreate(&e0));
         DWF_HIP(hipEventCreate(&e1));
         DWF_HIP(hipEventRecord(e0, st));
         for (int i = 0; i < nrep; ++i)
-            hop(op, k, 1, in.p, nullptr, out.p, PRE_K, MAT_Q, -1, 0.0, nullptr, 0, 0, nullptr, 0, 1, st);
+            hop(op, k, 1, in.p, nullptr, out.p, PRE_K, MAT_Q, -1, 0.0, nullptr, 0, 0, nullptr, 0, 1, st, 0, 1);
         DWF_HIP(hipEventRecord(e1, st));
         DWF_HIP(hipEventSynchronize(e1));
         float ms = 0;
@@ -284,6 +292,40 @@ int dwf_bench_hop(const dwf_op* op, int prec, int nrep, double* ms_per_launch, d
         // read every input spinor once, write every output once, read every link once
         const double w = (double)cb / 2.0;   // bytes per real
         if (bytes_per_launch) *bytes_per_launch = w * (double)Vh * (48.0 * op->Ls + 144.0);
+        return DWF_OK;
+    });
+}
+
+int dwf_bench_copy(size_t bytes, int nrep, double* ms_per_launch, void* stream) {
+    return guarded([&] {
+        DWF_REQUIRE(bytes >= 16 && nrep > 0, DWF_EINVAL, "bad argument");
+        bytes &= ~(size_t)15;
+        hipStream_t st = S(stream);
+        DevBuf a(bytes), b(bytes);
+        DWF_HIP(hipMemsetAsync(a.p, 0, bytes, st));
+        launch_copy(b.p, a.p, bytes, st);
+        hipEvent_t e0, e1;
+        DWF_HIP(hipEventCreate(&e0));
+        DWF_HIP(hipEventCreate(&e1));
+        DWF_HIP(hipEventRecord(e0, st));
+        for (int i = 0; i < nrep; ++i) launch_copy(b.p, a.p, bytes, st);
+        DWF_HIP(hipEventRecord(e1, st));
+        DWF_HIP(hipEventSynchronize(e1));
+        float ms = 0;
+        DWF_HIP(hipEventElapsedTime(&ms, e0, e1));
+        DWF_HIP(hipEventDestroy(e0));
+        DWF_HIP(hipEventDestroy(e1));
+        if (ms_per_launch) *ms_per_launch = ms / nrep;
+        return DWF_OK;
+    });
+}
+
+int dwf_residual_4d(const dwf_op* op, const void* x4, const void* b4, double tol_inner, double* rel,
+                    void* stream) {
+    return guarded([&] {
+        DWF_REQUIRE(op && x4 && b4 && rel, DWF_EINVAL, "null argument");
+        DWF_REQUIRE(op->lat->has_gauge, DWF_ESTATE, "gauge field not set");
+        *rel = residual_4d(op, x4, b4, tol_inner > 0 ? tol_inner : 1e-13, S(stream));
         return DWF_OK;
     });
 }

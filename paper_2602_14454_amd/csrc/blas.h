@@ -1,5 +1,6 @@
 // Launch interface of the vector kernels (blas.hip).  All `kind` arguments
-// are StoreKind values; n counts complex elements.
+// are StoreKind values; n counts complex elements.  Internal fields have
+// Vh sites per row and row stride Vhp (zero padding in between).
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -11,12 +12,17 @@ enum { CG_RR = 0, CG_QQ = 1, CG_ALPHA = 2, CG_BETA = 3, CG_RRNEW = 4, CG_NANFLAG
        CG_TMP = 7, CG_NSLOTS = 16 };
 
 int blas_grid(long n);
-void pack_full(int kind, void* dst, const void* src, const int* lex, long Vh, long V, long nslices, hipStream_t st);
-void unpack_full(int kind, void* dst, const void* src, const int* lex, long Vh, long V, long nslices, hipStream_t st);
-void pack_half(int kind, void* dst, const void* src, long Vh, long nslices, hipStream_t st);
-void unpack_half(int kind, void* dst, const void* src, long Vh, long nslices, hipStream_t st);
-void pack_chiral_pair_f64(void* dst, const void* b4, const int* lex, long Vh, hipStream_t st);
+void pack_full(int kind, void* dst, const void* src, const int* lex, long Vh, long Vhp, long V, long nslices,
+               hipStream_t st);
+void unpack_full(int kind, void* dst, const void* src, const int* lex, long Vh, long Vhp, long V, long nslices,
+                 hipStream_t st);
+void pack_half(int kind, void* dst, const void* src, const int* lex, long Vh, long Vhp, long nslices,
+               hipStream_t st);
+void unpack_half(int kind, void* dst, const void* src, const int* lex, long Vh, long Vhp, long nslices,
+                 hipStream_t st);
+void pack_chiral_pair_f64(void* dst, const void* b4, const int* lex, long Vh, long Vhp, hipStream_t st);
 void project_4d(void* x4, const void* x5, long V, int Ls, hipStream_t st);
+void embed_4d(void* e5, const void* y, long V, int Ls, hipStream_t st);
 void convert(int kd, int ks, void* dst, const void* src, long n, hipStream_t st);
 void norm2_partial(int kind, const void* x, long n, double* partial, hipStream_t st);
 void dot_partial(int kind, const void* x, const void* y, long n, double* partial, hipStream_t st);

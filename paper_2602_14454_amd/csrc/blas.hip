@@ -31,74 +31,79 @@ __device__ __forceinline__ double block_sum(double v, double* red) {
 // ---------------------------------------------------------------------
 // Full 5D canonical: src[((r*Ls + s)*V + lex)*12 + comp]
 template <class S>
-__global__ void pack_full_kernel(void* dst, const double2* src, const int* lex_of_eo, long Vh,
+__global__ void pack_full_kernel(void* dst, const double2* src, const int* lex_of_site, long Vh, long Vhp,
                                  long V, long nslices) {
     const long idx = (long)blockIdx.x * blockDim.x + threadIdx.x;
     if (idx >= nslices * Vh) return;
     const long rs = idx / Vh, eo = idx % Vh;
-    const long lex = lex_of_eo[eo];
+    const long lex = lex_of_site[eo];
     const double2* in = src + (rs * V + lex) * 12;
 #pragma unroll
     for (int cp = 0; cp < 12; ++cp) {
         double2 v = in[cp];
-        cstore<S>(dst, (rs * 12 + cp) * Vh + eo, (typename Traits<S>::R)v.x, (typename Traits<S>::R)v.y);
+        cstore<S>(dst, (rs * 12 + cp) * Vhp + eo, (typename Traits<S>::R)v.x, (typename Traits<S>::R)v.y);
     }
 }
 
 template <class S>
-__global__ void unpack_full_kernel(double2* dst, const void* src, const int* lex_of_eo, long Vh,
+__global__ void unpack_full_kernel(double2* dst, const void* src, const int* lex_of_site, long Vh, long Vhp,
                                    long V, long nslices) {
     const long idx = (long)blockIdx.x * blockDim.x + threadIdx.x;
     if (idx >= nslices * Vh) return;
     const long rs = idx / Vh, eo = idx % Vh;
-    const long lex = lex_of_eo[eo];
+    const long lex = lex_of_site[eo];
     double2* out = dst + (rs * V + lex) * 12;
 #pragma unroll
     for (int cp = 0; cp < 12; ++cp) {
         typename Traits<S>::R re, im;
-        cload<S>(src, (rs * 12 + cp) * Vh + eo, re, im);
+        cload<S>(src, (rs * 12 + cp) * Vhp + eo, re, im);
         out[cp] = make_double2((double)re, (double)im);
     }
 }
 
-// Even canonical: src[((r*Ls + s)*Vh + eo)*12 + comp]
+// Even canonical: src[((r*Ls + s)*Vh + eo)*12 + comp], eo = lex >> 1;
+// internal site i holds lex_of_site[i].
 template <class S>
-__global__ void pack_half_kernel(void* dst, const double2* src, long Vh, long nslices) {
+__global__ void pack_half_kernel(void* dst, const double2* src, const int* lex_of_site, long Vh, long Vhp,
+                                 long nslices) {
     const long idx = (long)blockIdx.x * blockDim.x + threadIdx.x;
     if (idx >= nslices * Vh) return;
-    const long rs = idx / Vh, eo = idx % Vh;
+    const long rs = idx / Vh, i = idx % Vh;
+    const long eo = lex_of_site[i] >> 1;
 #pragma unroll
     for (int cp = 0; cp < 12; ++cp) {
         double2 v = src[(rs * Vh + eo) * 12 + cp];
-        cstore<S>(dst, (rs * 12 + cp) * Vh + eo, (typename Traits<S>::R)v.x, (typename Traits<S>::R)v.y);
+        cstore<S>(dst, (rs * 12 + cp) * Vhp + i, (typename Traits<S>::R)v.x, (typename Traits<S>::R)v.y);
     }
 }
 
 template <class S>
-__global__ void unpack_half_kernel(double2* dst, const void* src, long Vh, long nslices) {
+__global__ void unpack_half_kernel(double2* dst, const void* src, const int* lex_of_site, long Vh, long Vhp,
+                                   long nslices) {
     const long idx = (long)blockIdx.x * blockDim.x + threadIdx.x;
     if (idx >= nslices * Vh) return;
-    const long rs = idx / Vh, eo = idx % Vh;
+    const long rs = idx / Vh, i = idx % Vh;
+    const long eo = lex_of_site[i] >> 1;
 #pragma unroll
     for (int cp = 0; cp < 12; ++cp) {
         typename Traits<S>::R re, im;
-        cload<S>(src, (rs * 12 + cp) * Vh + eo, re, im);
+        cload<S>(src, (rs * 12 + cp) * Vhp + i, re, im);
         dst[(rs * Vh + eo) * 12 + cp] = make_double2((double)re, (double)im);
     }
 }
 
 // 4D canonical -> two-slice half field of one parity: slice 0 = P+ b4, slice 1 = P- b4
 template <class S>
-__global__ void pack_chiral_pair_kernel(void* dst, const double2* b4, const int* lex_of_eo, long Vh) {
+__global__ void pack_chiral_pair_kernel(void* dst, const double2* b4, const int* lex_of_site, long Vh, long Vhp) {
     const long eo = (long)blockIdx.x * blockDim.x + threadIdx.x;
     if (eo >= Vh) return;
-    const long lex = lex_of_eo[eo];
+    const long lex = lex_of_site[eo];
 #pragma unroll
     for (int cp = 0; cp < 12; ++cp) {
         double2 v = b4[lex * 12 + cp];
         const bool up = cp < 6;
-        cstore<S>(dst, ((long)0 * 12 + cp) * Vh + eo, up ? v.x : 0.0, up ? v.y : 0.0);
-        cstore<S>(dst, ((long)1 * 12 + cp) * Vh + eo, up ? 0.0 : v.x, up ? 0.0 : v.y);
+        cstore<S>(dst, ((long)0 * 12 + cp) * Vhp + eo, up ? v.x : 0.0, up ? v.y : 0.0);
+        cstore<S>(dst, ((long)1 * 12 + cp) * Vhp + eo, up ? 0.0 : v.x, up ? 0.0 : v.y);
     }
 }
 
@@ -110,6 +115,21 @@ __global__ void project4d_kernel(double2* x4, const double2* x5, long V, int Ls)
     for (int cp = 0; cp < 12; ++cp) {
         const bool up = cp < 6;   // P_+ components come from s = Ls-1, P_- from s = 0
         x4[lex * 12 + cp] = up ? x5[((long)(Ls - 1) * V + lex) * 12 + cp] : x5[lex * 12 + cp];
+    }
+}
+
+// e5 = P (y, 0, ..., 0): the first block column of the paper's projector
+// matrix, (P_- y at s = 0, P_+ y at s = Ls-1, zero elsewhere); canonical.
+__global__ void embed4d_kernel(double2* e5, const double2* y, long V, int Ls) {
+    const long idx = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (idx >= (long)Ls * V) return;
+    const int s = (int)(idx / V);
+    const long lex = idx % V;
+#pragma unroll
+    for (int cp = 0; cp < 12; ++cp) {
+        const bool up = cp < 6;
+        const bool keep = (s == 0 && !up) || (s == Ls - 1 && up);
+        e5[idx * 12 + cp] = keep ? y[lex * 12 + cp] : make_double2(0.0, 0.0);
     }
 }
 
@@ -273,54 +293,64 @@ int blas_grid(long n) {
     }
 
 template <class S>
-static void pack_full_t(void* dst, const void* src, const int* lex, long Vh, long V, long ns, hipStream_t st) {
+static void pack_full_t(void* dst, const void* src, const int* lex, long Vh, long Vhp, long V, long ns,
+                        hipStream_t st) {
     hipLaunchKernelGGL(pack_full_kernel<S>, dim3(blocks_for(ns * Vh, 256)), dim3(256), 0, st, dst,
-                       (const double2*)src, lex, Vh, V, ns);
+                       (const double2*)src, lex, Vh, Vhp, V, ns);
 }
-void pack_full(int kind, void* dst, const void* src, const int* lex, long Vh, long V, long ns, hipStream_t st) {
-    DISPATCH1(kind, pack_full_t, dst, src, lex, Vh, V, ns, st);
+void pack_full(int kind, void* dst, const void* src, const int* lex, long Vh, long Vhp, long V, long ns,
+               hipStream_t st) {
+    DISPATCH1(kind, pack_full_t, dst, src, lex, Vh, Vhp, V, ns, st);
     DWF_HIP(hipGetLastError());
 }
 
 template <class S>
-static void unpack_full_t(void* dst, const void* src, const int* lex, long Vh, long V, long ns, hipStream_t st) {
+static void unpack_full_t(void* dst, const void* src, const int* lex, long Vh, long Vhp, long V, long ns,
+                          hipStream_t st) {
     hipLaunchKernelGGL(unpack_full_kernel<S>, dim3(blocks_for(ns * Vh, 256)), dim3(256), 0, st,
-                       (double2*)dst, src, lex, Vh, V, ns);
+                       (double2*)dst, src, lex, Vh, Vhp, V, ns);
 }
-void unpack_full(int kind, void* dst, const void* src, const int* lex, long Vh, long V, long ns, hipStream_t st) {
-    DISPATCH1(kind, unpack_full_t, dst, src, lex, Vh, V, ns, st);
+void unpack_full(int kind, void* dst, const void* src, const int* lex, long Vh, long Vhp, long V, long ns,
+                 hipStream_t st) {
+    DISPATCH1(kind, unpack_full_t, dst, src, lex, Vh, Vhp, V, ns, st);
     DWF_HIP(hipGetLastError());
 }
 
 template <class S>
-static void pack_half_t(void* dst, const void* src, long Vh, long ns, hipStream_t st) {
+static void pack_half_t(void* dst, const void* src, const int* lex, long Vh, long Vhp, long ns, hipStream_t st) {
     hipLaunchKernelGGL(pack_half_kernel<S>, dim3(blocks_for(ns * Vh, 256)), dim3(256), 0, st, dst,
-                       (const double2*)src, Vh, ns);
+                       (const double2*)src, lex, Vh, Vhp, ns);
 }
-void pack_half(int kind, void* dst, const void* src, long Vh, long ns, hipStream_t st) {
-    DISPATCH1(kind, pack_half_t, dst, src, Vh, ns, st);
+void pack_half(int kind, void* dst, const void* src, const int* lex, long Vh, long Vhp, long ns, hipStream_t st) {
+    DISPATCH1(kind, pack_half_t, dst, src, lex, Vh, Vhp, ns, st);
     DWF_HIP(hipGetLastError());
 }
 
 template <class S>
-static void unpack_half_t(void* dst, const void* src, long Vh, long ns, hipStream_t st) {
+static void unpack_half_t(void* dst, const void* src, const int* lex, long Vh, long Vhp, long ns, hipStream_t st) {
     hipLaunchKernelGGL(unpack_half_kernel<S>, dim3(blocks_for(ns * Vh, 256)), dim3(256), 0, st,
-                       (double2*)dst, src, Vh, ns);
+                       (double2*)dst, src, lex, Vh, Vhp, ns);
 }
-void unpack_half(int kind, void* dst, const void* src, long Vh, long ns, hipStream_t st) {
-    DISPATCH1(kind, unpack_half_t, dst, src, Vh, ns, st);
+void unpack_half(int kind, void* dst, const void* src, const int* lex, long Vh, long Vhp, long ns, hipStream_t st) {
+    DISPATCH1(kind, unpack_half_t, dst, src, lex, Vh, Vhp, ns, st);
     DWF_HIP(hipGetLastError());
 }
 
-void pack_chiral_pair_f64(void* dst, const void* b4, const int* lex, long Vh, hipStream_t st) {
+void pack_chiral_pair_f64(void* dst, const void* b4, const int* lex, long Vh, long Vhp, hipStream_t st) {
     hipLaunchKernelGGL(pack_chiral_pair_kernel<double>, dim3(blocks_for(Vh, 256)), dim3(256), 0, st, dst,
-                       (const double2*)b4, lex, Vh);
+                       (const double2*)b4, lex, Vh, Vhp);
     DWF_HIP(hipGetLastError());
 }
 
 void project_4d(void* x4, const void* x5, long V, int Ls, hipStream_t st) {
     hipLaunchKernelGGL(project4d_kernel, dim3(blocks_for(V, 256)), dim3(256), 0, st, (double2*)x4,
                        (const double2*)x5, V, Ls);
+    DWF_HIP(hipGetLastError());
+}
+
+void embed_4d(void* e5, const void* y, long V, int Ls, hipStream_t st) {
+    hipLaunchKernelGGL(embed4d_kernel, dim3(blocks_for((long)Ls * V, 256)), dim3(256), 0, st, (double2*)e5,
+                       (const double2*)y, V, Ls);
     DWF_HIP(hipGetLastError());
 }
 

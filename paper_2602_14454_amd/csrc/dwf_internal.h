@@ -1,15 +1,20 @@
 // Internal declarations of libdwf (host and device).
 //
 // Internal field layout ("half field"): for one parity, one right-hand side,
-//   elem[(s*12 + comp)*Vh + site], comp = spin*3 + colour, site = eo index,
+//   elem[(s*12 + comp)*Vhp + site], comp = spin*3 + colour, site = internal
+// site index of that parity (see build_geometry: spatial bricks of about
+// 8^3, swept in t; lex_of_site gives the lexicographic site),
 // complex stored as (re, im) pairs of the storage type.  Multi-RHS fields put
-// the RHS index outermost: elem[((r*Ls + s)*12 + comp)*Vh + site].
+// the RHS index outermost: elem[((r*Ls + s)*12 + comp)*Vhp + site].
+// Vhp >= Vh is the padded row stride (32 times an odd number): with a
+// power-of-two stride every row of a site falls into the same L2 set and
+// the hop thrashes the cache by conflict.  Padding entries stay zero.
 //
 // Links per output parity p ("hop links"):
-//   link[((p*8 + d)*9 + row*3 + col)*Vh + site],
+//   link[((p*8 + d)*9 + row*3 + col)*Vhp + site],
 //   d = 0..3: U_mu(x) (forward hop to x+mu), d = 4..7: U_mu(x-mu)^dag,
 // with the antiperiodic time phase folded in.
-// Neighbours: nbr[(p*8 + d)*Vh + site] = eo index (other parity) of x+mu
+// Neighbours: nbr[(p*8 + d)*Vhp + site] = internal index (other parity) of x+mu
 // (d < 4) or x-mu (d >= 4).
 #pragma once
 
@@ -70,6 +75,9 @@ struct DevBuf {
             throw Error{DWF_ENOMEM, "hipMalloc(" + std::to_string(n) + " bytes) failed"};
         }
         bytes = n;
+        // fields keep zero padding beyond the last site of every row
+        e = hipMemset(p, 0, n);
+        if (e != hipSuccess) throw Error{DWF_EHIP, "hipMemset failed"};
     }
     void release() {
         if (p) (void)hipFree(p);
@@ -101,11 +109,12 @@ enum StoreKind { ST_F64 = 0, ST_F32 = 1, ST_BF16 = 2 };
 struct dwf_lattice {
     int dims[4];
     int antiperiodic_t;
-    long V, Vh;
-    std::vector<int> lex_of_eo;   // host [2][Vh]
+    long V, Vh, Vhp;   // sites, sites per parity, padded row stride
+    int brick[3] = {0, 0, 0};       // spatial brick extents of the internal site order
+    std::vector<int> lex_of_site;   // host [2][Vh]: lexicographic index of internal site
     std::vector<int> nbr_host;    // host [2][8][Vh]
     dwf::DevBuf nbr;              // device [2][8][Vh]
-    dwf::DevBuf lex_of_eo_dev;    // device [2][Vh]
+    dwf::DevBuf lex_of_site_dev;    // device [2][Vh]
     dwf::DevBuf links[3];         // per storage kind: [2][8][9][Vh] complex
     bool has_gauge = false;
 };

@@ -20,7 +20,8 @@ struct HopParams {
     const void* post2;     // dense POST2 (required with out2)
     const void* locmix2;   // dense LOCMIX2 (required with out2 and loc)
     double* partial;       // per-block FP64 partial norms (nullptr: none)
-    long Vh;
+    long Vh;               // sites of the output parity
+    long Vhp;              // padded row stride of fields, links and neighbour table
     int Ls;
     int pre_mode;          // 0 identity, 1 diagonal d, 2 d + e (K sparsity)
     int reduce;            // 1: |out|^2, 2: |out2|^2
@@ -33,11 +34,13 @@ struct MixParams {
     const void* mat;       // dense [2][16][16] compute type
     double* partial;
     long Vh;
+    long Vhp;
     int Ls;
 };
 
 int hop_grid_blocks(long Vh);
-void launch_hop(int kind, const HopParams& P, int nrhs, hipStream_t st);
+void launch_hop(int kind, const HopParams& P, int nrhs, hipStream_t st, int bench_tag = 0);
+void launch_copy(void* dst, const void* src, size_t bytes, hipStream_t st);
 void launch_mix(int kind, const MixParams& P, int nrhs, hipStream_t st);
 
 }  // namespace dwf

@@ -31,6 +31,29 @@
 
 namespace dwf {
 
+// Tuning knobs (compile time): occupancy target per precision, 4-slice
+// groups per wave in the hop phase (KPW: each link load then serves 2 slices),
+// unrolling of the direction loop, and whether the 8 neighbour indices are
+// loaded up front.  Defaults are the best of a sweep on MI355X (FP32 hop,
+// 16^3x32 and 24^3x48, Ls = 16).
+#ifndef DWF_HOP_WAVES_PER_EU
+#define DWF_HOP_WAVES_PER_EU 3
+#endif
+#ifndef DWF_HOP_WAVES_PER_EU64
+#define DWF_HOP_WAVES_PER_EU64 2
+#endif
+#ifndef DWF_HOP_UNROLL
+#define DWF_HOP_UNROLL 8
+#endif
+#ifndef DWF_HOP_KPW
+#define DWF_HOP_KPW 2
+#endif
+#ifndef DWF_HOP_KPW64
+#define DWF_HOP_KPW64 1
+#endif
+#ifndef DWF_HOP_NBR_PRELOAD
+#define DWF_HOP_NBR_PRELOAD 1
+#endif
 typedef float v4f __attribute__((ext_vector_type(4)));
 typedef double v4d __attribute__((ext_vector_type(4)));
 
@@ -54,6 +77,15 @@ template <class R>
 __device__ __forceinline__ int out_row(int sc, int i) {
     if constexpr (sizeof(R) == 8) return sc + 4 * i;
     else return 4 * sc + i;
+}
+
+// Workgroups are dealt to the 8 XCDs round-robin (workgroup b runs on XCD
+// b % 8), and each XCD has its own L2.  Remap so that XCD x sweeps one
+// contiguous range of logical blocks: the y/z/t neighbours a block reads
+// were then mostly fetched by the same XCD a few blocks earlier.
+__device__ __forceinline__ int xcd_block(int b, int nb) {
+    const int x = b & 7, j = b >> 3, q = nb >> 3, r = nb & 7;
+    return x * q + min(x, r) + j;
 }
 
 // ---------------------------------------------------------------------
@@ -129,122 +161,179 @@ __device__ __forceinline__ void hop_dir(const R* __restrict__ U, const R* __rest
     }
 }
 
-template <class S, int KK, int D>
-__device__ __forceinline__ void hop_direction(const HopParams& P, long sx, long roff, int sc,
-                                              const typename Traits<S>::R (&pd)[KK][2],
-                                              const typename Traits<S>::R (&pe)[KK][2],
-                                              typename Traits<S>::R (&h)[KK][24]) {
+// Buffer descriptors of one hop launch (wave-uniform, scalar registers).
+struct HopRes {
+    __amdgpu_buffer_rsrc_t in, loc, out, out2, links, nbr;
+};
+
+template <class S, int G>
+__device__ __forceinline__ void hop_direction(const HopParams& P, const HopRes& R_, unsigned rowb, unsigned sx,
+                                              int D, unsigned ynb, const int (&s)[G],
+                                              const typename Traits<S>::R (&pd)[G][2],
+                                              const typename Traits<S>::R (&pe)[G][2],
+                                              typename Traits<S>::R (&h)[G][24]) {
     using R = typename Traits<S>::R;
-    const long Vh = P.Vh;
+    constexpr unsigned CB = cbytes<S>();
     const int Ls = P.Ls;
-    const long y = P.nbr[(long)D * Vh + sx];
+    const unsigned Vh = rowb / CB;
+    const unsigned y = DWF_HOP_NBR_PRELOAD ? ynb
+                                           : __builtin_amdgcn_raw_buffer_load_b32(R_.nbr, sx * 4u, (unsigned)D * Vh * 4u, 0);
     R U[18];
 #pragma unroll
-    for (int e = 0; e < 9; ++e) cload<S>(P.links, ((long)D * 9 + e) * Vh + sx, U[2 * e], U[2 * e + 1]);
+    for (int e = 0; e < 9; ++e) bload<S>(R_.links, sx * CB, (unsigned)(D * 9 + e) * rowb, U[2 * e], U[2 * e + 1]);
+    const unsigned yb = y * CB;
 #pragma unroll
-    for (int kk = 0; kk < KK; ++kk) {
-        const int s = sc + 4 * kk;
-        if (s >= Ls) continue;
+    for (int g = 0; g < G; ++g) {
+        if (s[g] >= Ls) continue;
         R p[24];
+        const unsigned sb = (unsigned)s[g] * 12u * rowb + yb;
 #pragma unroll
-        for (int cp = 0; cp < 12; ++cp)
-            cload<S>(P.in, roff + ((long)s * 12 + cp) * Vh + y, p[2 * cp], p[2 * cp + 1]);
+        for (int cp = 0; cp < 12; ++cp) bload<S>(R_.in, sb, (unsigned)cp * rowb, p[2 * cp], p[2 * cp + 1]);
         if (P.pre_mode >= 1) {
 #pragma unroll
-            for (int k = 0; k < 12; ++k) p[k] *= pd[kk][0];
+            for (int k = 0; k < 12; ++k) p[k] *= pd[g][0];
 #pragma unroll
-            for (int k = 12; k < 24; ++k) p[k] *= pd[kk][1];
+            for (int k = 12; k < 24; ++k) p[k] *= pd[g][1];
         }
         if (P.pre_mode == 2) {
             // K pattern: upper chirality couples s-1, lower chirality s+1 (cyclic)
-            const int sm = s == 0 ? Ls - 1 : s - 1;
-            const int sp = s == Ls - 1 ? 0 : s + 1;
+            const unsigned sm = (unsigned)(s[g] == 0 ? Ls - 1 : s[g] - 1) * 12u * rowb + yb;
+            const unsigned sp = (unsigned)(s[g] == Ls - 1 ? 0 : s[g] + 1) * 12u * rowb + yb;
 #pragma unroll
             for (int cp = 0; cp < 6; ++cp) {
                 R re, im;
-                cload<S>(P.in, roff + ((long)sm * 12 + cp) * Vh + y, re, im);
-                p[2 * cp] += pe[kk][0] * re;
-                p[2 * cp + 1] += pe[kk][0] * im;
+                bload<S>(R_.in, sm, (unsigned)cp * rowb, re, im);
+                p[2 * cp] += pe[g][0] * re;
+                p[2 * cp + 1] += pe[g][0] * im;
             }
 #pragma unroll
             for (int cp = 6; cp < 12; ++cp) {
                 R re, im;
-                cload<S>(P.in, roff + ((long)sp * 12 + cp) * Vh + y, re, im);
-                p[2 * cp] += pe[kk][1] * re;
-                p[2 * cp + 1] += pe[kk][1] * im;
+                bload<S>(R_.in, sp, (unsigned)cp * rowb, re, im);
+                p[2 * cp] += pe[g][1] * re;
+                p[2 * cp + 1] += pe[g][1] * im;
             }
         }
-        constexpr int MU = D & 3;
-        constexpr int SG = D < 4 ? -1 : +1;
-        hop_dir<MU, SG, R>(U, p, h[kk]);
+        switch (D) {   // wave-uniform
+            case 0: hop_dir<0, -1, R>(U, p, h[g]); break;
+            case 1: hop_dir<1, -1, R>(U, p, h[g]); break;
+            case 2: hop_dir<2, -1, R>(U, p, h[g]); break;
+            case 3: hop_dir<3, -1, R>(U, p, h[g]); break;
+            case 4: hop_dir<0, +1, R>(U, p, h[g]); break;
+            case 5: hop_dir<1, +1, R>(U, p, h[g]); break;
+            case 6: hop_dir<2, +1, R>(U, p, h[g]); break;
+            default: hop_dir<3, +1, R>(U, p, h[g]); break;
+        }
     }
 }
 
-template <class S, int KK>
-__global__ __launch_bounds__(256) void hop_mfma_kernel(HopParams P) {
+// Number of 4-slice groups each wave computes in the hop phase, and waves
+// per block, for KK = ceil(Ls/4) groups.
+__host__ __device__ constexpr int hop_kpw(int KK, bool f64) {
+    return f64 ? (KK % DWF_HOP_KPW64 == 0 ? DWF_HOP_KPW64 : 1) : (KK % DWF_HOP_KPW == 0 ? DWF_HOP_KPW : 1);
+}
+__host__ __device__ constexpr int hop_waves(int KK, bool f64) { return KK / hop_kpw(KK, f64); }
+
+// Block = KK waves = 16 sites x all s (KK = ceil(Ls/4)).
+//  phase 1: wave w computes the hop for s = 4w + sc at site j of the block
+//           (lane = 16 sc + j) and stores it to LDS as hs[w][real r][lane];
+//           that is exactly the MFMA B operand for k-step w.
+//  phase 2: wave w takes 12/KK of the 12 spin-colour components; for each it
+//           runs the dense s-mixes as KK MFMAs per real part with B read back
+//           from LDS, adds the local term and stores.
+// Keeping one 4-slice group per wave (instead of all Ls slices) keeps the
+// data a wave touches, and its registers, four times smaller; that lets an
+// XCD's 4 MB L2 hold the neighbour reuse window.
+// TAG only renames the symbol: TAG = 1 is the instance launched by the
+// stand-alone hop benchmark, so profilers report it apart from the solver's.
+template <class S, int KK, int TAG = 0>
+__global__ __launch_bounds__(256)
+__attribute__((amdgpu_waves_per_eu(sizeof(S) == 8 ? DWF_HOP_WAVES_PER_EU64 : DWF_HOP_WAVES_PER_EU)))
+void hop_mfma_kernel(HopParams P) {
     using R = typename Traits<S>::R;
     using V = typename Vec4<R>::T;
+    __shared__ R hs[KK][24][64];
+    __shared__ double red[4];
     const int lane = threadIdx.x & 63;
+    const int w = threadIdx.x >> 6;
     const int j = lane & 15, sc = lane >> 4;
     const long Vh = P.Vh;
     const int Ls = P.Ls;
-    const long site = ((long)blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6)) * 16 + j;
+    const long site = (long)xcd_block(blockIdx.x, gridDim.x) * 16 + j;
     const bool valid = site < Vh;
     const long sx = valid ? site : Vh - 1;
-    const long roff = (long)blockIdx.y * Ls * 12 * Vh;
+    constexpr unsigned CB = cbytes<S>();
+    const unsigned rowb = (unsigned)P.Vhp * CB;                // bytes of one (s, comp) row
+    const unsigned fieldb = (unsigned)Ls * 12u * rowb;         // bytes of one right-hand side
+    const size_t rhsb = (size_t)blockIdx.y * fieldb;           // bytes of the preceding RHS
+    const unsigned sxb = (unsigned)sx * CB;
+    HopRes R_;
+    R_.in = make_rsrc(static_cast<const char*>(P.in) + rhsb, fieldb);
+    R_.loc = make_rsrc(P.loc ? static_cast<const char*>(P.loc) + rhsb : nullptr, P.loc ? fieldb : 0u);
+    R_.out = make_rsrc(P.out ? static_cast<const char*>(P.out) + rhsb : nullptr, P.out ? fieldb : 0u);
+    R_.out2 = make_rsrc(P.out2 ? static_cast<const char*>(P.out2) + rhsb : nullptr, P.out2 ? fieldb : 0u);
+    R_.links = make_rsrc(P.links, 72u * rowb);
+    R_.nbr = make_rsrc(P.nbr, 8u * (unsigned)P.Vhp * 4u);
 
-    // sparse pre-mix coefficients for this lane's slices
-    R pd[KK][2], pe[KK][2];
-    const R* pre = static_cast<const R*>(P.pre);
+    {
+        constexpr int G = hop_kpw(KK, sizeof(S) == 8);
+        R h[G][24];
+        int sg[G];
+        R pd[G][2], pe[G][2];
+        const R* pre = static_cast<const R*>(P.pre);
 #pragma unroll
-    for (int kk = 0; kk < KK; ++kk) {
-        const int s = min(sc + 4 * kk, LS_MAX - 1);
-        pd[kk][0] = pre ? pre[0 * 16 + s] : R(1);
-        pd[kk][1] = pre ? pre[1 * 16 + s] : R(1);
-        pe[kk][0] = pre ? pre[2 * 16 + s] : R(0);
-        pe[kk][1] = pre ? pre[3 * 16 + s] : R(0);
+        for (int g = 0; g < G; ++g) {
+            sg[g] = 4 * (w * G + g) + sc;
+            const int sc_ = min(sg[g], LS_MAX - 1);
+            pd[g][0] = pre ? pre[0 * 16 + sc_] : R(1);
+            pd[g][1] = pre ? pre[1 * 16 + sc_] : R(1);
+            pe[g][0] = pre ? pre[2 * 16 + sc_] : R(0);
+            pe[g][1] = pre ? pre[3 * 16 + sc_] : R(0);
+#pragma unroll
+            for (int k = 0; k < 24; ++k) h[g][k] = 0;
+        }
+        // Loop over the 8 hop directions.  Its unrolling (DWF_HOP_UNROLL)
+        // trades registers for loads in flight: with 1, nothing of direction
+        // d+1 (its links in particular) is hoisted above direction d.
+        unsigned ynb[8];
+#pragma unroll
+        for (int d = 0; d < 8; ++d)
+            ynb[d] = DWF_HOP_NBR_PRELOAD
+                         ? __builtin_amdgcn_raw_buffer_load_b32(R_.nbr, (unsigned)sx * 4u, (unsigned)d * (unsigned)P.Vhp * 4u, 0)
+                         : 0u;
+#pragma unroll DWF_HOP_UNROLL
+        for (int d = 0; d < 8; ++d) hop_direction<S, G>(P, R_, rowb, (unsigned)sx, d, ynb[d], sg, pd, pe, h);
+#pragma unroll
+        for (int g = 0; g < G; ++g)
+#pragma unroll
+            for (int k = 0; k < 24; ++k) hs[w * G + g][k][lane] = h[g][k];
     }
-
-    R h[KK][24];
-#pragma unroll
-    for (int kk = 0; kk < KK; ++kk)
-#pragma unroll
-        for (int k = 0; k < 24; ++k) h[kk][k] = 0;
-
-    hop_direction<S, KK, 0>(P, sx, roff, sc, pd, pe, h);
-    hop_direction<S, KK, 1>(P, sx, roff, sc, pd, pe, h);
-    hop_direction<S, KK, 2>(P, sx, roff, sc, pd, pe, h);
-    hop_direction<S, KK, 3>(P, sx, roff, sc, pd, pe, h);
-    hop_direction<S, KK, 4>(P, sx, roff, sc, pd, pe, h);
-    hop_direction<S, KK, 5>(P, sx, roff, sc, pd, pe, h);
-    hop_direction<S, KK, 6>(P, sx, roff, sc, pd, pe, h);
-    hop_direction<S, KK, 7>(P, sx, roff, sc, pd, pe, h);
+    __syncthreads();
 
     // A operands: A[m][k] = MAT[chi][row m = j][col 4*kk + sc]
     const R* post = static_cast<const R*>(P.post);
     const R* lmix = static_cast<const R*>(P.locmix);
     const R* post2 = static_cast<const R*>(P.post2);
     const R* lmix2 = static_cast<const R*>(P.locmix2);
-    R ap[2][KK], al[2][KK], ap2[2][KK], al2[2][KK];
-#pragma unroll
-    for (int chi = 0; chi < 2; ++chi)
-#pragma unroll
-        for (int kk = 0; kk < KK; ++kk) {
-            const int idx = (chi * 16 + j) * 16 + 4 * kk + sc;
-            ap[chi][kk] = post[idx];
-            al[chi][kk] = lmix ? lmix[idx] : R(0);
-            ap2[chi][kk] = post2 ? post2[idx] : R(0);
-            al2[chi][kk] = lmix2 ? lmix2[idx] : R(0);
-        }
     const bool has_loc = P.loc != nullptr;
     const bool dense_loc = has_loc && lmix != nullptr;
     const bool has_out2 = P.out2 != nullptr;
     const R lscale = R(P.loc_scale);
+    constexpr int CPW = 12 / hop_waves(KK, sizeof(S) == 8);
 
     double nrm = 0.0;
+    for (int q = 0; q < CPW; ++q) {
+        const int cp = w * CPW + q;
+        const int chi = cp >= 6 ? 1 : 0;
+        R ap[KK], al[KK], ap2[KK], al2[KK];
 #pragma unroll
-    for (int cp = 0; cp < 12; ++cp) {
-        const int chi = cp / 6;
+        for (int kk = 0; kk < KK; ++kk) {
+            const int idx = (chi * 16 + j) * 16 + 4 * kk + sc;
+            ap[kk] = post[idx];
+            al[kk] = dense_loc ? lmix[idx] : R(0);
+            ap2[kk] = has_out2 ? post2[idx] : R(0);
+            al2[kk] = (has_out2 && has_loc) ? lmix2[idx] : R(0);
+        }
         // B-layout local values (needed by dense loc mixes)
         R lr[KK], li[KK];
 #pragma unroll
@@ -253,20 +342,20 @@ __global__ __launch_bounds__(256) void hop_mfma_kernel(HopParams P) {
 #pragma unroll
             for (int kk = 0; kk < KK; ++kk) {
                 const int s = sc + 4 * kk;
-                if (s < Ls) cload<S>(P.loc, roff + ((long)s * 12 + cp) * Vh + sx, lr[kk], li[kk]);
+                if (s < Ls) bload<S>(R_.loc, sxb, ((unsigned)s * 12u + cp) * rowb, lr[kk], li[kk]);
             }
         }
         V cr = {0, 0, 0, 0}, ci = {0, 0, 0, 0};
 #pragma unroll
         for (int kk = 0; kk < KK; ++kk) {
-            cr = mfma4(ap[chi][kk], h[kk][2 * cp], cr);
-            ci = mfma4(ap[chi][kk], h[kk][2 * cp + 1], ci);
+            cr = mfma4(ap[kk], hs[kk][2 * cp][lane], cr);
+            ci = mfma4(ap[kk], hs[kk][2 * cp + 1][lane], ci);
         }
         if (dense_loc) {
 #pragma unroll
             for (int kk = 0; kk < KK; ++kk) {
-                cr = mfma4(al[chi][kk], lr[kk], cr);
-                ci = mfma4(al[chi][kk], li[kk], ci);
+                cr = mfma4(al[kk], lr[kk], cr);
+                ci = mfma4(al[kk], li[kk], ci);
             }
         }
 #pragma unroll
@@ -275,12 +364,12 @@ __global__ __launch_bounds__(256) void hop_mfma_kernel(HopParams P) {
             R orr = cr[i], oi = ci[i];
             if (has_loc && !dense_loc && s < Ls) {
                 R xr, xi;
-                cload<S>(P.loc, roff + ((long)s * 12 + cp) * Vh + sx, xr, xi);
+                bload<S>(R_.loc, sxb, ((unsigned)s * 12u + cp) * rowb, xr, xi);
                 orr += lscale * xr;
                 oi += lscale * xi;
             }
             if (valid && s < Ls) {
-                if (P.out) cstore<S>(P.out, roff + ((long)s * 12 + cp) * Vh + site, orr, oi);
+                if (P.out) bstore<S>(R_.out, sxb, ((unsigned)s * 12u + cp) * rowb, orr, oi);
                 if (P.reduce == 1) nrm += double(orr) * double(orr) + double(oi) * double(oi);
             }
         }
@@ -288,21 +377,21 @@ __global__ __launch_bounds__(256) void hop_mfma_kernel(HopParams P) {
             V dr = {0, 0, 0, 0}, di = {0, 0, 0, 0};
 #pragma unroll
             for (int kk = 0; kk < KK; ++kk) {
-                dr = mfma4(ap2[chi][kk], h[kk][2 * cp], dr);
-                di = mfma4(ap2[chi][kk], h[kk][2 * cp + 1], di);
+                dr = mfma4(ap2[kk], hs[kk][2 * cp][lane], dr);
+                di = mfma4(ap2[kk], hs[kk][2 * cp + 1][lane], di);
             }
             if (has_loc) {
 #pragma unroll
                 for (int kk = 0; kk < KK; ++kk) {
-                    dr = mfma4(al2[chi][kk], lr[kk], dr);
-                    di = mfma4(al2[chi][kk], li[kk], di);
+                    dr = mfma4(al2[kk], lr[kk], dr);
+                    di = mfma4(al2[kk], li[kk], di);
                 }
             }
 #pragma unroll
             for (int i = 0; i < 4; ++i) {
                 const int s = out_row<R>(sc, i);
                 if (valid && s < Ls) {
-                    cstore<S>(P.out2, roff + ((long)s * 12 + cp) * Vh + site, dr[i], di[i]);
+                    bstore<S>(R_.out2, sxb, ((unsigned)s * 12u + cp) * rowb, dr[i], di[i]);
                     if (P.reduce == 2) nrm += double(dr[i]) * double(dr[i]) + double(di[i]) * double(di[i]);
                 }
             }
@@ -312,12 +401,11 @@ __global__ __launch_bounds__(256) void hop_mfma_kernel(HopParams P) {
     if (P.partial) {
 #pragma unroll
         for (int off = 32; off >= 1; off >>= 1) nrm += __shfl_xor(nrm, off, 64);
-        __shared__ double red[4];
-        if (lane == 0) red[threadIdx.x >> 6] = nrm;
+        if (lane == 0) red[w] = nrm;
         __syncthreads();
         if (threadIdx.x == 0) {
             double t = 0.0;
-            for (int w = 0; w < (int)(blockDim.x >> 6); ++w) t += red[w];
+            for (int ww = 0; ww < hop_waves(KK, sizeof(S) == 8); ++ww) t += red[ww];
             P.partial[(long)blockIdx.y * gridDim.x + blockIdx.x] = t;
         }
     }
@@ -338,7 +426,8 @@ __global__ __launch_bounds__(256) void mix_mfma_kernel(MixParams P) {
     const long site = ((long)blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6)) * 16 + j;
     const bool valid = site < Vh;
     const long sx = valid ? site : Vh - 1;
-    const long roff = (long)blockIdx.y * Ls * 12 * Vh;
+    const long Vhp = P.Vhp;
+    const long roff = (long)blockIdx.y * Ls * 12 * Vhp;
     const R* A = static_cast<const R*>(P.mat);
     R a[2][KK];
 #pragma unroll
@@ -354,7 +443,7 @@ __global__ __launch_bounds__(256) void mix_mfma_kernel(MixParams P) {
         for (int kk = 0; kk < KK; ++kk) {
             const int s = sc + 4 * kk;
             R xr = 0, xi = 0;
-            if (s < Ls) cload<S>(P.in, roff + ((long)s * 12 + cp) * Vh + sx, xr, xi);
+            if (s < Ls) cload<S>(P.in, roff + ((long)s * 12 + cp) * Vhp + sx, xr, xi);
             cr = mfma4(a[chi][kk], xr, cr);
             ci = mfma4(a[chi][kk], xi, ci);
         }
@@ -362,7 +451,7 @@ __global__ __launch_bounds__(256) void mix_mfma_kernel(MixParams P) {
         for (int i = 0; i < 4; ++i) {
             const int s = out_row<R>(sc, i);
             if (valid && s < Ls) {
-                cstore<S>(P.out, roff + ((long)s * 12 + cp) * Vh + site, cr[i], ci[i]);
+                cstore<S>(P.out, roff + ((long)s * 12 + cp) * Vhp + site, cr[i], ci[i]);
                 nrm += double(cr[i]) * double(cr[i]) + double(ci[i]) * double(ci[i]);
             }
         }
@@ -384,34 +473,53 @@ __global__ __launch_bounds__(256) void mix_mfma_kernel(MixParams P) {
 // ---------------------------------------------------------------------
 // launchers
 // ---------------------------------------------------------------------
-int hop_grid_blocks(long Vh) { return (int)((Vh + 63) / 64); }
+int hop_grid_blocks(long Vh) { return (int)((Vh + 15) / 16); }
+static int mix_grid_blocks(long Vh) { return (int)((Vh + 63) / 64); }
 
-template <class S>
+template <class S, int TAG>
 static void launch_hop_t(const HopParams& P, int nrhs, hipStream_t st) {
-    dim3 grid(hop_grid_blocks(P.Vh), nrhs), block(256);
     const int KK = (P.Ls + 3) / 4;
+    dim3 grid(hop_grid_blocks(P.Vh), nrhs), block(64 * hop_waves(KK, sizeof(S) == 8));
     switch (KK) {
-        case 1: hipLaunchKernelGGL((hop_mfma_kernel<S, 1>), grid, block, 0, st, P); break;
-        case 2: hipLaunchKernelGGL((hop_mfma_kernel<S, 2>), grid, block, 0, st, P); break;
-        case 3: hipLaunchKernelGGL((hop_mfma_kernel<S, 3>), grid, block, 0, st, P); break;
-        case 4: hipLaunchKernelGGL((hop_mfma_kernel<S, 4>), grid, block, 0, st, P); break;
+        case 1: hipLaunchKernelGGL((hop_mfma_kernel<S, 1, TAG>), grid, block, 0, st, P); break;
+        case 2: hipLaunchKernelGGL((hop_mfma_kernel<S, 2, TAG>), grid, block, 0, st, P); break;
+        case 3: hipLaunchKernelGGL((hop_mfma_kernel<S, 3, TAG>), grid, block, 0, st, P); break;
+        case 4: hipLaunchKernelGGL((hop_mfma_kernel<S, 4, TAG>), grid, block, 0, st, P); break;
         default: throw Error{DWF_EDIMS, "Ls > 16 not supported by the fused hop"};
     }
     DWF_HIP(hipGetLastError());
 }
 
-void launch_hop(int kind, const HopParams& P, int nrhs, hipStream_t st) {
+void launch_hop(int kind, const HopParams& P, int nrhs, hipStream_t st, int bench_tag) {
     switch (kind) {
-        case ST_F64: launch_hop_t<double>(P, nrhs, st); break;
-        case ST_F32: launch_hop_t<float>(P, nrhs, st); break;
-        case ST_BF16: launch_hop_t<bf16s>(P, nrhs, st); break;
+        case ST_F64:
+            if (bench_tag) launch_hop_t<double, 1>(P, nrhs, st); else launch_hop_t<double, 0>(P, nrhs, st);
+            break;
+        case ST_F32:
+            if (bench_tag) launch_hop_t<float, 1>(P, nrhs, st); else launch_hop_t<float, 0>(P, nrhs, st);
+            break;
+        case ST_BF16:
+            if (bench_tag) launch_hop_t<bf16s, 1>(P, nrhs, st); else launch_hop_t<bf16s, 0>(P, nrhs, st);
+            break;
         default: throw Error{DWF_EINVAL, "bad storage kind"};
     }
 }
 
+// Plain streaming copy (16-byte vectors), used to calibrate memory counters.
+__global__ void copy_kernel(float4* __restrict__ dst, const float4* __restrict__ src, long n) {
+    for (long i = (long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (long)gridDim.x * blockDim.x)
+        dst[i] = src[i];
+}
+
+void launch_copy(void* dst, const void* src, size_t bytes, hipStream_t st) {
+    const long n = (long)(bytes / 16);
+    hipLaunchKernelGGL(copy_kernel, dim3(4096), dim3(256), 0, st, (float4*)dst, (const float4*)src, n);
+    DWF_HIP(hipGetLastError());
+}
+
 template <class S>
 static void launch_mix_t(const MixParams& P, int nrhs, hipStream_t st) {
-    dim3 grid(hop_grid_blocks(P.Vh), nrhs), block(256);
+    dim3 grid(mix_grid_blocks(P.Vh), nrhs), block(256);
     const int KK = (P.Ls + 3) / 4;
     switch (KK) {
         case 1: hipLaunchKernelGGL((mix_mfma_kernel<S, 1>), grid, block, 0, st, P); break;

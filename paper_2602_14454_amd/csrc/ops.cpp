@@ -21,18 +21,19 @@ namespace dwf {
 
 void hop(const dwf_op* op, int kind, int out_parity, const void* in, const void* loc, void* out,
          int pre_slot, int post_slot, int locmix_slot, double loc_scale, void* out2, int post2_slot,
-         int locmix2_slot, double* partial, int reduce, int nrhs, hipStream_t st, int Ls_override) {
+         int locmix2_slot, double* partial, int reduce, int nrhs, hipStream_t st, int Ls_override,
+         int bench_tag) {
     const dwf_lattice* L = op->lat;
     DWF_REQUIRE(L->has_gauge, DWF_ESTATE, "gauge field not set");
     HopParams P{};
-    const long Vh = L->Vh;
+    const long Vh = L->Vh, Vhp = L->Vhp;
     const size_t cb = complex_bytes_of(kind);
     P.in = in;
     P.loc = loc;
     P.out = out;
     P.out2 = out2;
-    P.links = static_cast<const char*>(L->links[kind].p) + (size_t)out_parity * 8 * 9 * Vh * cb;
-    P.nbr = L->nbr.as<int>() + (size_t)out_parity * 8 * Vh;
+    P.links = static_cast<const char*>(L->links[kind].p) + (size_t)out_parity * 8 * 9 * Vhp * cb;
+    P.nbr = L->nbr.as<int>() + (size_t)out_parity * 8 * Vhp;
     P.pre = pre_slot >= 0 ? op->pre(kind, pre_slot) : nullptr;
     P.pre_mode = pre_slot < 0 ? 0 : (pre_slot == PRE_K && op->c != 0.0 ? 2 : 1);
     P.post = op->mat(kind, post_slot);
@@ -42,9 +43,13 @@ void hop(const dwf_op* op, int kind, int out_parity, const void* in, const void*
     P.partial = partial;
     P.reduce = reduce;
     P.Vh = Vh;
+    P.Vhp = Vhp;
     P.Ls = Ls_override > 0 ? Ls_override : op->Ls;
     P.loc_scale = loc_scale;
-    launch_hop(kind, P, nrhs, st);
+    // the kernels address one right-hand side with 32-bit byte offsets
+    DWF_REQUIRE((double)P.Ls * 12.0 * (double)Vhp * (double)cb < 4294967296.0, DWF_EDIMS,
+                "field too large for 32-bit in-kernel offsets");
+    launch_hop(kind, P, nrhs, st, bench_tag);
 }
 
 void mix(const dwf_op* op, int kind, const void* in, void* out, int slot, double* partial, int nrhs,
@@ -55,6 +60,7 @@ void mix(const dwf_op* op, int kind, const void* in, void* out, int slot, double
     P.mat = op->mat(kind, slot);
     P.partial = partial;
     P.Vh = op->lat->Vh;
+    P.Vhp = op->lat->Vhp;
     P.Ls = op->Ls;
     launch_mix(kind, P, nrhs, st);
 }

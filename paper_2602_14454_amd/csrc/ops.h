@@ -14,7 +14,8 @@ inline size_t complex_bytes_of(int kind) { return kind == ST_F64 ? 16 : kind == 
 // Generic fused hop; see hop.h.  *_slot < 0 means "not used".
 void hop(const dwf_op* op, int kind, int out_parity, const void* in, const void* loc, void* out,
          int pre_slot, int post_slot, int locmix_slot, double loc_scale, void* out2, int post2_slot,
-         int locmix2_slot, double* partial, int reduce, int nrhs, hipStream_t st, int Ls_override = 0);
+         int locmix2_slot, double* partial, int reduce, int nrhs, hipStream_t st, int Ls_override = 0,
+         int bench_tag = 0);
 void mix(const dwf_op* op, int kind, const void* in, void* out, int slot, double* partial, int nrhs,
          hipStream_t st);
 int hop_partials(const dwf_op* op, int nrhs);

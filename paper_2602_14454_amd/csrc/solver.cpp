@@ -36,7 +36,7 @@ static void read_scalars(const double* dev, Pinned& host, hipStream_t st) {
 }
 
 CgWork::CgWork(const dwf_op* op, int kx_, int kp_, int nrhs_) : kx(kx_), kp(kp_), nrhs(nrhs_) {
-    n = (long)op->Ls * 12 * op->lat->Vh * nrhs;
+    n = (long)op->Ls * 12 * op->lat->Vhp * nrhs;
     const size_t bx = complex_bytes_of(kx) * n, bp = complex_bytes_of(kp) * n;
     x.alloc(bx);
     r.alloc(bx);
@@ -108,9 +108,9 @@ int solve(const dwf_op* op, void* x5, const void* b5, const dwf_solve_params* pr
           hipStream_t st) {
     const dwf_lattice* L = op->lat;
     DWF_REQUIRE(L->has_gauge, DWF_ESTATE, "gauge field not set");
-    const long Vh = L->Vh, V = L->V;
+    const long Vh = L->Vh, Vhp = L->Vhp, V = L->V;
     const int Ls = op->Ls;
-    const long n = (long)Ls * 12 * Vh;
+    const long n = (long)Ls * 12 * Vhp;
     const size_t b64 = 16 * n;
     DevBuf be(b64), bo(b64), bt(b64), xe(b64), xo(b64), rh(b64), te(b64), to(b64);
     DevBuf partial((std::max<long>(hop_partials(op, 1), blas_grid(n)) * 2 + 16) * sizeof(double));
@@ -132,9 +132,9 @@ int solve(const dwf_op* op, void* x5, const void* b5, const dwf_solve_params* pr
     DWF_HIP(hipEventRecord(e0, st));
     DWF_HIP(hipMemsetAsync(scal.p, 0, CG_NSLOTS * sizeof(double), st));
 
-    const int* lex = L->lex_of_eo_dev.as<int>();
-    pack_full(ST_F64, be.p, b5, lex, Vh, V, Ls, st);
-    pack_full(ST_F64, bo.p, b5, lex + Vh, Vh, V, Ls, st);
+    const int* lex = L->lex_of_site_dev.as<int>();
+    pack_full(ST_F64, be.p, b5, lex, Vh, Vhp, V, Ls, st);
+    pack_full(ST_F64, bo.p, b5, lex + Vh, Vh, Vhp, V, Ls, st);
     const double b2 = norm2_host(ST_F64, be.p, n, pp, sc, hs, st) + norm2_host(ST_F64, bo.p, n, pp, sc, hs, st);
     schur_rhs(op, ST_F64, bt.p, be.p, bo.p, to.p, 1, st);
 
@@ -182,8 +182,8 @@ int solve(const dwf_op* op, void* x5, const void* b5, const dwf_solve_params* pr
         prev_rel = rel5;
     }
     reconstruct_odd(op, ST_F64, xo.p, xe.p, bo.p, 1, st);
-    unpack_full(ST_F64, x5, xe.p, lex, Vh, V, Ls, st);
-    unpack_full(ST_F64, x5, xo.p, lex + Vh, Vh, V, Ls, st);
+    unpack_full(ST_F64, x5, xe.p, lex, Vh, Vhp, V, Ls, st);
+    unpack_full(ST_F64, x5, xo.p, lex + Vh, Vh, Vhp, V, Ls, st);
     DWF_HIP(hipEventRecord(e1, st));
     // final FP64 true residual of the 5D system (outside the timed region)
     apply_full(op, ST_F64, 0, te.p, to.p, xe.p, xo.p, 1, st);
@@ -211,17 +211,17 @@ int solve(const dwf_op* op, void* x5, const void* b5, const dwf_solve_params* pr
 
 double true_residual(const dwf_op* op, const void* x5, const void* b5, hipStream_t st) {
     const dwf_lattice* L = op->lat;
-    const long Vh = L->Vh, V = L->V;
+    const long Vh = L->Vh, Vhp = L->Vhp, V = L->V;
     const int Ls = op->Ls;
-    const long n = (long)Ls * 12 * Vh;
+    const long n = (long)Ls * 12 * Vhp;
     DevBuf xe(16 * n), xo(16 * n), be(16 * n), bo(16 * n), te(16 * n), to(16 * n);
     DevBuf partial((blas_grid(n) + 16) * sizeof(double)), scal(CG_NSLOTS * sizeof(double));
     Pinned hs(CG_NSLOTS);
-    const int* lex = L->lex_of_eo_dev.as<int>();
-    pack_full(ST_F64, xe.p, x5, lex, Vh, V, Ls, st);
-    pack_full(ST_F64, xo.p, x5, lex + Vh, Vh, V, Ls, st);
-    pack_full(ST_F64, be.p, b5, lex, Vh, V, Ls, st);
-    pack_full(ST_F64, bo.p, b5, lex + Vh, Vh, V, Ls, st);
+    const int* lex = L->lex_of_site_dev.as<int>();
+    pack_full(ST_F64, xe.p, x5, lex, Vh, Vhp, V, Ls, st);
+    pack_full(ST_F64, xo.p, x5, lex + Vh, Vh, Vhp, V, Ls, st);
+    pack_full(ST_F64, be.p, b5, lex, Vh, Vhp, V, Ls, st);
+    pack_full(ST_F64, bo.p, b5, lex + Vh, Vh, Vhp, V, Ls, st);
     apply_full(op, ST_F64, 0, te.p, to.p, xe.p, xo.p, 1, st);
     double* pp = partial.as<double>();
     double* sc = scal.as<double>();
@@ -229,6 +229,58 @@ double true_residual(const dwf_op* op, const void* x5, const void* b5, hipStream
     axpby(ST_F64, ST_F64, te.p, be.p, n, nullptr, 1.0, nullptr, -1.0, nullptr, st);
     axpby(ST_F64, ST_F64, to.p, bo.p, n, nullptr, 1.0, nullptr, -1.0, nullptr, st);
     const double r2 = norm2_host(ST_F64, te.p, n, pp, sc, hs, st) + norm2_host(ST_F64, to.p, n, pp, sc, hs, st);
+    return b2 > 0 ? std::sqrt(r2 / b2) : 0.0;
+}
+
+// 4D residual of a projected solution (Sec. 2.3: the 4D solution is the
+// same for every alpha).  With D_eff(m) y = [P^dag D(1)^-1 D(m) P (y,0,..,0)]_{s=1}
+// (alpha = 1; the Pauli-Villars ratio of the domain-wall literature) the
+// map G: b4 -> x4 satisfies (1 - m) G + 1 = D_eff^-1, hence
+//   r4 = b4 - D_eff((1 - m) x4 + b4)
+// vanishes for the exact x4.  Cost: one D(m) application and one well
+// conditioned m = 1 solve (FP64 CGNR to tol_inner).
+double residual_4d(const dwf_op* op, const void* x4, const void* b4, double tol_inner, hipStream_t st) {
+    dwf_lattice* L = op->lat;
+    const long V = L->V, Vh = L->Vh, Vhp = L->Vhp;
+    const int Ls = op->Ls;
+    const long n4 = V * 12, n = (long)Ls * 12 * Vhp;
+    dwf_op om, o1;
+    om.lat = o1.lat = L;
+    om.Ls = o1.Ls = Ls;
+    om.M0 = o1.M0 = op->M0;
+    om.b = o1.b = op->b;
+    om.c = o1.c = op->c;
+    om.alpha = o1.alpha = 1.0;
+    om.m = op->m;
+    o1.m = 1.0;
+    setup_op(&om);
+    setup_op(&o1);
+    DevBuf y(16 * n4), e5(16 * n4 * Ls), z5(16 * n4 * Ls), v5(16 * n4 * Ls), ie(16 * n), io(16 * n), oe(16 * n),
+        oo(16 * n), partial((blas_grid(n4 * Ls) + 16) * sizeof(double)), scal(CG_NSLOTS * sizeof(double));
+    Pinned hs(CG_NSLOTS);
+    const int* lex = L->lex_of_site_dev.as<int>();
+    convert(ST_F64, ST_F64, y.p, b4, n4, st);
+    axpby(ST_F64, ST_F64, y.p, x4, n4, nullptr, 1.0 - op->m, nullptr, 1.0, nullptr, st);
+    embed_4d(e5.p, y.p, V, Ls, st);
+    pack_full(ST_F64, ie.p, e5.p, lex, Vh, Vhp, V, Ls, st);
+    pack_full(ST_F64, io.p, e5.p, lex + Vh, Vh, Vhp, V, Ls, st);
+    apply_full(&om, ST_F64, 0, oe.p, oo.p, ie.p, io.p, 1, st);
+    unpack_full(ST_F64, z5.p, oe.p, lex, Vh, Vhp, V, Ls, st);
+    unpack_full(ST_F64, z5.p, oo.p, lex + Vh, Vh, Vhp, V, Ls, st);
+    dwf_solve_params prm;
+    std::memset(&prm, 0, sizeof prm);
+    prm.tol = tol_inner;
+    prm.maxiter = 100000;
+    prm.algo = DWF_ALGO_CGNR;
+    prm.inner_prec = DWF_F64;
+    prm.check_every = 4;
+    solve(&o1, v5.p, z5.p, &prm, nullptr, st);
+    project_4d(y.p, v5.p, V, Ls, st);
+    axpby(ST_F64, ST_F64, y.p, b4, n4, nullptr, 1.0, nullptr, -1.0, nullptr, st);   // y = b4 - D_eff(...)
+    double* pp = partial.as<double>();
+    double* sc = scal.as<double>();
+    const double r2 = norm2_host(ST_F64, y.p, n4, pp, sc, hs, st);
+    const double b2 = norm2_host(ST_F64, b4, n4, pp, sc, hs, st);
     return b2 > 0 ? std::sqrt(r2 / b2) : 0.0;
 }
 

@@ -22,5 +22,6 @@ int cgnr(const dwf_op* op, CgWork& W, const void* b_kp, double tol_rel, int maxi
 int solve(const dwf_op* op, void* x5, const void* b5, const dwf_solve_params* prm, dwf_solve_info* info,
           hipStream_t st);
 double true_residual(const dwf_op* op, const void* x5, const void* b5, hipStream_t st);
+double residual_4d(const dwf_op* op, const void* x4, const void* b4, double tol_inner, hipStream_t st);
 
 }  // namespace dwf

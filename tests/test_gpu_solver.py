@@ -117,3 +117,24 @@ def test_nan_source_reports_enan():
     with pytest.raises(dwf.DwfError) as e:
         op.solve(x5, _dev(b5), dwf.default_params())
     assert e.value.status == -6
+
+
+def test_residual_4d_matches_oracle():
+    """GPU 4D residual of a perturbed 4D solution equals the oracle's."""
+    import torch
+    import paper_2602_14454_amd as dwf
+    dims = (4, 4, 2, 4)
+    Ls = 6
+    lat, op, p, U = _setup(dims, Ls, 1.6, 0.05, 1.5, 0.5, 0.7, eps=0.5, seed=3)
+    b4 = dwfgen.gaussian_source_4d(dims, 4)
+    b5 = torch.empty((Ls, p.V, 4, 3), dtype=torch.complex128, device="cuda")
+    op.source_4d(b5, _dev(b4))
+    x5 = torch.zeros_like(b5)
+    op.solve(x5, b5, dwf.default_params(tol=1e-12))
+    x4 = torch.empty((p.V, 4, 3), dtype=torch.complex128, device="cuda")
+    op.project_4d(x4, x5)
+    assert op.residual_4d(x4, _dev(b4)) < 1e-11
+    x4p = x4.cpu().numpy() + 1e-4 * dwfgen.gaussian_source_4d(dims, 5)
+    g = op.residual_4d(_dev(x4p), _dev(b4))
+    o = oracle.residual_4d(p, U, x4p, b4)
+    assert g > 1e-6 and abs(g - o) < 1e-8 * o
