@@ -3,8 +3,8 @@
 
 A step is one full solve of the 5D domain-wall system for a 4D source that is
 already resident in HBM: b5 = (-D_-) P^dag (0,..,b4) on the device, even-odd
-Schur RHS, CG on D^dag D^ (FP32 inner CG inside FP64 defect correction by
-default), reconstruction, 4D projection.  The timed region is exactly K such
+Schur RHS, CG on D^dag D^ (by default BF16-storage CG, FP32 arithmetic,
+restarted inside FP64 defect correction), reconstruction, 4D projection.  The timed region is exactly K such
 solves bracketed by torch.cuda.synchronize().
 
 Workload (default): 16^3 x 32 lattice, Ls = 16, M0 = 1.6, m = 0.01, Shamir
@@ -13,7 +13,9 @@ Workload (default): 16^3 x 32 lattice, Ls = 16, M0 = 1.6, m = 0.01, Shamir
 in for the paper's quenched ensembles.
 
 Besides the headline line this script measures, once each: the FP64 CGNR
-solve (standard and Neff form) it is compared with, the BF16-inner solve,
+solve (standard and Neff form) it is compared with, the other mixed
+precision solvers (restarted defect correction and reliable updates, FP32
+and BF16 inner),
 the 4D residual of every x4 (on the GPU), the roofline of the fused hop
 kernel (HIP events on the stream it runs on), and the FP64 CPU oracle on a
 bounded sample (a few CG iterations on the full lattice).
@@ -41,7 +43,8 @@ CONFIGS = {
     "c1": dict(dims=(4, 4, 4, 4), Ls=8, M0=1.6, m=0.05, b=1.0, c=0.0, alpha=1.0, eps=0.3,
                seed=1, src_seed=2, nsmear=0, rho=0.0),
 }
-MODES = {"dc_f32": ("DC", 1), "dc_bf16": ("DC", 2), "fp64": ("CGNR", 0)}
+MODES = {"mixed_f32": ("MIXED", 1), "mixed_bf16": ("MIXED", 2), "dc_f32": ("DC", 1), "dc_bf16": ("DC", 2),
+         "fp64": ("CGNR", 0)}
 
 
 def log(*a):
@@ -69,7 +72,7 @@ def main():
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--config", default="c2", choices=sorted(CONFIGS))
-    ap.add_argument("--mode", default="dc_f32", choices=sorted(MODES))
+    ap.add_argument("--mode", default="dc_bf16", choices=sorted(MODES))
     ap.add_argument("--skip-cpu", action="store_true", help="skip the oracle CPU baseline")
     ap.add_argument("--skip-variants", action="store_true", help="skip the comparison solves")
     ap.add_argument("--hop-only", action="store_true", help="only time the fused hop (for counter runs)")
@@ -107,7 +110,7 @@ def main():
     x5 = torch.zeros_like(b5)
     x4 = torch.empty((V, 4, 3), dtype=torch.complex128, device=dev)
 
-    hop_prec = {"dc_f32": dwf.F32, "dc_bf16": dwf.BF16, "fp64": dwf.F64}[args.mode]
+    hop_prec = {"f32": dwf.F32, "bf16": dwf.BF16, "fp64": dwf.F64}[args.mode.split("_")[-1]]
     if args.hop_only:
         ms, nbytes = op.bench_hop(prec=hop_prec, nrep=args.hop_reps)
         copy_bytes = 1 << 30
@@ -118,8 +121,8 @@ def main():
 
     algo, inner = MODES[args.mode]
     params = dwf.default_params(tol=1e-10, check_every=8)
-    if algo == "DC":
-        params.algo = dwf.ALGO_DC
+    if algo in ("DC", "MIXED"):
+        params.algo = dwf.ALGO_DC if algo == "DC" else dwf.ALGO_MIXED
         params.inner_prec = inner
 
     def one_solve(p, o=op):
@@ -164,16 +167,18 @@ def main():
         x4_64 = run_variant("fp64_cgnr_neff", p64, op)
         op_std = dwf.Op(lat, Ls, cfg["M0"], cfg["m"], cfg["b"], cfg["c"], 1.0)
         x4_std = run_variant("fp64_cgnr_standard", p64, op_std)
-        pbf = dwf.default_params(tol=1e-10, check_every=8, algo=dwf.ALGO_DC, inner_prec=dwf.BF16)
-        x4_bf = run_variant("dc_bf16_neff", pbf, op)
-        pf = dwf.default_params(tol=1e-10, check_every=8, algo=dwf.ALGO_DC, inner_prec=dwf.F32)
-        x4_f = run_variant("dc_f32_neff", pf, op)
+        others = {}
+        for name, algo_v, pr in (("dc_bf16_neff", dwf.ALGO_DC, dwf.BF16), ("dc_f32_neff", dwf.ALGO_DC, dwf.F32),
+                                 ("mixed_bf16_neff", dwf.ALGO_MIXED, dwf.BF16),
+                                 ("mixed_f32_neff", dwf.ALGO_MIXED, dwf.F32)):
+            pv = dwf.default_params(tol=1e-10, check_every=8, algo=algo_v, inner_prec=pr)
+            others[name] = run_variant(name, pv, op)
         pp = dwf.default_params(check_every=8, paper_mode=1, inner_prec=dwf.F32)
         for name, o in (("paper_mode_f32_neff", op), ("paper_mode_f32_standard", op_std)):
             st, info = one_solve(pp, o)
             variants[name] = {"iters": info.iters, "true_res5": info.true_res5}
         nrm = torch.linalg.vector_norm(x4_64).item()
-        for name, xv in (("fp64_cgnr_standard", x4_std), ("dc_bf16_neff", x4_bf), ("dc_f32_neff", x4_f)):
+        for name, xv in [("fp64_cgnr_standard", x4_std)] + list(others.items()):
             variants[name]["x4_rel_err_vs_fp64"] = torch.linalg.vector_norm(xv - x4_64).item() / nrm
         variants["headline_x4_rel_err_vs_fp64"] = torch.linalg.vector_norm(x4_head - x4_64).item() / nrm
         it_n, it_s = variants["paper_mode_f32_neff"]["iters"], variants["paper_mode_f32_standard"]["iters"]
@@ -185,7 +190,7 @@ def main():
         ms, nbytes = op.bench_hop(prec=pk, nrep=args.hop_reps)
         hop[pname] = {"ms": ms, "bytes": nbytes, "GBps": nbytes / ms / 1e6}
         log(f"hop {pname}: {ms * 1e3:.1f} us, {nbytes / ms / 1e6:.0f} GB/s")
-    hp = {"dc_f32": "f32", "dc_bf16": "bf16", "fp64": "f64"}[args.mode]
+    hp = {"f32": "f32", "bf16": "bf16", "fp64": "f64"}[args.mode.split("_")[-1]]
     achieved = hop[hp]["GBps"]
     traffic = None
     cpath = os.path.join(ROOT, "profiles", "hop_counters.json")
@@ -222,10 +227,11 @@ def main():
 
     out = {
         "metric": ("time to 1e-10 4D residual (one solve, b4 resident -> x4 resident): "
-                   f"{args.mode} Neff-form CGNR; D_dw hop HBM GB/s in roofline"),
+                   f"{args.mode} Neff-form CGNR (low-precision inner CG, FP64 outer); "
+                   "D_dw hop HBM GB/s in roofline"),
         "value": t_solve, "unit": "s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
         "ms_per_step": t_solve * 1e3, "higher_is_better": False, "scaling": "weak", "vs_baseline": None,
-        "dtype": {"dc_f32": "f32", "dc_bf16": "bf16", "fp64": "f64"}[args.mode], "data": "synthetic",
+        "dtype": hp, "data": "synthetic",
         "config": {"workload": workload_name(cfg), "lattice": list(dims), "Ls": Ls, "mode": args.mode,
                    "tol_true_res5": 1e-10, "plaquette": plaq},
         "roofline": roofline, "cpu_baseline": cpu,

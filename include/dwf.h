@@ -56,7 +56,13 @@ enum {
 
 typedef enum { DWF_F64 = 0, DWF_F32 = 1, DWF_BF16 = 2 } dwf_prec;
 typedef enum { DWF_FULL5D = 0, DWF_EVEN5D = 1 } dwf_space;
-typedef enum { DWF_ALGO_CGNR = 0, DWF_ALGO_DC = 1, DWF_ALGO_FGCR_LEARNED = 2 } dwf_algo;
+typedef enum {
+    DWF_ALGO_CGNR = 0,         /* FP64 CGNR (restarted if the 5D residual is not yet met)        */
+    DWF_ALGO_DC = 1,           /* FP64 defect correction around restarted low-precision CGNR     */
+    DWF_ALGO_FGCR_LEARNED = 2, /* flexible GCR with the learned preconditioner (ptc_model)       */
+    DWF_ALGO_MIXED = 3         /* low-precision CGNR with FP64 reliable updates (inner_tol: the  */
+                               /* residual drop that triggers an update; <= 0: 0.1 FP32, 0.25 BF16) */
+} dwf_algo;
 
 typedef struct dwf_lattice dwf_lattice;
 typedef struct dwf_op dwf_op;

@@ -16,7 +16,7 @@ from dataclasses import dataclass
 
 __all__ = [
     "load", "DwfError", "SolveParams", "SolveInfo", "Lattice", "Op",
-    "F64", "F32", "BF16", "FULL5D", "EVEN5D", "ALGO_CGNR", "ALGO_DC", "ALGO_FGCR_LEARNED",
+    "F64", "F32", "BF16", "FULL5D", "EVEN5D", "ALGO_CGNR", "ALGO_DC", "ALGO_FGCR_LEARNED", "ALGO_MIXED",
 ]
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
@@ -25,7 +25,7 @@ LIB_PATH = os.environ.get("DWF_LIB") or os.path.join(_HERE, "libdwf.so")
 
 F64, F32, BF16 = 0, 1, 2
 FULL5D, EVEN5D = 0, 1
-ALGO_CGNR, ALGO_DC, ALGO_FGCR_LEARNED = 0, 1, 2
+ALGO_CGNR, ALGO_DC, ALGO_FGCR_LEARNED, ALGO_MIXED = 0, 1, 2, 3
 OK, NOT_CONVERGED = 0, 1
 
 

@@ -249,7 +249,8 @@ int dwf_solve(const dwf_op* op, void* x5, const void* b5, const dwf_solve_params
         dwf_solve_params def;
         dwf_solve_params_default(&def);
         const dwf_solve_params* p = prm ? prm : &def;
-        DWF_REQUIRE(p->algo == DWF_ALGO_CGNR || p->algo == DWF_ALGO_DC, DWF_EINVAL, "unsupported algorithm");
+        DWF_REQUIRE(p->algo == DWF_ALGO_CGNR || p->algo == DWF_ALGO_DC || p->algo == DWF_ALGO_MIXED, DWF_EINVAL,
+                    "unsupported algorithm");
         return solve(op, x5, b5, p, info, S(stream));
     });
 }

@@ -9,7 +9,7 @@ namespace dwf {
 
 // Slots of the device-resident CG scalar block (doubles).
 enum { CG_RR = 0, CG_QQ = 1, CG_ALPHA = 2, CG_BETA = 3, CG_RRNEW = 4, CG_NANFLAG = 5, CG_RR0 = 6,
-       CG_TMP = 7, CG_NSLOTS = 16 };
+       CG_TMP = 7, CG_RROLD = 8, CG_NSLOTS = 16 };
 
 int blas_grid(long n);
 void pack_full(int kind, void* dst, const void* src, const int* lex, long Vh, long Vhp, long V, long nslices,
@@ -32,7 +32,8 @@ void axpby(int ky, int kx, void* y, const void* x, long n, const double* sa, dou
 void cg_update_xr(int kx, int kp, void* x, void* r, const void* p, const void* w, long n, const double* alpha,
                   double* partial, hipStream_t st);
 void cg_update_p(int kr, int kp, void* p, const void* r, long n, const double* beta, hipStream_t st);
-// mode 0: out[0] = sum; 1: alpha step; 2: beta step (see CG slots)
+// mode 0: out[0] = sum; 1: alpha step; 2: beta step; 3: beta after a residual
+// replacement (RR = sum, BETA = sum / RROLD) (see CG slots)
 void finalize(const double* partial, int nparts, int stride, double* out, int mode, hipStream_t st);
 
 }  // namespace dwf

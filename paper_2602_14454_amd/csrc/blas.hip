@@ -242,7 +242,8 @@ __global__ void cg_p_kernel(void* p, const void* r, long n, const double* beta) 
 // Sum nparts partials in a fixed order; store according to mode:
 //  mode 0: out[0] = sum
 //  mode 1 (alpha): s[QQ] = sum; s[ALPHA] = s[RR] / sum (0 if sum <= 0)
-//  mode 2 (beta):  s[RRNEW] = sum; s[BETA] = sum / s[RR]; s[RR] = sum
+//  mode 2 (beta):  s[RRNEW] = sum; s[BETA] = sum / s[RR]; s[RROLD] = s[RR]; s[RR] = sum
+//  mode 3 (beta after replacing r): s[RRNEW] = s[RR] = sum; s[BETA] = sum / s[RROLD]
 // A non-finite sum sets s[NANFLAG] = 1.
 __global__ void finalize_kernel(const double* partial, int nparts, int stride, double* out, int mode) {
     __shared__ double red[BLAS_THREADS];
@@ -265,6 +266,11 @@ __global__ void finalize_kernel(const double* partial, int nparts, int stride, d
         } else if (mode == 2) {
             out[CG_RRNEW] = sum;
             out[CG_BETA] = out[CG_RR] > 0.0 ? sum / out[CG_RR] : 0.0;
+            out[CG_RROLD] = out[CG_RR];
+            out[CG_RR] = sum;
+        } else if (mode == 3) {
+            out[CG_RRNEW] = sum;
+            out[CG_BETA] = out[CG_RROLD] > 0.0 ? sum / out[CG_RROLD] : 0.0;
             out[CG_RR] = sum;
         }
     }

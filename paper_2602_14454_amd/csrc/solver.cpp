@@ -104,6 +104,89 @@ static double norm2_host(int kind, const void* v, long n, double* partial, doubl
     return hs.h[CG_TMP];
 }
 
+// Mixed-precision CGNR with reliable updates (Sleijpen and van der Vorst).
+// The CG iteration runs with x_lo, r_lo in FP32 storage and p, w and the hop
+// temporaries in the low storage precision (FP32 or BF16).  Whenever the
+// low-precision residual has dropped by `delta` since the last update, the
+// partial solution is folded into the FP64 solution x_hi, the FP64 Schur
+// residual r^ = b~ - D^ x_hi and the normal residual D^dag r^ are recomputed,
+// and the CG continues with that residual and its old search direction.  The
+// Krylov space is kept (unlike a restart), so the iteration count stays close
+// to the FP64 one while all operator applications but the updates are cheap.
+// Each update also gives the exact 5D residual |M r^| / |b5| (odd rows
+// vanish after reconstruction), which is the stopping test.
+static int cgnr_reliable(const dwf_op* op, CgWork& W, void* xe, const void* bt, void* rh, void* te, void* to,
+                         void* tmp_e, double b2, double tol, double delta, int maxiter, int check_every,
+                         double* pp, double* sc, Pinned& hs, hipStream_t st, int* nupdates, double* rel5_out,
+                         bool* nan_seen) {
+    const long n = W.n;
+    double* partial = W.partial.as<double>();
+    double* scal = W.scal.as<double>();
+    if (check_every < 1) check_every = 1;
+    *nupdates = 0;
+    *nan_seen = false;
+    DWF_HIP(hipMemsetAsync(W.scal.p, 0, CG_NSLOTS * sizeof(double), st));
+    // r^ = b~ (x_hi = 0), r = D^dag r^
+    convert(ST_F64, ST_F64, rh, bt, n, st);
+    apply_dhat(op, ST_F64, 1, te, rh, to, tmp_e, 1, st);
+    convert(W.kx, ST_F64, W.r.p, te, n, st);
+    convert(W.kp, W.kx, W.p.p, W.r.p, n, st);
+    DWF_HIP(hipMemsetAsync(W.x.p, 0, complex_bytes_of(W.kx) * n, st));
+    norm2_partial(W.kx, W.r.p, n, partial, st);
+    finalize(partial, blas_grid(n), 1, scal + CG_RR, 0, st);
+    read_scalars(scal, hs, st);
+    const double rr0 = hs.h[CG_RR];
+    if (!std::isfinite(rr0)) { *nan_seen = true; return 0; }
+    if (rr0 == 0.0) { *rel5_out = 0.0; return 0; }
+    double rmax2 = rr0;
+    double target = tol * tol * rr0;
+    double rel5 = 1.0;
+    int k = 0;
+    while (k < maxiter) {
+        apply_normal(op, W.kp, W.w.p, W.p.p, W.t.p, W.v.p, partial, W.nrhs, st);
+        finalize(partial, hop_partials(op, W.nrhs), 1, scal, 1, st);
+        cg_update_xr(W.kx, W.kp, W.x.p, W.r.p, W.p.p, W.w.p, n, scal + CG_ALPHA, partial, st);
+        finalize(partial, blas_grid(n), 1, scal, 2, st);
+        ++k;
+        if (k % check_every == 0 || k == maxiter) {
+            read_scalars(scal, hs, st);
+            const double rr = hs.h[CG_RR];
+            if (hs.h[CG_NANFLAG] != 0.0 || !std::isfinite(rr)) { *nan_seen = true; break; }
+            if (rr < delta * delta * rmax2 || rr < target || k == maxiter) {
+                // reliable update: fold x_lo into x_hi and recompute the residual in FP64
+                axpby(ST_F64, W.kx, xe, W.x.p, n, nullptr, 1.0, nullptr, 1.0, nullptr, st);
+                DWF_HIP(hipMemsetAsync(W.x.p, 0, complex_bytes_of(W.kx) * n, st));
+                apply_dhat(op, ST_F64, 0, te, xe, to, tmp_e, 1, st);
+                convert(ST_F64, ST_F64, rh, bt, n, st);
+                axpby(ST_F64, ST_F64, rh, te, n, nullptr, -1.0, nullptr, 1.0, nullptr, st);
+                mix(op, ST_F64, rh, te, MAT_M, nullptr, 1, st);
+                rel5 = std::sqrt(norm2_host(ST_F64, te, n, pp, sc, hs, st) / b2);
+                ++*nupdates;
+                if (rel5 <= tol || k == maxiter) break;
+                apply_dhat(op, ST_F64, 1, te, rh, to, tmp_e, 1, st);
+                convert(W.kx, ST_F64, W.r.p, te, n, st);
+                norm2_partial(W.kx, W.r.p, n, partial, st);
+                finalize(partial, blas_grid(n), 1, scal, 3, st);
+                read_scalars(scal, hs, st);
+                const double rr_true = hs.h[CG_RR];
+                if (rr < target) {
+                    // the recursive residual met the normal-equation target but the
+                    // 5D residual did not: tighten the target by the observed gap
+                    const double f = tol / rel5;
+                    target = rr_true * f * f * 0.25;
+                }
+                rmax2 = rr_true;
+            } else {
+                rmax2 = std::max(rmax2, rr);
+            }
+        }
+        cg_update_p(W.kx, W.kp, W.p.p, W.r.p, n, scal + CG_BETA, st);
+    }
+    if (*nan_seen) return k;
+    *rel5_out = rel5;
+    return k;
+}
+
 int solve(const dwf_op* op, void* x5, const void* b5, const dwf_solve_params* prm, dwf_solve_info* info,
           hipStream_t st) {
     const dwf_lattice* L = op->lat;
@@ -120,7 +203,7 @@ int solve(const dwf_op* op, void* x5, const void* b5, const dwf_solve_params* pr
     double* sc = scal.as<double>();
 
     int kp = ST_F64;
-    if (prm->algo == DWF_ALGO_DC || prm->paper_mode) kp = prm->inner_prec;
+    if (prm->algo == DWF_ALGO_DC || prm->algo == DWF_ALGO_MIXED || prm->paper_mode) kp = prm->inner_prec;
     DWF_REQUIRE(kp == ST_F64 || kp == ST_F32 || kp == ST_BF16, DWF_EINVAL, "bad inner precision");
     // all workspace is allocated before the timed region starts
     std::unique_ptr<CgWork> W(new CgWork(op, kp == ST_F64 ? ST_F64 : ST_F32, kp, 1));
@@ -154,7 +237,17 @@ int solve(const dwf_op* op, void* x5, const void* b5, const dwf_solve_params* pr
         rel5 = 0.0;
     }
     double prev_rel = 1e300;
-    while (!converged && total < maxiter && outer < 100) {
+    if (prm->algo == DWF_ALGO_MIXED && !converged) {
+        const double delta = prm->inner_tol > 0 ? prm->inner_tol : (kp == ST_BF16 ? 0.25 : 0.1);
+        int nup = 0;
+        double r5 = 1.0;
+        total = cgnr_reliable(op, *W, xe.p, bt.p, rh.p, te.p, to.p, xo.p, b2, tol, delta, maxiter,
+                              prm->check_every, pp, sc, hs, st, &nup, &r5, &nan_seen);
+        outer = nup;
+        rel5 = r5;
+        converged = !nan_seen && r5 <= tol;
+    }
+    while (prm->algo != DWF_ALGO_MIXED && !converged && total < maxiter && outer < 100) {
         const int kx = kp == ST_F64 ? ST_F64 : ST_F32;
         if (W->kp != kp) W.reset(new CgWork(op, kx, kp, 1));
         convert(kp, ST_F64, rin.p, rh.p, n, st);

@@ -138,3 +138,25 @@ def test_residual_4d_matches_oracle():
     g = op.residual_4d(_dev(x4p), _dev(b4))
     o = oracle.residual_4d(p, U, x4p, b4)
     assert g > 1e-6 and abs(g - o) < 1e-8 * o
+
+
+@pytest.mark.parametrize("inner", ["f32", "bf16"])
+def test_mixed_reliable_update_cg(inner):
+    """Low-precision CGNR with FP64 reliable updates: FP64 accuracy (checked by
+    the oracle), and an iteration count close to the FP64 CGNR one."""
+    import torch
+    import paper_2602_14454_amd as dwf
+    dims = (6, 4, 4, 4)
+    Ls = 8
+    lat, op, p, U = _setup(dims, Ls, 1.8, 0.01, 1.5, 0.5, 0.6, eps=0.5, seed=21, nsmear=1)
+    b4 = dwfgen.gaussian_source_4d(dims, 22)
+    b5 = torch.empty((Ls, p.V, 4, 3), dtype=torch.complex128, device="cuda")
+    op.source_4d(b5, _dev(b4))
+    x5 = torch.zeros_like(b5)
+    st, info = op.solve(x5, b5, dwf.default_params(tol=1e-10, algo=dwf.ALGO_MIXED, inner_prec=inner))
+    assert st == 0 and info.converged and info.outer_iters >= 1
+    assert oracle.true_residual(p, U, x5.cpu().numpy(), b5.cpu().numpy()) <= 1e-10
+    x5d = torch.zeros_like(b5)
+    st, info64 = op.solve(x5d, b5, dwf.default_params(tol=1e-10))
+    assert info.iters <= (1.35 if inner == "f32" else 2.0) * info64.iters
+    assert (x5 - x5d).abs().max().item() / x5d.abs().max().item() < 1e-7
