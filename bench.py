@@ -78,6 +78,8 @@ def main():
     ap.add_argument("--hop-only", action="store_true", help="only time the fused hop (for counter runs)")
     ap.add_argument("--cpu-iters", type=int, default=3)
     ap.add_argument("--hop-reps", type=int, default=200)
+    ap.add_argument("--spectrum", action="store_true",
+                    help="also measure lambda_min, lambda_max and kappa of D^dag D^ (Lanczos) for alpha and 1")
     args = ap.parse_args()
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
@@ -184,6 +186,21 @@ def main():
         it_n, it_s = variants["paper_mode_f32_neff"]["iters"], variants["paper_mode_f32_standard"]["iters"]
         variants["paper_mode_iteration_reduction"] = 1.0 - it_n / it_s
 
+    spectrum = None
+    if args.spectrum:
+        spectrum = {}
+        for name, al in (("neff", cfg["alpha"]), ("standard", 1.0)):
+            o = dwf.Op(lat, Ls, cfg["M0"], cfg["m"], cfg["b"], cfg["c"], al)
+            torch.cuda.synchronize()
+            t = time.perf_counter()
+            lo, hi, mv, conv = o.lanczos_extremes(basis=64, keep=24, max_restarts=200, tol=1e-8)
+            dt = time.perf_counter() - t
+            spectrum[name] = {"alpha": al, "lambda_min": lo, "lambda_max": hi, "kappa": hi / lo,
+                              "matvecs": mv, "converged": conv, "seconds": dt}
+            log(f"spectrum {name} alpha={al}: lmin {lo:.6e} lmax {hi:.6e} kappa {hi / lo:.4e} "
+                f"({mv} matvecs, {dt:.1f}s, converged {conv})")
+        spectrum["kappa_reduction"] = 1.0 - spectrum["neff"]["kappa"] / spectrum["standard"]["kappa"]
+
     # fused hop roofline (the dominant kernel), HIP events on its stream
     hop = {}
     for pname, pk in (("f64", dwf.F64), ("f32", dwf.F32), ("bf16", dwf.BF16)):
@@ -240,6 +257,8 @@ def main():
                   "gpu_event_seconds": infos[-1]["seconds"]},
         "variants": variants, "hop": hop,
     }
+    if spectrum is not None:
+        out["spectrum"] = spectrum
     print(json.dumps(out))
 
 

@@ -155,6 +155,17 @@ int dwf_true_residual(const dwf_op* op, const void* x5, const void* b5, double* 
 int dwf_residual_4d(const dwf_op* op, const void* x4, const void* b4, double tol_inner, double* rel,
                     void* stream);
 
+/* Smallest and largest eigenvalue of the CGNR normal operator D^dag D^ (the
+ * condition number study of Sec. 3.2.1, measured there with implicitly
+ * restarted Lanczos in double precision).  Thick-restart Lanczos in FP64
+ * with full re-orthogonalisation: `basis` Krylov vectors (device memory:
+ * (basis + 1 + keep) even FP64 fields), restart keeping `keep` Ritz vectors,
+ * at most `max_restarts` restarts per end, convergence when the Ritz
+ * residual |beta_m y_m| <= tol * |theta|.  matvecs and converged may be NULL.
+ * Returns DWF_OK, or DWF_NOT_CONVERGED with the best Ritz values. */
+int dwf_lanczos_extremes(const dwf_op* op, int basis, int keep, int max_restarts, double tol,
+                         double* lambda_min, double* lambda_max, int* matvecs, int* converged, void* stream);
+
 /* ---- measurement helpers ------------------------------------------ */
 
 /* Times `nrep` launches of the fused half-lattice hop kernel of D^ (the

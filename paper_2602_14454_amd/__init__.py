@@ -72,6 +72,7 @@ SIGNATURES = {
     "dwf_true_residual": (_i, [_vp, _vp, _vp, _dp, _vp]),
     "dwf_bench_hop": (_i, [_vp, _i, _i, _dp, _dp, _vp]),
     "dwf_residual_4d": (_i, [_vp, _vp, _vp, _d, _dp, _vp]),
+    "dwf_lanczos_extremes": (_i, [_vp, _i, _i, _i, _d, _dp, _dp, _ip, _ip, _vp]),
     "dwf_bench_copy": (_i, [ctypes.c_size_t, _i, _dp, _vp]),
     "dwf_status_string": (ctypes.c_char_p, [_i]),
     "dwf_last_error": (ctypes.c_char_p, []),
@@ -244,6 +245,15 @@ class Op:
         _check(load().dwf_residual_4d(self._h, _dev_ptr(x4), _dev_ptr(b4), float(tol_inner), ctypes.byref(r),
                                       _stream(stream)), "dwf_residual_4d")
         return r.value
+
+    def lanczos_extremes(self, basis=64, keep=24, max_restarts=50, tol=1e-10, stream=None):
+        """(lambda_min, lambda_max, matvecs, converged) of D^dag D^."""
+        lo, hi = ctypes.c_double(), ctypes.c_double()
+        mv, cv = ctypes.c_int(), ctypes.c_int()
+        _check(load().dwf_lanczos_extremes(self._h, int(basis), int(keep), int(max_restarts), float(tol),
+                                           ctypes.byref(lo), ctypes.byref(hi), ctypes.byref(mv), ctypes.byref(cv),
+                                           _stream(stream)), "dwf_lanczos_extremes")
+        return lo.value, hi.value, mv.value, bool(cv.value)
 
     def bench_hop(self, prec=F32, nrep=50, stream=None):
         ms = ctypes.c_double()

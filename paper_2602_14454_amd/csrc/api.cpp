@@ -297,6 +297,15 @@ int dwf_bench_hop(const dwf_op* op, int prec, int nrep, double* ms_per_launch, d
     });
 }
 
+int dwf_lanczos_extremes(const dwf_op* op, int basis, int keep, int max_restarts, double tol, double* lambda_min,
+                         double* lambda_max, int* matvecs, int* converged, void* stream) {
+    return guarded([&] {
+        DWF_REQUIRE(op && lambda_min && lambda_max, DWF_EINVAL, "null argument");
+        lanczos_extremes(op, basis, keep, max_restarts, tol, lambda_min, lambda_max, matvecs, converged, S(stream));
+        return (converged && !*converged) ? DWF_NOT_CONVERGED : DWF_OK;
+    });
+}
+
 int dwf_bench_copy(size_t bytes, int nrep, double* ms_per_launch, void* stream) {
     return guarded([&] {
         DWF_REQUIRE(bytes >= 16 && nrep > 0, DWF_EINVAL, "bad argument");

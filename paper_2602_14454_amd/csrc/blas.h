@@ -32,6 +32,10 @@ void axpby(int ky, int kx, void* y, const void* x, long n, const double* sa, dou
 void cg_update_xr(int kx, int kp, void* x, void* r, const void* p, const void* w, long n, const double* alpha,
                   double* partial, hipStream_t st);
 void cg_update_p(int kr, int kp, void* p, const void* r, long n, const double* beta, hipStream_t st);
+// y += (ar + i ai) x
+void caxpy(int kind, void* y, const void* x, long n, double ar, double ai, hipStream_t st);
+// FP64 half field(s) of `rows` rows: uniform [-1,1) real and imaginary parts on valid sites
+void random_fill_f64(void* v, long rows, long Vh, long Vhp, unsigned long long seed, hipStream_t st);
 // mode 0: out[0] = sum; 1: alpha step; 2: beta step; 3: beta after a residual
 // replacement (RR = sum, BETA = sum / RROLD) (see CG slots)
 void finalize(const double* partial, int nparts, int stride, double* out, int mode, hipStream_t st);

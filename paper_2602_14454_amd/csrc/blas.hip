@@ -200,6 +200,36 @@ __global__ void axpby_kernel(void* y, const void* x, long n, const double* sa, d
     }
 }
 
+// y += (ar + i ai) x  (complex scalar from the host), one storage type
+template <class S>
+__global__ void caxpy_kernel(void* y, const void* x, long n, double ar, double ai) {
+    using R = typename Traits<S>::R;
+    for (long i = (long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (long)gridDim.x * blockDim.x) {
+        R xr, xi, yr, yi;
+        cload<S>(x, i, xr, xi);
+        cload<S>(y, i, yr, yi);
+        cstore<S>(y, i, yr + R(ar) * xr - R(ai) * xi, yi + R(ar) * xi + R(ai) * xr);
+    }
+}
+
+// Deterministic pseudo-random fill in [-1, 1) (SplitMix64 of seed and index)
+// on the valid sites of each row; padding stays zero.
+__global__ void random_fill_kernel(double2* v, long rows, long Vh, long Vhp, unsigned long long seed) {
+    const long n = rows * Vh;
+    for (long k = (long)blockIdx.x * blockDim.x + threadIdx.x; k < n; k += (long)gridDim.x * blockDim.x) {
+        const long row = k / Vh, site = k % Vh;
+        double out[2];
+        for (int h = 0; h < 2; ++h) {
+            unsigned long long z = seed + 0x9E3779B97F4A7C15ull * (unsigned long long)(2 * k + h + 1);
+            z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+            z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+            z ^= z >> 31;
+            out[h] = (double)(z >> 11) * (2.0 / 9007199254740992.0) - 1.0;
+        }
+        v[row * Vhp + site] = make_double2(out[0], out[1]);
+    }
+}
+
 // CG update: x += alpha p; r -= alpha w; partial |r|^2.  x, r of type SX; p, w of type SP.
 template <class SX, class SP>
 __global__ void cg_xr_kernel(void* x, void* r, const void* p, const void* w, long n,
@@ -455,6 +485,21 @@ static void cg_p_t1(int kp, void* p, const void* r, long n, const double* beta, 
 }
 void cg_update_p(int kr, int kp, void* p, const void* r, long n, const double* beta, hipStream_t st) {
     DISPATCH1(kr, cg_p_t1, kp, p, r, n, beta, st);
+    DWF_HIP(hipGetLastError());
+}
+
+template <class S>
+static void caxpy_t(void* y, const void* x, long n, double ar, double ai, hipStream_t st) {
+    hipLaunchKernelGGL(caxpy_kernel<S>, dim3(blas_grid(n)), dim3(BLAS_THREADS), 0, st, y, x, n, ar, ai);
+}
+void caxpy(int kind, void* y, const void* x, long n, double ar, double ai, hipStream_t st) {
+    DISPATCH1(kind, caxpy_t, y, x, n, ar, ai, st);
+    DWF_HIP(hipGetLastError());
+}
+
+void random_fill_f64(void* v, long rows, long Vh, long Vhp, unsigned long long seed, hipStream_t st) {
+    hipLaunchKernelGGL(random_fill_kernel, dim3(blas_grid(rows * Vh)), dim3(BLAS_THREADS), 0, st, (double2*)v, rows,
+                       Vh, Vhp, seed);
     DWF_HIP(hipGetLastError());
 }
 

@@ -24,4 +24,8 @@ int solve(const dwf_op* op, void* x5, const void* b5, const dwf_solve_params* pr
 double true_residual(const dwf_op* op, const void* x5, const void* b5, hipStream_t st);
 double residual_4d(const dwf_op* op, const void* x4, const void* b4, double tol_inner, hipStream_t st);
 
+// lanczos.cpp: extreme eigenvalues of D^dag D^ (thick-restart Lanczos, FP64)
+void lanczos_extremes(const dwf_op* op, int m, int keep, int max_restarts, double tol, double* lmin, double* lmax,
+                      int* matvecs, int* converged, hipStream_t st);
+
 }  // namespace dwf
