@@ -78,6 +78,9 @@ typedef struct {
                              (Sec. 3.2 criterion), no defect correction; iteration counting only */
     void*    ptc_model;   /* dwf_ptc handle for DWF_ALGO_FGCR_LEARNED, else NULL */
     int      restart;     /* FGCR restart length */
+    int      autotune;    /* batched solves: 0 cached tiles or defaults, 1 tune when not cached,
+                             2 always re-tune */
+    int      use_graph;   /* batched solves: 1 replay the CG iteration body as a HIP graph */
 } dwf_solve_params;
 
 typedef struct {
@@ -142,6 +145,41 @@ int dwf_project_4d(const dwf_op* op, void* x4, const void* x5, void* stream);
  * canonical).  info may be NULL.  Returns DWF_OK or DWF_NOT_CONVERGED. */
 int dwf_solve(const dwf_op* op, void* x5, const void* b5, const dwf_solve_params* prm,
               dwf_solve_info* info, void* stream);
+
+/* Batched solve of n operators (lattices may differ in size, Ls, mass and
+ * (b, c, alpha)), nrhs[i] right-hand sides each: x5[i] and b5[i] hold
+ * nrhs[i] 5D canonical fields back to back (device).  Each right-hand side
+ * ("slot") is solved as by dwf_solve with algo DWF_ALGO_DC (FP64 defect
+ * correction around an FP32/BF16-storage CGNR, Sec. 2.3) or DWF_ALGO_CGNR
+ * (FP64 inner); the slots share every kernel launch of the inner iteration
+ * (the hops of all operators with the same ceil(Ls/4) in one work-list
+ * launch, links of a tile reused across right-hand sides), each with its own
+ * CG scalars and stopping test, and the iteration body is replayed as a HIP
+ * graph (prm->use_graph).  Tiles (right-hand sides per block, block order)
+ * come from the autotuner (prm->autotune).  infos: sum(nrhs) entries in slot
+ * order (operator-major), or NULL; `seconds` is the time of the whole batch.
+ * prm NULL: DC with FP32 inner, tol 1e-10.  Returns DWF_OK when every slot
+ * reached tol, else DWF_NOT_CONVERGED. */
+int dwf_solve_batch(int n, const dwf_op* const* ops, void* const* x5, const void* const* b5, const int* nrhs,
+                    const dwf_solve_params* prm, dwf_solve_info* infos, void* stream);
+
+/* Tile autotuner of the batched solve: times the four hops of D^dag D^ for
+ * every (right-hand sides per block, block order) candidate with HIP events
+ * and keeps the fastest, keyed by (arch, precision, dims, Ls, nrhs of every
+ * operator), in memory and in the text file named by $DWF_TUNE_CACHE
+ * (default $HOME/.cache/libdwf_tune.txt; "off": memory only).  force = 1
+ * re-times a cached key.  ms (may be NULL): time of the four hops.
+ * Cache key: "gfx950|p<prec>" followed by "|<Lx>x<Ly>x<Lz>x<Lt>s<Ls>r<nrhs>"
+ * per operator in batch order; entry (nrb = right-hand sides per block
+ * 1..64, order = 0 tiles fastest / 1 right-hand-side chunks fastest). */
+int dwf_autotune_batch(int n, const dwf_op* const* ops, const int* nrhs, int prec, int force, int* nrb,
+                       int* order, double* ms, void* stream);
+/* Tune-cache access (host only, no GPU call): put an entry, look one up
+ * (DWF_NOT_CONVERGED when absent), and drop the in-memory copy so the next
+ * access re-reads the file. */
+int dwf_tune_cache_put(const char* key, int nrb, int order, double ms);
+int dwf_tune_cache_get(const char* key, int* nrb, int* order, double* ms);
+int dwf_tune_cache_reload(void);
 
 /* |b5 - D^(alpha) x5| / |b5| in FP64. */
 int dwf_true_residual(const dwf_op* op, const void* x5, const void* b5, double* rel, void* stream);

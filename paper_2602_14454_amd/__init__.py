@@ -17,6 +17,7 @@ from dataclasses import dataclass
 __all__ = [
     "load", "DwfError", "SolveParams", "SolveInfo", "Lattice", "Op",
     "F64", "F32", "BF16", "FULL5D", "EVEN5D", "ALGO_CGNR", "ALGO_DC", "ALGO_FGCR_LEARNED", "ALGO_MIXED",
+    "solve_batch", "autotune_batch", "tune_cache_put", "tune_cache_get", "tune_cache_reload",
 ]
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
@@ -39,7 +40,8 @@ class SolveParams(ctypes.Structure):
     _fields_ = [("tol", ctypes.c_double), ("maxiter", ctypes.c_int), ("algo", ctypes.c_int),
                 ("inner_prec", ctypes.c_int), ("inner_tol", ctypes.c_double),
                 ("check_every", ctypes.c_int), ("paper_mode", ctypes.c_int),
-                ("ptc_model", ctypes.c_void_p), ("restart", ctypes.c_int)]
+                ("ptc_model", ctypes.c_void_p), ("restart", ctypes.c_int),
+                ("autotune", ctypes.c_int), ("use_graph", ctypes.c_int)]
 
 
 class SolveInfo(ctypes.Structure):
@@ -73,6 +75,12 @@ SIGNATURES = {
     "dwf_bench_hop": (_i, [_vp, _i, _i, _dp, _dp, _vp]),
     "dwf_residual_4d": (_i, [_vp, _vp, _vp, _d, _dp, _vp]),
     "dwf_lanczos_extremes": (_i, [_vp, _i, _i, _i, _d, _dp, _dp, _ip, _ip, _vp]),
+    "dwf_solve_batch": (_i, [_i, ctypes.POINTER(_vp), ctypes.POINTER(_vp), ctypes.POINTER(_vp), _ip,
+                             ctypes.POINTER(SolveParams), ctypes.POINTER(SolveInfo), _vp]),
+    "dwf_autotune_batch": (_i, [_i, ctypes.POINTER(_vp), _ip, _i, _i, _ip, _ip, _dp, _vp]),
+    "dwf_tune_cache_put": (_i, [ctypes.c_char_p, _i, _i, _d]),
+    "dwf_tune_cache_get": (_i, [ctypes.c_char_p, _ip, _ip, _dp]),
+    "dwf_tune_cache_reload": (_i, []),
     "dwf_bench_copy": (_i, [ctypes.c_size_t, _i, _dp, _vp]),
     "dwf_status_string": (ctypes.c_char_p, [_i]),
     "dwf_last_error": (ctypes.c_char_p, []),
@@ -136,6 +144,51 @@ def _dev_ptr(t):
     if not t.is_contiguous():
         raise ValueError("tensor must be contiguous")
     return ctypes.c_void_p(t.data_ptr())
+
+
+def solve_batch(ops, x5s, b5s, nrhs, params=None, stream=None):
+    """dwf_solve_batch: ops[i] with nrhs[i] right-hand sides stored back to
+    back in x5s[i] / b5s[i].  Returns (status, [SolveInfo per slot])."""
+    n = len(ops)
+    if not (len(x5s) == len(b5s) == len(nrhs) == n):
+        raise ValueError("ops, x5s, b5s and nrhs must have the same length")
+    arr_ops = (ctypes.c_void_p * n)(*[o._h.value for o in ops])
+    arr_x = (ctypes.c_void_p * n)(*[_dev_ptr(x) for x in x5s])
+    arr_b = (ctypes.c_void_p * n)(*[_dev_ptr(b) for b in b5s])
+    arr_n = (ctypes.c_int * n)(*[int(k) for k in nrhs])
+    infos = (SolveInfo * sum(int(k) for k in nrhs))()
+    p = params if params is not None else default_params(algo=ALGO_DC, check_every=8)
+    st = _check(load().dwf_solve_batch(n, arr_ops, arr_x, arr_b, arr_n, ctypes.byref(p), infos,
+                                       _stream(stream)), "dwf_solve_batch")
+    return st, list(infos)
+
+
+def autotune_batch(ops, nrhs, prec=None, force=False, stream=None):
+    """(rhs_per_block, order, ms) chosen by the tile autotuner."""
+    n = len(ops)
+    arr_ops = (ctypes.c_void_p * n)(*[o._h.value for o in ops])
+    arr_n = (ctypes.c_int * n)(*[int(k) for k in nrhs])
+    a, b, ms = ctypes.c_int(), ctypes.c_int(), ctypes.c_double()
+    _check(load().dwf_autotune_batch(n, arr_ops, arr_n, int(F32 if prec is None else prec), int(bool(force)),
+                                     ctypes.byref(a), ctypes.byref(b), ctypes.byref(ms), _stream(stream)),
+           "dwf_autotune_batch")
+    return a.value, b.value, ms.value
+
+
+def tune_cache_put(key: str, nrb: int, order: int, ms: float) -> None:
+    _check(load().dwf_tune_cache_put(key.encode(), int(nrb), int(order), float(ms)), "dwf_tune_cache_put")
+
+
+def tune_cache_get(key: str):
+    """(nrb, order, ms) or None."""
+    a, b, ms = ctypes.c_int(), ctypes.c_int(), ctypes.c_double()
+    st = _check(load().dwf_tune_cache_get(key.encode(), ctypes.byref(a), ctypes.byref(b), ctypes.byref(ms)),
+                "dwf_tune_cache_get")
+    return None if st != 0 else (a.value, b.value, ms.value)
+
+
+def tune_cache_reload() -> None:
+    _check(load().dwf_tune_cache_reload(), "dwf_tune_cache_reload")
 
 
 def default_params(**kw) -> SolveParams:

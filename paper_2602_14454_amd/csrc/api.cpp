@@ -68,6 +68,8 @@ void dwf_solve_params_default(dwf_solve_params* p) {
     p->paper_mode = 0;
     p->ptc_model = nullptr;
     p->restart = 16;
+    p->autotune = 1;
+    p->use_graph = 1;
 }
 
 int dwf_lattice_create(const int dims[4], int antiperiodic_t, dwf_lattice** out) {
@@ -293,6 +295,50 @@ int dwf_bench_hop(const dwf_op* op, int prec, int nrep, double* ms_per_launch, d
         // read every input spinor once, write every output once, read every link once
         const double w = (double)cb / 2.0;   // bytes per real
         if (bytes_per_launch) *bytes_per_launch = w * (double)Vh * (48.0 * op->Ls + 144.0);
+        return DWF_OK;
+    });
+}
+
+int dwf_solve_batch(int n, const dwf_op* const* ops, void* const* x5, const void* const* b5, const int* nrhs,
+                    const dwf_solve_params* prm, dwf_solve_info* infos, void* stream) {
+    return guarded([&] {
+        dwf_solve_params def;
+        dwf_solve_params_default(&def);
+        def.algo = DWF_ALGO_DC;
+        def.check_every = 8;
+        return solve_batch(n, ops, x5, b5, nrhs, prm ? prm : &def, infos, S(stream));
+    });
+}
+
+int dwf_autotune_batch(int n, const dwf_op* const* ops, const int* nrhs, int prec, int force, int* nrb, int* order,
+                       double* ms, void* stream) {
+    return guarded([&] {
+        DWF_REQUIRE(nrb && order, DWF_EINVAL, "null argument");
+        double t = 0;
+        autotune_batch(n, ops, nrhs, prec, force, nrb, order, &t, S(stream));
+        if (ms) *ms = t;
+        return DWF_OK;
+    });
+}
+
+int dwf_tune_cache_put(const char* key, int nrb, int order, double ms) {
+    return guarded([&] {
+        DWF_REQUIRE(key && nrb >= 1 && nrb <= 64 && (order == 0 || order == 1), DWF_EINVAL, "bad tune entry");
+        tune_put(key, nrb, order, ms);
+        return DWF_OK;
+    });
+}
+
+int dwf_tune_cache_get(const char* key, int* nrb, int* order, double* ms) {
+    return guarded([&] {
+        DWF_REQUIRE(key && nrb && order, DWF_EINVAL, "null argument");
+        return tune_get(key, nrb, order, ms) ? DWF_OK : DWF_NOT_CONVERGED;
+    });
+}
+
+int dwf_tune_cache_reload(void) {
+    return guarded([&] {
+        tune_forget();
         return DWF_OK;
     });
 }

@@ -26,6 +26,10 @@ struct HopParams {
     int pre_mode;          // 0 identity, 1 diagonal d, 2 d + e (K sparsity)
     int reduce;            // 1: |out|^2, 2: |out2|^2
     double loc_scale;
+    // work-list (batch) launches only
+    const double* done;    // per-RHS done flags, done[r * done_stride] != 0: skip (nullptr: none)
+    long done_stride;
+    long pstride;          // partial of (rhs r, tile t) at partial[r * pstride + t]
 };
 
 struct MixParams {
@@ -40,6 +44,11 @@ struct MixParams {
 
 int hop_grid_blocks(long Vh);
 void launch_hop(int kind, const HopParams& P, int nrhs, hipStream_t st, int bench_tag = 0);
+// One work-list launch over `nitems` HopParams (device array `items`, same
+// ceil(Ls/4) = KK for all) with block prefix sums and RHS counts in `meta`
+// (device, 2 * nitems + 1 ints); `blocks` = meta[nitems].
+void launch_hop_batch(int kind, int KK, const HopParams* items, const int* meta, int nitems, int blocks, int nrb,
+                      int order, hipStream_t st);
 void launch_copy(void* dst, const void* src, size_t bytes, hipStream_t st);
 void launch_mix(int kind, const MixParams& P, int nrhs, hipStream_t st);
 

@@ -246,26 +246,27 @@ __host__ __device__ constexpr int hop_waves(int KK, bool f64) { return KK / hop_
 // XCD's 4 MB L2 hold the neighbour reuse window.
 // TAG only renames the symbol: TAG = 1 is the instance launched by the
 // stand-alone hop benchmark, so profilers report it apart from the solver's.
-template <class S, int KK, int TAG = 0>
-__global__ __launch_bounds__(256)
-__attribute__((amdgpu_waves_per_eu(sizeof(S) == 8 ? DWF_HOP_WAVES_PER_EU64 : DWF_HOP_WAVES_PER_EU)))
-void hop_mfma_kernel(HopParams P) {
+//
+// hop_tile computes one such block's work: sites 16*tile .. 16*tile+15 of
+// right-hand side `rhs`; part_out (or nullptr) receives the block's partial
+// norm.  Both kernels below call it.
+template <class S, int KK>
+__device__ __forceinline__ void hop_tile(const HopParams& P, long tile, int rhs, double* part_out,
+                                         typename Traits<S>::R (&hs)[KK][24][64], double (&red)[4]) {
     using R = typename Traits<S>::R;
     using V = typename Vec4<R>::T;
-    __shared__ R hs[KK][24][64];
-    __shared__ double red[4];
     const int lane = threadIdx.x & 63;
     const int w = threadIdx.x >> 6;
     const int j = lane & 15, sc = lane >> 4;
     const long Vh = P.Vh;
     const int Ls = P.Ls;
-    const long site = (long)xcd_block(blockIdx.x, gridDim.x) * 16 + j;
+    const long site = tile * 16 + j;
     const bool valid = site < Vh;
     const long sx = valid ? site : Vh - 1;
     constexpr unsigned CB = cbytes<S>();
     const unsigned rowb = (unsigned)P.Vhp * CB;                // bytes of one (s, comp) row
     const unsigned fieldb = (unsigned)Ls * 12u * rowb;         // bytes of one right-hand side
-    const size_t rhsb = (size_t)blockIdx.y * fieldb;           // bytes of the preceding RHS
+    const size_t rhsb = (size_t)rhs * fieldb;                  // bytes of the preceding RHS
     const unsigned sxb = (unsigned)sx * CB;
     HopRes R_;
     R_.in = make_rsrc(static_cast<const char*>(P.in) + rhsb, fieldb);
@@ -398,7 +399,7 @@ void hop_mfma_kernel(HopParams P) {
         }
     }
 
-    if (P.partial) {
+    if (part_out) {
 #pragma unroll
         for (int off = 32; off >= 1; off >>= 1) nrm += __shfl_xor(nrm, off, 64);
         if (lane == 0) red[w] = nrm;
@@ -406,8 +407,58 @@ void hop_mfma_kernel(HopParams P) {
         if (threadIdx.x == 0) {
             double t = 0.0;
             for (int ww = 0; ww < hop_waves(KK, sizeof(S) == 8); ++ww) t += red[ww];
-            P.partial[(long)blockIdx.y * gridDim.x + blockIdx.x] = t;
+            *part_out = t;
         }
+    }
+}
+
+template <class S, int KK, int TAG = 0>
+__global__ __launch_bounds__(256)
+__attribute__((amdgpu_waves_per_eu(sizeof(S) == 8 ? DWF_HOP_WAVES_PER_EU64 : DWF_HOP_WAVES_PER_EU)))
+void hop_mfma_kernel(HopParams P) {
+    __shared__ typename Traits<S>::R hs[KK][24][64];
+    __shared__ double red[4];
+    hop_tile<S, KK>(P, xcd_block(blockIdx.x, gridDim.x), blockIdx.y,
+                    P.partial ? P.partial + (long)blockIdx.y * gridDim.x + blockIdx.x : nullptr, hs, red);
+}
+
+// Work-list form for batches: one launch covers several operators (lattices
+// of any size with the same ceil(Ls/4)) and all their right-hand sides.
+// meta[0..n] is the prefix sum of the blocks of each item, meta[n+1+i] its
+// number of right-hand sides.  Item i takes ceil(nrhs/nrb) x tiles blocks;
+// a block computes one tile for nrb consecutive right-hand sides, so the
+// tile's links and neighbour indices are fetched from HBM once and re-read
+// from cache for the others.  order 0 sweeps tiles fastest (neighbour reuse
+// across tiles of one RHS), order 1 sweeps RHS chunks fastest (link reuse
+// across chunks).  A right-hand side whose done flag is set is skipped
+// (its partial is written as 0).
+template <class S, int KK>
+__global__ __launch_bounds__(256)
+__attribute__((amdgpu_waves_per_eu(sizeof(S) == 8 ? DWF_HOP_WAVES_PER_EU64 : DWF_HOP_WAVES_PER_EU)))
+void hop_batch_kernel(const HopParams* __restrict__ items, const int* __restrict__ meta, int nitems, int nrb,
+                      int order) {
+    __shared__ typename Traits<S>::R hs[KK][24][64];
+    __shared__ double red[4];
+    const int b = xcd_block(blockIdx.x, gridDim.x);
+    int i = 0;
+    while (i + 1 < nitems && b >= meta[i + 1]) ++i;
+    const HopParams P = items[i];
+    const int nrhs = meta[nitems + 1 + i];
+    const long tiles = (P.Vh + 15) / 16;
+    const int chunks = (nrhs + nrb - 1) / nrb;
+    const long local = b - meta[i];
+    const long tile = order == 0 ? local % tiles : local / chunks;
+    const int chunk = order == 0 ? (int)(local / tiles) : (int)(local % chunks);
+    for (int q = 0; q < nrb; ++q) {
+        const int r = chunk * nrb + q;
+        if (r >= nrhs) break;
+        double* part = P.partial ? P.partial + (long)r * P.pstride + tile : nullptr;
+        if (P.done && P.done[(long)r * P.done_stride] != 0.0) {
+            if (part && threadIdx.x == 0) *part = 0.0;
+            continue;
+        }
+        hop_tile<S, KK>(P, tile, r, part, hs, red);
+        __syncthreads();   // hs and red are reused by the next right-hand side
     }
 }
 
@@ -488,6 +539,31 @@ static void launch_hop_t(const HopParams& P, int nrhs, hipStream_t st) {
         default: throw Error{DWF_EDIMS, "Ls > 16 not supported by the fused hop"};
     }
     DWF_HIP(hipGetLastError());
+}
+
+template <class S>
+static void launch_hop_batch_t(int KK, const HopParams* items, const int* meta, int nitems, int blocks, int nrb,
+                               int order, hipStream_t st) {
+    dim3 grid(blocks), block(64 * hop_waves(KK, sizeof(S) == 8));
+    switch (KK) {
+        case 1: hipLaunchKernelGGL((hop_batch_kernel<S, 1>), grid, block, 0, st, items, meta, nitems, nrb, order); break;
+        case 2: hipLaunchKernelGGL((hop_batch_kernel<S, 2>), grid, block, 0, st, items, meta, nitems, nrb, order); break;
+        case 3: hipLaunchKernelGGL((hop_batch_kernel<S, 3>), grid, block, 0, st, items, meta, nitems, nrb, order); break;
+        case 4: hipLaunchKernelGGL((hop_batch_kernel<S, 4>), grid, block, 0, st, items, meta, nitems, nrb, order); break;
+        default: throw Error{DWF_EDIMS, "Ls > 16 not supported by the fused hop"};
+    }
+    DWF_HIP(hipGetLastError());
+}
+
+void launch_hop_batch(int kind, int KK, const HopParams* items, const int* meta, int nitems, int blocks, int nrb,
+                      int order, hipStream_t st) {
+    if (blocks <= 0) return;
+    switch (kind) {
+        case ST_F64: launch_hop_batch_t<double>(KK, items, meta, nitems, blocks, nrb, order, st); break;
+        case ST_F32: launch_hop_batch_t<float>(KK, items, meta, nitems, blocks, nrb, order, st); break;
+        case ST_BF16: launch_hop_batch_t<bf16s>(KK, items, meta, nitems, blocks, nrb, order, st); break;
+        default: throw Error{DWF_EINVAL, "bad storage kind"};
+    }
 }
 
 void launch_hop(int kind, const HopParams& P, int nrhs, hipStream_t st, int bench_tag) {

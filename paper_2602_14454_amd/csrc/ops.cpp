@@ -19,10 +19,9 @@
 
 namespace dwf {
 
-void hop(const dwf_op* op, int kind, int out_parity, const void* in, const void* loc, void* out,
-         int pre_slot, int post_slot, int locmix_slot, double loc_scale, void* out2, int post2_slot,
-         int locmix2_slot, double* partial, int reduce, int nrhs, hipStream_t st, int Ls_override,
-         int bench_tag) {
+HopParams hop_params(const dwf_op* op, int kind, int out_parity, const void* in, const void* loc, void* out,
+                     int pre_slot, int post_slot, int locmix_slot, double loc_scale, void* out2, int post2_slot,
+                     int locmix2_slot, double* partial, int reduce, int Ls_override) {
     const dwf_lattice* L = op->lat;
     DWF_REQUIRE(L->has_gauge, DWF_ESTATE, "gauge field not set");
     HopParams P{};
@@ -46,9 +45,21 @@ void hop(const dwf_op* op, int kind, int out_parity, const void* in, const void*
     P.Vhp = Vhp;
     P.Ls = Ls_override > 0 ? Ls_override : op->Ls;
     P.loc_scale = loc_scale;
+    P.done = nullptr;
+    P.done_stride = 0;
+    P.pstride = hop_grid_blocks(Vh);
     // the kernels address one right-hand side with 32-bit byte offsets
     DWF_REQUIRE((double)P.Ls * 12.0 * (double)Vhp * (double)cb < 4294967296.0, DWF_EDIMS,
                 "field too large for 32-bit in-kernel offsets");
+    return P;
+}
+
+void hop(const dwf_op* op, int kind, int out_parity, const void* in, const void* loc, void* out,
+         int pre_slot, int post_slot, int locmix_slot, double loc_scale, void* out2, int post2_slot,
+         int locmix2_slot, double* partial, int reduce, int nrhs, hipStream_t st, int Ls_override,
+         int bench_tag) {
+    const HopParams P = hop_params(op, kind, out_parity, in, loc, out, pre_slot, post_slot, locmix_slot, loc_scale,
+                                   out2, post2_slot, locmix2_slot, partial, reduce, Ls_override);
     launch_hop(kind, P, nrhs, st, bench_tag);
 }
 

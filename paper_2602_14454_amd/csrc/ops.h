@@ -6,11 +6,16 @@
 #include <complex>
 
 #include "dwf_internal.h"
+#include "hop.h"
 
 namespace dwf {
 
 inline size_t complex_bytes_of(int kind) { return kind == ST_F64 ? 16 : kind == ST_F32 ? 8 : 4; }
 
+// Parameters of one fused hop (see hop.h) without launching it.
+HopParams hop_params(const dwf_op* op, int kind, int out_parity, const void* in, const void* loc, void* out,
+                     int pre_slot, int post_slot, int locmix_slot, double loc_scale, void* out2, int post2_slot,
+                     int locmix2_slot, double* partial, int reduce, int Ls_override = 0);
 // Generic fused hop; see hop.h.  *_slot < 0 means "not used".
 void hop(const dwf_op* op, int kind, int out_parity, const void* in, const void* loc, void* out,
          int pre_slot, int post_slot, int locmix_slot, double loc_scale, void* out2, int post2_slot,

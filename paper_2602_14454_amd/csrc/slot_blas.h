@@ -1,0 +1,51 @@
+// Slot-aware vector kernels for batched solves (slot_blas.hip).
+//
+// A batch is a list of slots; a slot is one right-hand side of one operator
+// (lattices may differ in size and Ls).  Every batch vector is one buffer
+// holding the slots' even half fields back to back: slot v occupies complex
+// elements [off, off + n).  Each slot owns a block of CG scalars at
+// scal[v * CG_NSLOTS] and a run of partial sums at partial[v * pstride].
+// One launch covers all slots (block -> slot through block0); a slot whose
+// CG_DONE flag is set is left untouched.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+namespace dwf {
+
+// extra per-slot CG scalars (after the ones in blas.h)
+enum { CG_DONE = 9, CG_STOP = 10, CG_ITERS = 11 };
+
+struct SlotDesc {
+    long off;     // complex-element offset of the slot in every batch vector
+    long n;       // complex elements of the slot (Ls * 12 * Vhp)
+    int nb;       // vector-kernel blocks of the slot
+    int block0;   // first vector-kernel block of the slot
+    int nhop;     // partials written per hop launch (tiles of its lattice)
+    int pad;
+};
+
+// blocks of one slot for the vector kernels
+int slot_blocks(long n);
+
+// partial[v * pstride + b] = |x_v|^2 over block b of slot v
+void bnorm2(int kind, const void* x, const SlotDesc* slots, int nslots, int blocks, double* partial, long pstride,
+            const double* scal, hipStream_t st);
+// x_v += alpha_v p_v; r_v -= alpha_v w_v; partial |r_v|^2   (alpha_v = scal[v][CG_ALPHA])
+void bcg_xr(int kx, int kp, void* x, void* r, const void* p, const void* w, const SlotDesc* slots, int nslots,
+            int blocks, const double* scal, double* partial, long pstride, hipStream_t st);
+// p_v = r_v + beta_v p_v
+void bcg_p(int kx, int kp, void* p, const void* r, const SlotDesc* slots, int nslots, int blocks,
+           const double* scal, hipStream_t st);
+// Per-slot reduction of the partials (count: nhop if from_hop, else nb) and
+// CG scalar update, one block per slot:
+//  mode 0: RR = RR0 = sum; STOP = tol2 * sum; ITERS = 0;
+//          DONE = (sum == 0 || outer_done[v]); NANFLAG = !finite(sum)
+//  mode 1: QQ = sum; ALPHA = RR / QQ
+//  mode 2: RRNEW = sum; BETA = sum / RR; RROLD = RR; RR = sum; ITERS += 1;
+//          DONE = (sum <= STOP); non-finite: NANFLAG = DONE = 1
+//  mode 4: TMP = sum (any slot, done or not)
+void bfinalize(const double* partial, long pstride, const SlotDesc* slots, int nslots, double* scal, int mode,
+               int from_hop, double tol2, const int* outer_done, hipStream_t st);
+
+}  // namespace dwf

@@ -1,0 +1,223 @@
+// Slot-aware vector kernels for batched solves; see slot_blas.h.
+#include "slot_blas.h"
+#include "blas.h"
+#include "dwf_internal.h"
+#include "precision.h"
+
+namespace dwf {
+
+constexpr int BT = 256;
+
+__device__ __forceinline__ double bsum(double v, double* red) {
+#pragma unroll
+    for (int off = 32; off >= 1; off >>= 1) v += __shfl_xor(v, off, 64);
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    if (lane == 0) red[w] = v;
+    __syncthreads();
+    double t = 0.0;
+    if (threadIdx.x == 0)
+        for (int i = 0; i < BT / 64; ++i) t += red[i];
+    return t;
+}
+
+// slot of a block (binary search over block0, wave-uniform)
+__device__ __forceinline__ int find_slot(const SlotDesc* __restrict__ slots, int nslots, int b) {
+    int lo = 0, hi = nslots - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (slots[mid].block0 <= b) lo = mid; else hi = mid - 1;
+    }
+    return lo;
+}
+
+template <class S>
+__global__ __launch_bounds__(BT) void bnorm2_kernel(const void* x, const SlotDesc* __restrict__ slots, int nslots,
+                                                    double* partial, long pstride, const double* scal) {
+    __shared__ double red[BT / 64];
+    const int v = find_slot(slots, nslots, blockIdx.x);
+    const SlotDesc d = slots[v];
+    const int b = blockIdx.x - d.block0;
+    double acc = 0.0;
+    for (long i = (long)b * BT + threadIdx.x; i < d.n; i += (long)d.nb * BT) {
+        typename Traits<S>::R re, im;
+        cload<S>(x, d.off + i, re, im);
+        acc += double(re) * double(re) + double(im) * double(im);
+    }
+    const double t = bsum(acc, red);
+    if (threadIdx.x == 0) partial[(long)v * pstride + b] = t;
+}
+
+template <class SX, class SP>
+__global__ __launch_bounds__(BT) void bcg_xr_kernel(void* x, void* r, const void* p, const void* w,
+                                                    const SlotDesc* __restrict__ slots, int nslots,
+                                                    const double* scal, double* partial, long pstride) {
+    __shared__ double red[BT / 64];
+    const int v = find_slot(slots, nslots, blockIdx.x);
+    const SlotDesc d = slots[v];
+    const int b = blockIdx.x - d.block0;
+    const double* sv = scal + (long)v * CG_NSLOTS;
+    if (sv[CG_DONE] != 0.0) return;   // block-uniform
+    using RX = typename Traits<SX>::R;
+    const RX a = RX(sv[CG_ALPHA]);
+    double acc = 0.0;
+    for (long i = (long)b * BT + threadIdx.x; i < d.n; i += (long)d.nb * BT) {
+        const long k = d.off + i;
+        typename Traits<SP>::R pr, pi, wr, wi;
+        RX xr, xi, rr, ri;
+        cload<SP>(p, k, pr, pi);
+        cload<SP>(w, k, wr, wi);
+        cload<SX>(x, k, xr, xi);
+        cload<SX>(r, k, rr, ri);
+        xr += a * RX(pr); xi += a * RX(pi);
+        rr -= a * RX(wr); ri -= a * RX(wi);
+        cstore<SX>(x, k, xr, xi);
+        cstore<SX>(r, k, rr, ri);
+        acc += double(rr) * double(rr) + double(ri) * double(ri);
+    }
+    const double t = bsum(acc, red);
+    if (threadIdx.x == 0) partial[(long)v * pstride + b] = t;
+}
+
+template <class SR, class SP>
+__global__ __launch_bounds__(BT) void bcg_p_kernel(void* p, const void* r, const SlotDesc* __restrict__ slots,
+                                                   int nslots, const double* scal) {
+    const int v = find_slot(slots, nslots, blockIdx.x);
+    const SlotDesc d = slots[v];
+    const int b = blockIdx.x - d.block0;
+    const double* sv = scal + (long)v * CG_NSLOTS;
+    if (sv[CG_DONE] != 0.0) return;
+    using RP = typename Traits<SP>::R;
+    const RP be = RP(sv[CG_BETA]);
+    for (long i = (long)b * BT + threadIdx.x; i < d.n; i += (long)d.nb * BT) {
+        const long k = d.off + i;
+        typename Traits<SR>::R rr, ri;
+        RP pr, pi;
+        cload<SR>(r, k, rr, ri);
+        cload<SP>(p, k, pr, pi);
+        cstore<SP>(p, k, RP(rr) + be * pr, RP(ri) + be * pi);
+    }
+}
+
+__global__ __launch_bounds__(BT) void bfinalize_kernel(const double* partial, long pstride,
+                                                       const SlotDesc* __restrict__ slots, double* scal, int mode,
+                                                       int from_hop, double tol2, const int* outer_done) {
+    __shared__ double red[BT];
+    const int v = blockIdx.x;
+    const SlotDesc d = slots[v];
+    double* sv = scal + (long)v * CG_NSLOTS;
+    if ((mode == 1 || mode == 2) && sv[CG_DONE] != 0.0) return;
+    const int np = from_hop ? d.nhop : d.nb;
+    const double* pp = partial + (long)v * pstride;
+    double acc = 0.0;
+    for (int i = threadIdx.x; i < np; i += BT) acc += pp[i];
+    red[threadIdx.x] = acc;
+    __syncthreads();
+    for (int h = BT / 2; h >= 1; h >>= 1) {
+        if ((int)threadIdx.x < h) red[threadIdx.x] += red[threadIdx.x + h];
+        __syncthreads();
+    }
+    if (threadIdx.x != 0) return;
+    const double sum = red[0];
+    const bool fin = isfinite(sum);
+    if (mode == 0) {
+        sv[CG_RR] = sum;
+        sv[CG_RR0] = sum;
+        sv[CG_STOP] = tol2 * sum;
+        sv[CG_ITERS] = 0.0;
+        sv[CG_NANFLAG] = fin ? 0.0 : 1.0;
+        sv[CG_DONE] = (!fin || sum == 0.0 || (outer_done && outer_done[v])) ? 1.0 : 0.0;
+    } else if (mode == 1) {
+        sv[CG_QQ] = sum;
+        sv[CG_ALPHA] = (sum > 0.0 && fin) ? sv[CG_RR] / sum : 0.0;
+        if (!fin) { sv[CG_NANFLAG] = 1.0; sv[CG_DONE] = 1.0; }
+    } else if (mode == 2) {
+        sv[CG_RRNEW] = sum;
+        sv[CG_BETA] = sv[CG_RR] > 0.0 ? sum / sv[CG_RR] : 0.0;
+        sv[CG_RROLD] = sv[CG_RR];
+        sv[CG_RR] = sum;
+        sv[CG_ITERS] += 1.0;
+        if (!fin) { sv[CG_NANFLAG] = 1.0; sv[CG_DONE] = 1.0; }
+        else if (sum <= sv[CG_STOP]) sv[CG_DONE] = 1.0;
+    } else {
+        sv[CG_TMP] = sum;
+        if (!fin) sv[CG_NANFLAG] = 1.0;
+    }
+}
+
+// ---------------------------------------------------------------------
+int slot_blocks(long n) {
+    long b = (n + BT * 4 - 1) / (BT * 4);   // about 4 elements per thread
+    if (b > 1024) b = 1024;
+    return (int)(b < 1 ? 1 : b);
+}
+
+#define BDISPATCH1(kind, F, ...)                                             \
+    switch (kind) {                                                          \
+        case ST_F64: F<double>(__VA_ARGS__); break;                          \
+        case ST_F32: F<float>(__VA_ARGS__); break;                           \
+        case ST_BF16: F<bf16s>(__VA_ARGS__); break;                          \
+        default: throw Error{DWF_EINVAL, "bad storage kind"};                \
+    }
+
+template <class S>
+static void bnorm2_t(const void* x, const SlotDesc* slots, int nslots, int blocks, double* partial, long pstride,
+                     const double* scal, hipStream_t st) {
+    hipLaunchKernelGGL(bnorm2_kernel<S>, dim3(blocks), dim3(BT), 0, st, x, slots, nslots, partial, pstride, scal);
+}
+void bnorm2(int kind, const void* x, const SlotDesc* slots, int nslots, int blocks, double* partial, long pstride,
+            const double* scal, hipStream_t st) {
+    BDISPATCH1(kind, bnorm2_t, x, slots, nslots, blocks, partial, pstride, scal, st);
+    DWF_HIP(hipGetLastError());
+}
+
+template <class SX, class SP>
+static void bcg_xr_t2(void* x, void* r, const void* p, const void* w, const SlotDesc* slots, int nslots, int blocks,
+                      const double* scal, double* partial, long pstride, hipStream_t st) {
+    hipLaunchKernelGGL((bcg_xr_kernel<SX, SP>), dim3(blocks), dim3(BT), 0, st, x, r, p, w, slots, nslots, scal,
+                       partial, pstride);
+}
+template <class SX>
+static void bcg_xr_t1(int kp, void* x, void* r, const void* p, const void* w, const SlotDesc* slots, int nslots,
+                      int blocks, const double* scal, double* partial, long pstride, hipStream_t st) {
+    switch (kp) {
+        case ST_F64: bcg_xr_t2<SX, double>(x, r, p, w, slots, nslots, blocks, scal, partial, pstride, st); break;
+        case ST_F32: bcg_xr_t2<SX, float>(x, r, p, w, slots, nslots, blocks, scal, partial, pstride, st); break;
+        case ST_BF16: bcg_xr_t2<SX, bf16s>(x, r, p, w, slots, nslots, blocks, scal, partial, pstride, st); break;
+        default: throw Error{DWF_EINVAL, "bad storage kind"};
+    }
+}
+void bcg_xr(int kx, int kp, void* x, void* r, const void* p, const void* w, const SlotDesc* slots, int nslots,
+            int blocks, const double* scal, double* partial, long pstride, hipStream_t st) {
+    BDISPATCH1(kx, bcg_xr_t1, kp, x, r, p, w, slots, nslots, blocks, scal, partial, pstride, st);
+    DWF_HIP(hipGetLastError());
+}
+
+template <class SR, class SP>
+static void bcg_p_t2(void* p, const void* r, const SlotDesc* slots, int nslots, int blocks, const double* scal,
+                     hipStream_t st) {
+    hipLaunchKernelGGL((bcg_p_kernel<SR, SP>), dim3(blocks), dim3(BT), 0, st, p, r, slots, nslots, scal);
+}
+template <class SR>
+static void bcg_p_t1(int kp, void* p, const void* r, const SlotDesc* slots, int nslots, int blocks,
+                     const double* scal, hipStream_t st) {
+    switch (kp) {
+        case ST_F64: bcg_p_t2<SR, double>(p, r, slots, nslots, blocks, scal, st); break;
+        case ST_F32: bcg_p_t2<SR, float>(p, r, slots, nslots, blocks, scal, st); break;
+        case ST_BF16: bcg_p_t2<SR, bf16s>(p, r, slots, nslots, blocks, scal, st); break;
+        default: throw Error{DWF_EINVAL, "bad storage kind"};
+    }
+}
+void bcg_p(int kx, int kp, void* p, const void* r, const SlotDesc* slots, int nslots, int blocks,
+           const double* scal, hipStream_t st) {
+    BDISPATCH1(kx, bcg_p_t1, kp, p, r, slots, nslots, blocks, scal, st);
+    DWF_HIP(hipGetLastError());
+}
+
+void bfinalize(const double* partial, long pstride, const SlotDesc* slots, int nslots, double* scal, int mode,
+               int from_hop, double tol2, const int* outer_done, hipStream_t st) {
+    hipLaunchKernelGGL(bfinalize_kernel, dim3(nslots), dim3(BT), 0, st, partial, pstride, slots, scal, mode,
+                       from_hop, tol2, outer_done);
+    DWF_HIP(hipGetLastError());
+}
+
+}  // namespace dwf

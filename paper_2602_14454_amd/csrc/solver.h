@@ -1,6 +1,8 @@
 // CG workspace and solver entry points (solver.cpp).
 #pragma once
 
+#include <string>
+
 #include "dwf_internal.h"
 
 namespace dwf {
@@ -23,6 +25,15 @@ int solve(const dwf_op* op, void* x5, const void* b5, const dwf_solve_params* pr
           hipStream_t st);
 double true_residual(const dwf_op* op, const void* x5, const void* b5, hipStream_t st);
 double residual_4d(const dwf_op* op, const void* x4, const void* b4, double tol_inner, hipStream_t st);
+
+// batch.cpp: batched solves and the tile autotuner of the work-list hop
+int solve_batch(int n, const dwf_op* const* ops, void* const* x5, const void* const* b5, const int* nrhs,
+                const dwf_solve_params* prm, dwf_solve_info* infos, hipStream_t st);
+void autotune_batch(int n, const dwf_op* const* ops, const int* nrhs, int kp, int force, int* nrb, int* order,
+                    double* ms, hipStream_t st);
+bool tune_get(const std::string& key, int* nrb, int* order, double* ms);
+void tune_put(const std::string& key, int nrb, int order, double ms);
+void tune_forget();
 
 // lanczos.cpp: extreme eigenvalues of D^dag D^ (thick-restart Lanczos, FP64)
 void lanczos_extremes(const dwf_op* op, int m, int keep, int max_restarts, double tol, double* lmin, double* lmax,
