@@ -66,6 +66,155 @@ def source_hash():
     return h.hexdigest()[:16]
 
 
+# Batched workloads.  (a) the 12 spin-colour point sources at the origin of a
+# propagator on 16^3x32, Ls = 12; (b) 8 independent lattices of uneven size,
+# Ls and mass, one Gaussian 4D source each.  Both: M0 = 1.6, Shamir, Neff
+# alpha = 0.5, links exp(i 0.5 H) + 3 stout steps rho = 0.1.
+BATCH_A = dict(dims=(16, 16, 16, 32), Ls=12, M0=1.6, m=0.01, alpha=0.5, seed=31)
+BATCH_B = [((8, 8, 8, 8), 8, 0.05), ((8, 8, 8, 16), 12, 0.03), ((12, 12, 12, 12), 16, 0.02),
+           ((12, 12, 12, 24), 8, 0.005), ((16, 16, 16, 16), 12, 0.01), ((16, 16, 16, 24), 16, 0.005),
+           ((16, 16, 16, 32), 8, 0.02), ((16, 16, 16, 32), 16, 0.05)]
+
+
+def hop4_bytes(items, cb):
+    """Algorithmic HBM bytes of the four fused hops of D^dag D^ over a batch:
+    per site and right-hand side 24 Ls reals in + 24 Ls out for hops 1 and 3,
+    one more 24 Ls input for hops 2 and 4 (the local term), and 8 links of
+    18 reals per site per hop, read once per operator (shared by its RHS)."""
+    w = cb / 2.0
+    return sum(w * (V // 2) * (240.0 * Ls * k + 4 * 144.0) for V, Ls, k in items)
+
+
+def run_batch(args):
+    import numpy as np
+    import torch
+
+    import dwfgen
+    import paper_2602_14454_amd as dwf
+
+    dev = "cuda:0"
+    out = {"metric": "time to 1e-10 true 5D residual per batch (b4 resident -> x4 resident), batched vs "
+                     "sequential single solves vs FP64 CGNR", "unit": "s", "higher_is_better": False,
+           "n_gpus": 1, "data": "synthetic", "dtype": "f32"}
+
+    def solve_set(ops, b5s, x5s, nrhs, prm, batched):
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        if batched:
+            st, infos = dwf.solve_batch(ops, x5s, b5s, nrhs, prm)
+        else:
+            infos = []
+            for op, b, x, k in zip(ops, b5s, x5s, nrhs):
+                for j in range(k):
+                    st, info = op.solve(x[j], b[j], prm)
+                    infos.append(info)
+        torch.cuda.synchronize()
+        return time.perf_counter() - t, infos
+
+    def summarize(dt, infos):
+        return {"seconds": dt, "iters": [f.iters for f in infos],
+                "max_true_res5": max(f.true_res5 for f in infos),
+                "all_converged": all(bool(f.converged) for f in infos)}
+
+    p_dc = dwf.default_params(algo=dwf.ALGO_DC, inner_prec=dwf.F32, check_every=8, tol=1e-10)
+    p_64 = dwf.default_params(tol=1e-10, check_every=8)
+
+    # (a) 12 point sources
+    a = BATCH_A
+    dims, Ls = a["dims"], a["Ls"]
+    V = int(np.prod(dims))
+    U = dwfgen.make_links(dims, 0.5, a["seed"], rho=0.1, nsmear=3)
+    lat = dwf.Lattice(dims)
+    lat.set_gauge(U)
+    op = dwf.Op(lat, Ls, a["M0"], a["m"], 1.0, 0.0, a["alpha"])
+    b4 = torch.stack([torch.from_numpy(dwfgen.point_source_4d(dims, s, c)) for s in range(4) for c in range(3)]).to(dev)
+    b5 = torch.empty((12, Ls, V, 4, 3), dtype=torch.complex128, device=dev)
+    x5 = torch.zeros_like(b5)
+    x4 = torch.empty((12, V, 4, 3), dtype=torch.complex128, device=dev)
+    nrb, order, hop_ms = dwf.autotune_batch([op], [12], dwf.F32, force=True)
+    log(f"[a] tuner: {nrb} RHS per block, order {order}, four hops {hop_ms:.3f} ms")
+
+    def full_a(batched, prm):
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        for k in range(12):
+            op.source_4d(b5[k], b4[k])
+        x5.zero_()
+        dt, infos = solve_set([op], [b5], [x5], [12], prm, batched)
+        for k in range(12):
+            op.project_4d(x4[k], x5[k])
+        torch.cuda.synchronize()
+        return time.perf_counter() - t, infos
+
+    full_a(True, p_dc)   # warm-up (graph capture, allocations)
+    ta, ia = full_a(True, p_dc)
+    res4 = [op.residual_4d(x4[k], b4[k]) for k in (0, 5, 11)]
+    x4_batch = x4.clone()
+    ts, is_ = full_a(False, p_dc)
+    t64, i64 = full_a(False, p_64)
+    err = max((torch.linalg.vector_norm(x4_batch[k] - x4[k]) / torch.linalg.vector_norm(x4[k])).item()
+              for k in range(12))
+    log(f"[a] batched {ta:.3f}s, sequential DC {ts:.3f}s, sequential FP64 {t64:.3f}s")
+    bytes_a = hop4_bytes([(V, Ls, 12)], 8)
+    out["point_sources_12"] = {
+        "workload": f"16^3x32 Ls=12 M0=1.6 m=0.01 Shamir Neff alpha=0.5, 12 point sources at the origin",
+        "batched_dc_f32": summarize(ta, ia), "sequential_dc_f32": summarize(ts, is_),
+        "sequential_fp64_cgnr": summarize(t64, i64),
+        "speedup_vs_sequential_dc": ts / ta, "speedup_vs_fp64": t64 / ta,
+        "res4_sampled": res4, "x4_rel_err_vs_fp64_max": err,
+        "tiles": {"rhs_per_block": nrb, "order": order},
+        "hop4": {"ms": hop_ms, "bytes": bytes_a, "GBps": bytes_a / hop_ms / 1e6},
+    }
+
+    # (b) uneven batch of 8 lattices
+    ops, b4s, b5s, x5s, lats = [], [], [], [], []
+    t0 = time.time()
+    for k, (d, ls, m) in enumerate(BATCH_B):
+        Uk = dwfgen.make_links(d, 0.5, 401 + k, rho=0.1, nsmear=3)
+        lk = dwf.Lattice(d)
+        lk.set_gauge(Uk)
+        lats.append(lk)
+        ok = dwf.Op(lk, ls, 1.6, m, 1.0, 0.0, 0.5)
+        ops.append(ok)
+        Vk = int(np.prod(d))
+        b4k = torch.from_numpy(dwfgen.gaussian_source_4d(d, 501 + k)).to(dev)
+        b5k = torch.empty((1, ls, Vk, 4, 3), dtype=torch.complex128, device=dev)
+        ok.source_4d(b5k[0], b4k)
+        b4s.append(b4k)
+        b5s.append(b5k)
+        x5s.append(torch.zeros_like(b5k))
+    log(f"[b] inputs in {time.time() - t0:.1f}s")
+    nrhs = [1] * len(ops)
+    nrb_b, order_b, hop_ms_b = dwf.autotune_batch(ops, nrhs, dwf.F32, force=True)
+    res = {}
+    for name, prm, batched in (("batched_dc_f32", p_dc, True), ("batched_dc_f32_nograph", None, True),
+                               ("sequential_dc_f32", p_dc, False), ("sequential_fp64_cgnr", p_64, False)):
+        if prm is None:
+            prm = dwf.default_params(algo=dwf.ALGO_DC, inner_prec=dwf.F32, check_every=8, tol=1e-10, use_graph=0)
+        for x in x5s:
+            x.zero_()
+        if batched:
+            solve_set(ops, b5s, x5s, nrhs, prm, True)   # warm-up
+            for x in x5s:
+                x.zero_()
+        dt, infos = solve_set(ops, b5s, x5s, nrhs, prm, batched)
+        res[name] = summarize(dt, infos)
+        log(f"[b] {name}: {dt:.3f}s iters {res[name]['iters']}")
+    bytes_b = hop4_bytes([(int(np.prod(d)), ls, 1) for d, ls, _ in BATCH_B], 8)
+    res["speedup_vs_sequential_dc"] = res["sequential_dc_f32"]["seconds"] / res["batched_dc_f32"]["seconds"]
+    res["speedup_vs_fp64"] = res["sequential_fp64_cgnr"]["seconds"] / res["batched_dc_f32"]["seconds"]
+    res["graph_gain"] = res["batched_dc_f32_nograph"]["seconds"] / res["batched_dc_f32"]["seconds"]
+    res["workload"] = ("8 lattices (dims; Ls; m): " + ", ".join(f"({'x'.join(map(str, d))}; {ls}; {m})"
+                                                              for d, ls, m in BATCH_B)
+                       + "; M0=1.6 Shamir Neff alpha=0.5; one Gaussian 4D source each")
+    res["tiles"] = {"rhs_per_block": nrb_b, "order": order_b}
+    res["hop4"] = {"ms": hop_ms_b, "bytes": bytes_b, "GBps": bytes_b / hop_ms_b / 1e6}
+    out["uneven_batch_8"] = res
+    out["value"] = ta
+    out["config"] = {"workload": out["point_sources_12"]["workload"]}
+    print(json.dumps(out))
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -78,6 +227,9 @@ def main():
     ap.add_argument("--hop-only", action="store_true", help="only time the fused hop (for counter runs)")
     ap.add_argument("--cpu-iters", type=int, default=3)
     ap.add_argument("--hop-reps", type=int, default=200)
+    ap.add_argument("--batch", action="store_true",
+                    help="run the batched workloads instead: 12 point sources on 16^3x32 Ls=12, and an uneven "
+                         "batch of 8 lattices; each against sequential single solves and FP64 CGNR")
     ap.add_argument("--spectrum", action="store_true",
                     help="also measure lambda_min, lambda_max and kappa of D^dag D^ (Lanczos) for alpha and 1")
     args = ap.parse_args()
@@ -93,6 +245,9 @@ def main():
     import paper_2602_14454_amd as dwf
 
     torch.cuda.set_device(0)
+    if args.batch:
+        run_batch(args)
+        return
     dev = "cuda:0"
     cfg = dict(CONFIGS[args.config])
     dims, Ls = cfg["dims"], cfg["Ls"]

@@ -261,7 +261,7 @@ struct Batch {
     long pstride = 0;    // partials per slot
     int vblocks = 0;     // vector-kernel blocks of a slot-table launch
     int nslots = 0;
-    DevBuf slots_dev, partial, scal, outer_done;
+    DevBuf slots_dev, partial, scal, inner_tol2;
 };
 
 void make_batch(Batch& B, int n, const dwf_op* const* ops, const int* nrhs) {
@@ -301,7 +301,7 @@ void make_batch(Batch& B, int n, const dwf_op* const* ops, const int* nrhs) {
     DWF_HIP(hipMemcpy(B.slots_dev.p, B.slots.data(), B.slots.size() * sizeof(SlotDesc), hipMemcpyHostToDevice));
     B.partial.alloc((size_t)B.pstride * B.nslots * sizeof(double));
     B.scal.alloc((size_t)B.nslots * CG_NSLOTS * sizeof(double));
-    B.outer_done.alloc((size_t)B.nslots * sizeof(int));
+    B.inner_tol2.alloc((size_t)B.nslots * sizeof(double));
 }
 
 struct Inner {
@@ -328,11 +328,11 @@ void iteration(const Batch& B, Inner& I, hipStream_t st) {
     double* sc = B.scal.as<double>();
     I.hops.stage(0, st);
     I.hops.stage(1, st);
-    bfinalize(pp, B.pstride, sd, B.nslots, sc, 1, 1, 0.0, nullptr, st);
+    bfinalize(pp, B.pstride, sd, B.nslots, sc, 1, 1, nullptr, st);
     I.hops.stage(2, st);
     I.hops.stage(3, st);
     bcg_xr(I.kx, I.kp, I.x.p, I.r.p, I.p.p, I.w.p, sd, B.nslots, B.vblocks, sc, pp, B.pstride, st);
-    bfinalize(pp, B.pstride, sd, B.nslots, sc, 2, 0, 0.0, nullptr, st);
+    bfinalize(pp, B.pstride, sd, B.nslots, sc, 2, 0, nullptr, st);
     bcg_p(I.kx, I.kp, I.p.p, I.r.p, sd, B.nslots, B.vblocks, sc, st);
 }
 
@@ -397,6 +397,8 @@ void choose_tiles(const Batch& B, Inner& I, int autotune, hipStream_t st, int* n
                 if (mx == 1) continue;   // same schedule as order 0
             }
             const double ms = time_hops(B, I, nb, od, st);
+            if (trace_on())
+                std::fprintf(stderr, "dwf trace: tune %s nrb %d order %d four hops %.4f ms\n", key.c_str(), nb, od, ms);
             if (ms < best) {
                 best = ms;
                 *nrb = nb;
@@ -446,9 +448,8 @@ int solve_batch(int n, const dwf_op* const* ops, void* const* x5, const void* co
     const int ns = B.nslots;
     PinnedD hs((size_t)ns * CG_NSLOTS);
     std::vector<int> odone(ns, 0);
-    int* odone_h = nullptr;
-    DWF_HIP(hipHostMalloc(reinterpret_cast<void**>(&odone_h), sizeof(int) * ns, hipHostMallocDefault));
-    std::unique_ptr<int, void (*)(int*)> odone_guard(odone_h, [](int* q) { (void)hipHostFree(q); });
+    std::vector<double> req(ns, 0.0), fr(ns, 1.0);
+    PinnedD itol2_h(ns);
 
     Stream cs;
     Event ev_in, e0, e1;
@@ -469,7 +470,7 @@ int solve_batch(int n, const dwf_op* const* ops, void* const* x5, const void* co
     };
     auto slot_norms = [&](int kind, const void* f, std::vector<double>& out) {
         bnorm2(kind, f, sd, ns, B.vblocks, pp, B.pstride, sc, cs.s);
-        bfinalize(pp, B.pstride, sd, ns, sc, 4, 0, 0.0, nullptr, cs.s);
+        bfinalize(pp, B.pstride, sd, ns, sc, 4, 0, nullptr, cs.s);
         read_scal();
         out.resize(ns);
         for (int v = 0; v < ns; ++v) out[v] = hs.h[(size_t)v * CG_NSLOTS + CG_TMP];
@@ -517,11 +518,15 @@ int solve_batch(int n, const dwf_op* const* ops, void* const* x5, const void* co
         convert(I->kx, ST_F64, I->r.p, te.p, N, cs.s);
         convert(I->kp, I->kx, I->p.p, I->r.p, N, cs.s);
         DWF_HIP(hipMemsetAsync(I->x.p, 0, complex_bytes_of(I->kx) * N, cs.s));
-        for (int v = 0; v < ns; ++v) odone_h[v] = odone[v];
-        DWF_HIP(hipMemcpyAsync(B.outer_done.p, odone_h, sizeof(int) * ns, hipMemcpyHostToDevice, cs.s));
         const double itol = inner_tol_of(I->kp);
+        for (int v = 0; v < ns; ++v) {
+            const bool plain = I->kp == ST_F64 && outer[v] == 0;
+            req[v] = plain ? itol : dc_target(tol, rel5[v], I->kp, itol, fr[v]);
+            itol2_h.h[v] = odone[v] ? -1.0 : req[v] * req[v];
+        }
+        DWF_HIP(hipMemcpyAsync(B.inner_tol2.p, itol2_h.h, sizeof(double) * ns, hipMemcpyHostToDevice, cs.s));
         bnorm2(I->kx, I->r.p, sd, ns, B.vblocks, pp, B.pstride, sc, cs.s);
-        bfinalize(pp, B.pstride, sd, ns, sc, 0, 0, itol * itol, B.outer_done.as<int>(), cs.s);
+        bfinalize(pp, B.pstride, sd, ns, sc, 0, 0, B.inner_tol2.as<double>(), cs.s);
         // inner iterations: graph replays of check_every iterations
         const bool use_graph = prm->use_graph != 0;
         if (use_graph && I->graph_k != check_every) capture(B, *I, check_every, cs.s);
@@ -562,7 +567,12 @@ int solve_batch(int n, const dwf_op* const* ops, void* const* x5, const void* co
         bool stagnated = false;
         for (int v = 0; v < ns; ++v) {
             if (odone[v]) continue;
+            const double old5 = rel5[v];
             rel5[v] = std::sqrt(t2[v] / b2[v]);
+            fr[v] = dc_ratio(rel5[v] / old5, req[v]);
+            if (trace_on())
+                std::fprintf(stderr, "dwf trace: batch step %d slot %d prec %d requested %.3e iters %d rel5 %.3e\n",
+                             total_rounds, v, I->kp, req[v], iters[v], rel5[v]);
             if (rel5[v] <= tol) odone[v] = 1;
             else if (rel5[v] > 0.5 * prev[v] && I->kp != ST_F64) stagnated = true;
             prev[v] = rel5[v];

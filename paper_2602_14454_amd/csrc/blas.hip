@@ -274,7 +274,7 @@ __global__ void cg_p_kernel(void* p, const void* r, long n, const double* beta) 
 //  mode 1 (alpha): s[QQ] = sum; s[ALPHA] = s[RR] / sum (0 if sum <= 0)
 //  mode 2 (beta):  s[RRNEW] = sum; s[BETA] = sum / s[RR]; s[RROLD] = s[RR]; s[RR] = sum
 //  mode 3 (beta after replacing r): s[RRNEW] = s[RR] = sum; s[BETA] = sum / s[RROLD]
-// A non-finite sum sets s[NANFLAG] = 1.
+// In modes 1-3 a non-finite sum sets s[NANFLAG] = 1.
 __global__ void finalize_kernel(const double* partial, int nparts, int stride, double* out, int mode) {
     __shared__ double red[BLAS_THREADS];
     double acc = 0.0;
@@ -287,7 +287,9 @@ __global__ void finalize_kernel(const double* partial, int nparts, int stride, d
     }
     if (threadIdx.x == 0) {
         const double sum = red[0];
-        if (!isfinite(sum)) out[CG_NANFLAG] = 1.0;
+        // modes 1-3 address a whole CG scalar block; mode 0 writes out[0] only
+        // (a non-finite sum is visible in the value itself)
+        if (mode != 0 && !isfinite(sum)) out[CG_NANFLAG] = 1.0;
         if (mode == 0) {
             out[0] = sum;
         } else if (mode == 1) {

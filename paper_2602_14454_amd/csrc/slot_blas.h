@@ -39,13 +39,13 @@ void bcg_p(int kx, int kp, void* p, const void* r, const SlotDesc* slots, int ns
            const double* scal, hipStream_t st);
 // Per-slot reduction of the partials (count: nhop if from_hop, else nb) and
 // CG scalar update, one block per slot:
-//  mode 0: RR = RR0 = sum; STOP = tol2 * sum; ITERS = 0;
-//          DONE = (sum == 0 || outer_done[v]); NANFLAG = !finite(sum)
+//  mode 0: RR = RR0 = sum; STOP = tol2[v] * sum; ITERS = 0;
+//          DONE = (sum == 0 || tol2[v] < 0); NANFLAG = !finite(sum)
 //  mode 1: QQ = sum; ALPHA = RR / QQ
 //  mode 2: RRNEW = sum; BETA = sum / RR; RROLD = RR; RR = sum; ITERS += 1;
 //          DONE = (sum <= STOP); non-finite: NANFLAG = DONE = 1
 //  mode 4: TMP = sum (any slot, done or not)
 void bfinalize(const double* partial, long pstride, const SlotDesc* slots, int nslots, double* scal, int mode,
-               int from_hop, double tol2, const int* outer_done, hipStream_t st);
+               int from_hop, const double* tol2, hipStream_t st);
 
 }  // namespace dwf

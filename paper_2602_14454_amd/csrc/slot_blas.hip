@@ -100,7 +100,7 @@ __global__ __launch_bounds__(BT) void bcg_p_kernel(void* p, const void* r, const
 
 __global__ __launch_bounds__(BT) void bfinalize_kernel(const double* partial, long pstride,
                                                        const SlotDesc* __restrict__ slots, double* scal, int mode,
-                                                       int from_hop, double tol2, const int* outer_done) {
+                                                       int from_hop, const double* tol2) {
     __shared__ double red[BT];
     const int v = blockIdx.x;
     const SlotDesc d = slots[v];
@@ -122,10 +122,11 @@ __global__ __launch_bounds__(BT) void bfinalize_kernel(const double* partial, lo
     if (mode == 0) {
         sv[CG_RR] = sum;
         sv[CG_RR0] = sum;
-        sv[CG_STOP] = tol2 * sum;
+        const double t2 = tol2 ? tol2[v] : 0.0;
+        sv[CG_STOP] = t2 * sum;
         sv[CG_ITERS] = 0.0;
         sv[CG_NANFLAG] = fin ? 0.0 : 1.0;
-        sv[CG_DONE] = (!fin || sum == 0.0 || (outer_done && outer_done[v])) ? 1.0 : 0.0;
+        sv[CG_DONE] = (!fin || sum == 0.0 || t2 < 0.0) ? 1.0 : 0.0;
     } else if (mode == 1) {
         sv[CG_QQ] = sum;
         sv[CG_ALPHA] = (sum > 0.0 && fin) ? sv[CG_RR] / sum : 0.0;
@@ -214,9 +215,9 @@ void bcg_p(int kx, int kp, void* p, const void* r, const SlotDesc* slots, int ns
 }
 
 void bfinalize(const double* partial, long pstride, const SlotDesc* slots, int nslots, double* scal, int mode,
-               int from_hop, double tol2, const int* outer_done, hipStream_t st) {
+               int from_hop, const double* tol2, hipStream_t st) {
     hipLaunchKernelGGL(bfinalize_kernel, dim3(nslots), dim3(BT), 0, st, partial, pstride, slots, scal, mode,
-                       from_hop, tol2, outer_done);
+                       from_hop, tol2);
     DWF_HIP(hipGetLastError());
 }
 

@@ -21,6 +21,12 @@ struct CgWork {
 int cgnr(const dwf_op* op, CgWork& W, const void* b_kp, double tol_rel, int maxiter, int check_every,
          hipStream_t st, double* final_rel, bool* nan_seen);
 
+// defect-correction inner target and step ratio (solver.cpp); DWF_TRACE in
+// the environment prints one line per outer step to stderr
+double dc_target(double tol, double rel5, int kp, double standard, double f);
+double dc_ratio(double achieved, double requested);
+bool trace_on();
+
 int solve(const dwf_op* op, void* x5, const void* b5, const dwf_solve_params* prm, dwf_solve_info* info,
           hipStream_t st);
 double true_residual(const dwf_op* op, const void* x5, const void* b5, hipStream_t st);
