@@ -59,13 +59,17 @@ typedef enum { DWF_FULL5D = 0, DWF_EVEN5D = 1 } dwf_space;
 typedef enum {
     DWF_ALGO_CGNR = 0,         /* FP64 CGNR (restarted if the 5D residual is not yet met)        */
     DWF_ALGO_DC = 1,           /* FP64 defect correction around restarted low-precision CGNR     */
-    DWF_ALGO_FGCR_LEARNED = 2, /* flexible GCR with the learned preconditioner (ptc_model)       */
+    DWF_ALGO_FGCR_LEARNED = 2, /* FP64 defect correction around FP32 flexible GCR on D^dag D^,    */
+                               /* right-preconditioned by the learned network (ptc_model); on  */
+                               /* NaN or stagnation the solve continues with CGNR (fallback)   */
     DWF_ALGO_MIXED = 3         /* low-precision CGNR with FP64 reliable updates (inner_tol: the  */
                                /* residual drop that triggers an update; <= 0: 0.1 FP32, 0.25 BF16) */
 } dwf_algo;
 
 typedef struct dwf_lattice dwf_lattice;
 typedef struct dwf_op dwf_op;
+typedef struct dwf_ptc dwf_ptc;             /* learned preconditioner (network weights, Adam state) */
+typedef struct dwf_ptc_pairs dwf_ptc_pairs; /* device-resident training pairs of one operator */
 
 typedef struct {
     double   tol;         /* target true relative residual of the 5D system |b5 - D x5| / |b5| */
@@ -76,8 +80,8 @@ typedef struct {
     int      check_every; /* host convergence check period of the CG loop (>= 1) */
     int      paper_mode;  /* 1: plain CGNR in inner_prec stopping at |r|^2/|D^dag b~|^2 < 1e-14
                              (Sec. 3.2 criterion), no defect correction; iteration counting only */
-    void*    ptc_model;   /* dwf_ptc handle for DWF_ALGO_FGCR_LEARNED, else NULL */
-    int      restart;     /* FGCR restart length */
+    void*    ptc_model;   /* dwf_ptc* for DWF_ALGO_FGCR_LEARNED (NULL: FGCR without preconditioner) */
+    int      restart;     /* FGCR restart length (1..64) */
     int      autotune;    /* batched solves: 0 cached tiles or defaults, 1 tune when not cached,
                              2 always re-tune */
     int      use_graph;   /* batched solves: 1 replay the CG iteration body as a HIP graph */
@@ -203,6 +207,71 @@ int dwf_residual_4d(const dwf_op* op, const void* x4, const void* b4, double tol
  * Returns DWF_OK, or DWF_NOT_CONVERGED with the best Ritz values. */
 int dwf_lanczos_extremes(const dwf_op* op, int basis, int keep, int max_restarts, double tol,
                          double* lambda_min, double* lambda_max, int* matvecs, int* converged, void* stream);
+
+/* ---- learned preconditioner ----------------------------------------
+ * A linear gauge-equivariant parallel-transport convolution network
+ * M = PTC_2 o PTC_1 (1 -> hidden -> 1 channels) used as the right
+ * preconditioner of flexible GCR on the CGNR normal equations
+ * (D^dag D^, Sec. 2.3).  One layer:
+ *   out^a(x,s) = sum_b sum_p W_p^{ab} T_p[in^b](x,s)
+ * with W_p^{ab} a complex 4x4 spin matrix and the 11 paths p = 0 (identity),
+ * 1..4 (T_{+mu} psi(x) = U_mu(x) psi(x+mu), mu = x,y,z,t), 5..8
+ * (T_{-mu} psi(x) = U_mu(x-mu)^dag psi(x-mu)), 9 and 10 (psi(s+1), psi(s-1),
+ * zero outside the fifth dimension).  The fermion boundary phase is part of
+ * the transports.  Layer 1 reads an even field and writes hidden channels on
+ * both parities; layer 2 writes the even output.  FP32 weights and
+ * activations.  Weights (host, complex64 interleaved): W1 [11][hidden][1][4][4]
+ * followed by W2 [11][1][hidden][4][4], 2*11*hidden*16 complex numbers. */
+
+/* New model: W = identity on path 0 / channel 0 of both layers plus seeded
+ * complex Gaussian noise of standard deviation init_scale; 1 <= hidden <= 64. */
+int dwf_ptc_create(int hidden, unsigned long long seed, double init_scale, dwf_ptc** out);
+void dwf_ptc_destroy(dwf_ptc* m);
+/* Training loss of the model (used by gradient, train and eval), for pairs
+ * (r, e) with r = A e, A = D^dag D^:
+ *   kind 0:           |M r - e|^2 / |e|^2                       (error loss)
+ *   kind 1 (default): |A (M r - e)|^2 / |r|^2 = |A M r - r|^2 / |r|^2
+ *                     (residual left by the right-preconditioned operator;
+ *                     costs two more applications of A per step).  The error
+ *                     loss weights the low modes a local network cannot
+ *                     invert; fitted with it, A M is not positive and FGCR
+ *                     stalls. */
+int dwf_ptc_set_loss(dwf_ptc* m, int kind);
+/* hidden channels, number of complex weights, Adam steps taken (each may be NULL) */
+int dwf_ptc_info(const dwf_ptc* m, int* hidden, int* nweights, int* steps);
+int dwf_ptc_get_weights(const dwf_ptc* m, void* weights_c64_host);
+int dwf_ptc_set_weights(dwf_ptc* m, const void* weights_c64_host);
+/* out_e = M in_e on even canonical complex128 device vectors (computed in FP32). */
+int dwf_ptc_apply(dwf_ptc* m, const dwf_op* op, void* out_e, const void* in_e, void* stream);
+/* Loss |M r - e|^2 / |e|^2 and its gradient dL/dRe W + i dL/dIm W (host,
+ * complex64, weight layout; may be NULL) for one pair of even canonical
+ * complex128 device vectors. */
+int dwf_ptc_gradient(dwf_ptc* m, const dwf_op* op, const void* r_e, const void* e_e, double* loss,
+                     void* grad_c64_host, void* stream);
+/* Training pairs from the solver itself: CGNR on the Schur system is run
+ * from 0 and at each iteration k in snap_iters the pair
+ * (r_k = D^dag D^ e_k, e_k = x* - x_k) is kept on the device in FP32.  The
+ * system is that of the 5D source b5 (canonical, device; x* by FP64 CGNR
+ * to 1e-10) or, with b5 = NULL, one with known solution: x* a seeded
+ * uniform random even field and b~ = D^ x* (k = 0 then gives the pair
+ * (D^dag D^ x*, x*) of a random error). */
+int dwf_ptc_pairs_create(const dwf_op* op, const void* b5, unsigned long long seed, int nsnap,
+                         const int* snap_iters, dwf_ptc_pairs** out, void* stream);
+/* copies pair k out as even canonical complex128 device vectors */
+int dwf_ptc_pairs_get(const dwf_ptc_pairs* p, int k, void* r_e, void* e_e, void* stream);
+void dwf_ptc_pairs_destroy(dwf_ptc_pairs* p);
+/* `steps` Adam steps (learning rate lr, betas 0.9/0.999, eps 1e-8), each on
+ * one pair drawn by a seeded counter hash over all sets; loss_history
+ * (host, `steps` doubles, may be NULL) receives the loss of every step.  The
+ * sets' operators (and lattices) must still exist. */
+int dwf_ptc_train(dwf_ptc* m, int nsets, dwf_ptc_pairs* const* sets, int steps, double lr,
+                  unsigned long long seed, double* loss_history, void* stream);
+/* mean loss over every pair of the sets */
+int dwf_ptc_eval(dwf_ptc* m, int nsets, dwf_ptc_pairs* const* sets, double* mean_loss, void* stream);
+/* Checkpoint: "DWFPTC01", hidden, Adam step, weights and Adam moments, FNV-1a
+ * checksum; load rejects a file whose checksum or size does not match. */
+int dwf_ptc_save(const dwf_ptc* m, const char* path);
+int dwf_ptc_load(const char* path, dwf_ptc** out);
 
 /* ---- measurement helpers ------------------------------------------ */
 

@@ -25,6 +25,11 @@ lexicographic order x + Lx (y + Ly (z + Lz t)).  Even-canonical vectors
 `embed_even` / `restrict_even`.
 
 Complex weight gradients are returned as dL/dRe W + i dL/dIm W.
+
+Two losses for a pair (r, e) with r = A e (A = D^dag D^, Hermitian):
+    kind 0:  |M r - e|^2 / |e|^2
+    kind 1:  |A (M r - e)|^2 / |r|^2  (= |A M r - r|^2 / |r|^2)
+The caller passes A as a function on even-canonical vectors.
 """
 from __future__ import annotations
 
@@ -152,16 +157,29 @@ def _layer_backward(U, dims, W, x, g, antiperiodic_t):
     return gW, gx
 
 
-def gradients(U, dims, W1, W2, r_even, e_even, antiperiodic_t=True):
+def loss_residual(U, dims, W1, W2, r_even, e_even, apply_A, antiperiodic_t=True):
+    y, _ = forward(U, dims, W1, W2, r_even, antiperiodic_t)
+    u = apply_A(y - e_even)
+    return float(np.vdot(u, u).real / np.vdot(r_even, r_even).real)
+
+
+def gradients(U, dims, W1, W2, r_even, e_even, antiperiodic_t=True, kind=0, apply_A=None):
     """(loss, dL/dW1, dL/dW2) by the chain rule through both layers."""
     r = embed_even(dims, r_even)[None]
     h = layer(U, dims, W1, r, antiperiodic_t)
     yfull = layer(U, dims, W2, h, antiperiodic_t)
     y = restrict_even(dims, yfull[0])
     d = y - e_even
-    e2 = np.vdot(e_even, e_even).real
-    L = float(np.vdot(d, d).real / e2)
-    gy = embed_even(dims, 2.0 * d / e2)[None]
+    if kind == 0:
+        e2 = np.vdot(e_even, e_even).real
+        L = float(np.vdot(d, d).real / e2)
+        gy = embed_even(dims, 2.0 * d / e2)[None]
+    else:
+        # L = |A d|^2 / |r|^2, dL/dy = 2 A^dag A d / |r|^2 = 2 A A d / |r|^2
+        u = apply_A(d)
+        r2 = np.vdot(r_even, r_even).real
+        L = float(np.vdot(u, u).real / r2)
+        gy = embed_even(dims, 2.0 * apply_A(u) / r2)[None]
     gW2, gh = _layer_backward(U, dims, W2, h, gy, antiperiodic_t)
     gW1, _ = _layer_backward(U, dims, W1, r, gh, antiperiodic_t)
     return L, gW1, gW2

@@ -18,6 +18,7 @@ __all__ = [
     "load", "DwfError", "SolveParams", "SolveInfo", "Lattice", "Op",
     "F64", "F32", "BF16", "FULL5D", "EVEN5D", "ALGO_CGNR", "ALGO_DC", "ALGO_FGCR_LEARNED", "ALGO_MIXED",
     "solve_batch", "autotune_batch", "tune_cache_put", "tune_cache_get", "tune_cache_reload",
+    "PtcModel", "PtcPairs",
 ]
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
@@ -81,6 +82,21 @@ SIGNATURES = {
     "dwf_tune_cache_put": (_i, [ctypes.c_char_p, _i, _i, _d]),
     "dwf_tune_cache_get": (_i, [ctypes.c_char_p, _ip, _ip, _dp]),
     "dwf_tune_cache_reload": (_i, []),
+    "dwf_ptc_create": (_i, [_i, ctypes.c_ulonglong, _d, ctypes.POINTER(_vp)]),
+    "dwf_ptc_destroy": (None, [_vp]),
+    "dwf_ptc_info": (_i, [_vp, _ip, _ip, _ip]),
+    "dwf_ptc_set_loss": (_i, [_vp, _i]),
+    "dwf_ptc_get_weights": (_i, [_vp, _vp]),
+    "dwf_ptc_set_weights": (_i, [_vp, _vp]),
+    "dwf_ptc_apply": (_i, [_vp, _vp, _vp, _vp, _vp]),
+    "dwf_ptc_gradient": (_i, [_vp, _vp, _vp, _vp, _dp, _vp, _vp]),
+    "dwf_ptc_pairs_create": (_i, [_vp, _vp, ctypes.c_ulonglong, _i, _ip, ctypes.POINTER(_vp), _vp]),
+    "dwf_ptc_pairs_get": (_i, [_vp, _i, _vp, _vp, _vp]),
+    "dwf_ptc_pairs_destroy": (None, [_vp]),
+    "dwf_ptc_train": (_i, [_vp, _i, ctypes.POINTER(_vp), _i, _d, ctypes.c_ulonglong, _dp, _vp]),
+    "dwf_ptc_eval": (_i, [_vp, _i, ctypes.POINTER(_vp), _dp, _vp]),
+    "dwf_ptc_save": (_i, [_vp, ctypes.c_char_p]),
+    "dwf_ptc_load": (_i, [ctypes.c_char_p, ctypes.POINTER(_vp)]),
     "dwf_bench_copy": (_i, [ctypes.c_size_t, _i, _dp, _vp]),
     "dwf_status_string": (ctypes.c_char_p, [_i]),
     "dwf_last_error": (ctypes.c_char_p, []),
@@ -173,6 +189,120 @@ def autotune_batch(ops, nrhs, prec=None, force=False, stream=None):
                                      ctypes.byref(a), ctypes.byref(b), ctypes.byref(ms), _stream(stream)),
            "dwf_autotune_batch")
     return a.value, b.value, ms.value
+
+
+class PtcModel:
+    """dwf_ptc: the learned gauge-equivariant preconditioner."""
+
+    def __init__(self, hidden: int = 8, seed: int = 1, init_scale: float = 0.05, _handle=None):
+        lib = load()
+        if _handle is None:
+            h = ctypes.c_void_p()
+            _check(lib.dwf_ptc_create(int(hidden), int(seed), float(init_scale), ctypes.byref(h)), "dwf_ptc_create")
+            _handle = h
+        self._h = _handle
+        hid, nw, st = ctypes.c_int(), ctypes.c_int(), ctypes.c_int()
+        _check(lib.dwf_ptc_info(self._h, ctypes.byref(hid), ctypes.byref(nw), ctypes.byref(st)), "dwf_ptc_info")
+        self.hidden, self.nweights = hid.value, nw.value
+
+    def set_loss(self, kind: int) -> None:
+        """0: |M r - e|^2/|e|^2 (error loss); 1: |A M r - r|^2/|r|^2 (residual loss)."""
+        _check(load().dwf_ptc_set_loss(self._h, int(kind)), "dwf_ptc_set_loss")
+
+    @classmethod
+    def load_file(cls, path: str) -> "PtcModel":
+        h = ctypes.c_void_p()
+        _check(load().dwf_ptc_load(path.encode(), ctypes.byref(h)), "dwf_ptc_load")
+        return cls(_handle=h)
+
+    def save(self, path: str) -> None:
+        _check(load().dwf_ptc_save(self._h, path.encode()), "dwf_ptc_save")
+
+    @property
+    def steps(self) -> int:
+        st = ctypes.c_int()
+        _check(load().dwf_ptc_info(self._h, None, None, ctypes.byref(st)), "dwf_ptc_info")
+        return st.value
+
+    def weights(self):
+        """(W1 [11][H][1][4][4], W2 [11][1][H][4][4]) as complex64 numpy arrays."""
+        import numpy as np
+        w = np.empty(self.nweights, dtype=np.complex64)
+        _check(load().dwf_ptc_get_weights(self._h, w.ctypes.data_as(ctypes.c_void_p)), "dwf_ptc_get_weights")
+        half = self.nweights // 2
+        return w[:half].reshape(11, self.hidden, 1, 4, 4), w[half:].reshape(11, 1, self.hidden, 4, 4)
+
+    def set_weights(self, W1, W2) -> None:
+        import numpy as np
+        w = np.ascontiguousarray(np.concatenate([np.asarray(W1).reshape(-1), np.asarray(W2).reshape(-1)])
+                                 .astype(np.complex64))
+        if w.size != self.nweights:
+            raise ValueError("weight count mismatch")
+        _check(load().dwf_ptc_set_weights(self._h, w.ctypes.data_as(ctypes.c_void_p)), "dwf_ptc_set_weights")
+
+    def apply(self, op, out_e, in_e, stream=None) -> None:
+        _check(load().dwf_ptc_apply(self._h, op._h, _dev_ptr(out_e), _dev_ptr(in_e), _stream(stream)),
+               "dwf_ptc_apply")
+
+    def gradient(self, op, r_e, e_e, stream=None):
+        """(loss, (G1, G2)) with G = dL/dRe W + i dL/dIm W (complex64)."""
+        import numpy as np
+        g = np.empty(self.nweights, dtype=np.complex64)
+        loss = ctypes.c_double()
+        _check(load().dwf_ptc_gradient(self._h, op._h, _dev_ptr(r_e), _dev_ptr(e_e), ctypes.byref(loss),
+                                       g.ctypes.data_as(ctypes.c_void_p), _stream(stream)), "dwf_ptc_gradient")
+        half = self.nweights // 2
+        return loss.value, (g[:half].reshape(11, self.hidden, 1, 4, 4), g[half:].reshape(11, 1, self.hidden, 4, 4))
+
+    def train(self, pair_sets, steps: int, lr: float = 1e-3, seed: int = 7, stream=None):
+        import numpy as np
+        arr = (ctypes.c_void_p * len(pair_sets))(*[p._h.value for p in pair_sets])
+        hist = np.zeros(max(int(steps), 1), dtype=np.float64)
+        _check(load().dwf_ptc_train(self._h, len(pair_sets), arr, int(steps), float(lr), int(seed),
+                                    hist.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), _stream(stream)),
+               "dwf_ptc_train")
+        return hist[: int(steps)]
+
+    def eval(self, pair_sets, stream=None) -> float:
+        arr = (ctypes.c_void_p * len(pair_sets))(*[p._h.value for p in pair_sets])
+        v = ctypes.c_double()
+        _check(load().dwf_ptc_eval(self._h, len(pair_sets), arr, ctypes.byref(v), _stream(stream)), "dwf_ptc_eval")
+        return v.value
+
+    def __del__(self):
+        try:
+            if getattr(self, "_h", None) and _lib is not None:
+                _lib.dwf_ptc_destroy(self._h)
+                self._h = None
+        except Exception:
+            pass
+
+
+class PtcPairs:
+    """dwf_ptc_pairs: training pairs (r_k, e_k) of one operator, kept on the device."""
+
+    def __init__(self, op, b5, snap_iters, seed: int = 0, stream=None):
+        """b5: 5D source (device tensor), or None for a system with a seeded random solution."""
+        arr = (ctypes.c_int * len(snap_iters))(*[int(k) for k in snap_iters])
+        h = ctypes.c_void_p()
+        src = _dev_ptr(b5) if b5 is not None else None
+        _check(load().dwf_ptc_pairs_create(op._h, src, int(seed), len(snap_iters), arr, ctypes.byref(h),
+                                           _stream(stream)), "dwf_ptc_pairs_create")
+        self._h = h
+        self.op = op          # keeps the operator (and its lattice) alive
+        self.count = len(snap_iters)
+
+    def get(self, k, r_out, e_out, stream=None):
+        _check(load().dwf_ptc_pairs_get(self._h, int(k), _dev_ptr(r_out), _dev_ptr(e_out), _stream(stream)),
+               "dwf_ptc_pairs_get")
+
+    def __del__(self):
+        try:
+            if getattr(self, "_h", None) and _lib is not None:
+                _lib.dwf_ptc_pairs_destroy(self._h)
+                self._h = None
+        except Exception:
+            pass
 
 
 def tune_cache_put(key: str, nrb: int, order: int, ms: float) -> None:

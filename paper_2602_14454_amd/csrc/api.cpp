@@ -12,6 +12,7 @@
 #include "hop.h"
 #include "ops.h"
 #include "solver.h"
+#include "ptc_model.h"
 
 namespace dwf {
 static thread_local std::string g_last_error;
@@ -251,8 +252,11 @@ int dwf_solve(const dwf_op* op, void* x5, const void* b5, const dwf_solve_params
         dwf_solve_params def;
         dwf_solve_params_default(&def);
         const dwf_solve_params* p = prm ? prm : &def;
-        DWF_REQUIRE(p->algo == DWF_ALGO_CGNR || p->algo == DWF_ALGO_DC || p->algo == DWF_ALGO_MIXED, DWF_EINVAL,
-                    "unsupported algorithm");
+        DWF_REQUIRE(p->algo == DWF_ALGO_CGNR || p->algo == DWF_ALGO_DC || p->algo == DWF_ALGO_MIXED ||
+                        p->algo == DWF_ALGO_FGCR_LEARNED,
+                    DWF_EINVAL, "unsupported algorithm");
+        DWF_REQUIRE(!(p->algo == DWF_ALGO_FGCR_LEARNED && p->paper_mode), DWF_EINVAL,
+                    "paper_mode applies to CGNR only");
         return solve(op, x5, b5, p, info, S(stream));
     });
 }
@@ -349,6 +353,147 @@ int dwf_lanczos_extremes(const dwf_op* op, int basis, int keep, int max_restarts
         DWF_REQUIRE(op && lambda_min && lambda_max, DWF_EINVAL, "null argument");
         lanczos_extremes(op, basis, keep, max_restarts, tol, lambda_min, lambda_max, matvecs, converged, S(stream));
         return (converged && !*converged) ? DWF_NOT_CONVERGED : DWF_OK;
+    });
+}
+
+// ---- learned preconditioner ------------------------------------------
+int dwf_ptc_create(int hidden, unsigned long long seed, double init_scale, dwf_ptc** out) {
+    return guarded([&] {
+        DWF_REQUIRE(out, DWF_EINVAL, "null argument");
+        DWF_REQUIRE(init_scale >= 0.0 && init_scale < 10.0, DWF_EINVAL, "init_scale out of range");
+        *out = ptc_create(hidden, seed, init_scale);
+        return DWF_OK;
+    });
+}
+
+void dwf_ptc_destroy(dwf_ptc* m) { delete m; }
+
+int dwf_ptc_set_loss(dwf_ptc* m, int kind) {
+    return guarded([&] {
+        DWF_REQUIRE(m && (kind == 0 || kind == 1), DWF_EINVAL, "loss kind must be 0 or 1");
+        m->loss_kind = kind;
+        return DWF_OK;
+    });
+}
+
+int dwf_ptc_info(const dwf_ptc* m, int* hidden, int* nweights, int* steps) {
+    return guarded([&] {
+        DWF_REQUIRE(m, DWF_EINVAL, "null model");
+        if (hidden) *hidden = m->H;
+        if (nweights) *nweights = (int)m->nw;
+        if (steps) *steps = m->step;
+        return DWF_OK;
+    });
+}
+
+int dwf_ptc_get_weights(const dwf_ptc* m, void* w) {
+    return guarded([&] {
+        DWF_REQUIRE(m && w, DWF_EINVAL, "null argument");
+        DWF_HIP(hipMemcpy(w, m->W.p, m->nw * 8, hipMemcpyDeviceToHost));
+        return DWF_OK;
+    });
+}
+
+int dwf_ptc_set_weights(dwf_ptc* m, const void* w) {
+    return guarded([&] {
+        DWF_REQUIRE(m && w, DWF_EINVAL, "null argument");
+        DWF_HIP(hipMemcpy(m->W.p, w, m->nw * 8, hipMemcpyHostToDevice));
+        return DWF_OK;
+    });
+}
+
+int dwf_ptc_apply(dwf_ptc* m, const dwf_op* op, void* out_e, const void* in_e, void* stream) {
+    return guarded([&] {
+        DWF_REQUIRE(m && op && out_e && in_e, DWF_EINVAL, "null argument");
+        const dwf_lattice* L = op->lat;
+        DWF_REQUIRE(L->has_gauge, DWF_ESTATE, "gauge field not set");
+        hipStream_t st = S(stream);
+        const long n = ptc_field_elems(op);
+        DevBuf a(8 * (size_t)n), b(8 * (size_t)n);
+        const int* lex = L->lex_of_site_dev.as<int>();
+        pack_half(ST_F32, a.p, in_e, lex, L->Vh, L->Vhp, op->Ls, st);
+        m->forward(op, a.as<float2>(), b.as<float2>(), st);
+        unpack_half(ST_F32, out_e, b.p, lex, L->Vh, L->Vhp, op->Ls, st);
+        DWF_HIP(hipStreamSynchronize(st));
+        return DWF_OK;
+    });
+}
+
+int dwf_ptc_gradient(dwf_ptc* m, const dwf_op* op, const void* r_e, const void* e_e, double* loss, void* grad,
+                     void* stream) {
+    return guarded([&] {
+        DWF_REQUIRE(m && op && r_e && e_e, DWF_EINVAL, "null argument");
+        const dwf_lattice* L = op->lat;
+        DWF_REQUIRE(L->has_gauge, DWF_ESTATE, "gauge field not set");
+        hipStream_t st = S(stream);
+        const long n = ptc_field_elems(op);
+        DevBuf r(8 * (size_t)n), e(8 * (size_t)n);
+        const int* lex = L->lex_of_site_dev.as<int>();
+        pack_half(ST_F32, r.p, r_e, lex, L->Vh, L->Vhp, op->Ls, st);
+        pack_half(ST_F32, e.p, e_e, lex, L->Vh, L->Vhp, op->Ls, st);
+        m->gradient(op, r.as<float2>(), e.as<float2>(), st);
+        double h = 0;
+        DWF_HIP(hipMemcpyAsync(&h, m->stats.p, sizeof(double), hipMemcpyDeviceToHost, st));
+        if (grad) DWF_HIP(hipMemcpyAsync(grad, m->G.p, m->nw * 8, hipMemcpyDeviceToHost, st));
+        DWF_HIP(hipStreamSynchronize(st));
+        if (loss) *loss = h;
+        return DWF_OK;
+    });
+}
+
+int dwf_ptc_pairs_create(const dwf_op* op, const void* b5, unsigned long long seed, int nsnap,
+                         const int* snap_iters, dwf_ptc_pairs** out, void* stream) {
+    return guarded([&] {
+        DWF_REQUIRE(out, DWF_EINVAL, "null argument");
+        *out = ptc_pairs_create(op, b5, seed, nsnap, snap_iters, S(stream));
+        return DWF_OK;
+    });
+}
+
+int dwf_ptc_pairs_get(const dwf_ptc_pairs* p, int k, void* r_e, void* e_e, void* stream) {
+    return guarded([&] {
+        DWF_REQUIRE(p && r_e && e_e && k >= 0 && k < p->count, DWF_EINVAL, "bad pair index");
+        const dwf_lattice* L = p->op->lat;
+        hipStream_t st = S(stream);
+        const int* lex = L->lex_of_site_dev.as<int>();
+        unpack_half(ST_F32, r_e, p->r.as<float2>() + (size_t)k * p->n, lex, L->Vh, L->Vhp, p->op->Ls, st);
+        unpack_half(ST_F32, e_e, p->e.as<float2>() + (size_t)k * p->n, lex, L->Vh, L->Vhp, p->op->Ls, st);
+        DWF_HIP(hipStreamSynchronize(st));
+        return DWF_OK;
+    });
+}
+
+void dwf_ptc_pairs_destroy(dwf_ptc_pairs* p) { delete p; }
+
+int dwf_ptc_train(dwf_ptc* m, int nsets, dwf_ptc_pairs* const* sets, int steps, double lr, unsigned long long seed,
+                  double* loss_history, void* stream) {
+    return guarded([&] {
+        ptc_train(m, nsets, sets, steps, lr, seed, loss_history, S(stream));
+        return DWF_OK;
+    });
+}
+
+int dwf_ptc_eval(dwf_ptc* m, int nsets, dwf_ptc_pairs* const* sets, double* mean_loss, void* stream) {
+    return guarded([&] {
+        DWF_REQUIRE(m && nsets >= 1 && sets && mean_loss, DWF_EINVAL, "null argument");
+        for (int i = 0; i < nsets; ++i) DWF_REQUIRE(sets[i], DWF_EINVAL, "null pair set");
+        *mean_loss = ptc_eval(m, nsets, sets, S(stream));
+        return DWF_OK;
+    });
+}
+
+int dwf_ptc_save(const dwf_ptc* m, const char* path) {
+    return guarded([&] {
+        ptc_save(m, path);
+        return DWF_OK;
+    });
+}
+
+int dwf_ptc_load(const char* path, dwf_ptc** out) {
+    return guarded([&] {
+        DWF_REQUIRE(out, DWF_EINVAL, "null argument");
+        *out = ptc_load(path);
+        return DWF_OK;
     });
 }
 

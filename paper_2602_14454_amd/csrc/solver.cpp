@@ -16,7 +16,9 @@
 #include <memory>
 
 #include "blas.h"
+#include "fgcr.h"
 #include "ops.h"
+#include "ptc_model.h"
 
 namespace dwf {
 
@@ -52,7 +54,7 @@ CgWork::CgWork(const dwf_op* op, int kx_, int kp_, int nrhs_) : kx(kx_), kp(kp_)
 }
 
 int cgnr(const dwf_op* op, CgWork& W, const void* b_kp, double tol_rel, int maxiter, int check_every,
-         hipStream_t st, double* final_rel, bool* nan_seen) {
+         hipStream_t st, double* final_rel, bool* nan_seen, const IterHook& on_iter) {
     const long n = W.n;
     double* partial = W.partial.as<double>();
     double* scal = W.scal.as<double>();
@@ -83,6 +85,7 @@ int cgnr(const dwf_op* op, CgWork& W, const void* b_kp, double tol_rel, int maxi
         finalize(partial, blas_grid(n), 1, scal, 2, st);
         cg_update_p(W.kx, W.kp, W.p.p, W.r.p, n, scal + CG_BETA, st);
         ++k;
+        if (on_iter) on_iter(k, W.x.p);
         if (k % check_every == 0 || k == maxiter) {
             read_scalars(scal, hs, st);
             rr = hs.h[CG_RR];
@@ -230,6 +233,7 @@ int solve(const dwf_op* op, void* x5, const void* b5, const dwf_solve_params* pr
 
     int kp = ST_F64;
     if (prm->algo == DWF_ALGO_DC || prm->algo == DWF_ALGO_MIXED || prm->paper_mode) kp = prm->inner_prec;
+    if (prm->algo == DWF_ALGO_FGCR_LEARNED) kp = ST_F32;   // FGCR and the network run in FP32
     DWF_REQUIRE(kp == ST_F64 || kp == ST_F32 || kp == ST_BF16, DWF_EINVAL, "bad inner precision");
     // all workspace is allocated before the timed region starts
     std::unique_ptr<CgWork> W(new CgWork(op, kp == ST_F64 ? ST_F64 : ST_F32, kp, 1));
@@ -274,6 +278,11 @@ int solve(const dwf_op* op, void* x5, const void* b5, const dwf_solve_params* pr
         rel5 = r5;
         converged = !nan_seen && r5 <= tol;
     }
+    // flexible GCR with the learned preconditioner as the inner solver (FP32);
+    // on failure (NaN, stagnation) the solve falls back to CGNR
+    bool use_fgcr = prm->algo == DWF_ALGO_FGCR_LEARNED;
+    std::unique_ptr<FgcrWork> FW;
+    if (use_fgcr) FW.reset(new FgcrWork(op, prm->restart > 0 ? prm->restart : 16));
     while (prm->algo != DWF_ALGO_MIXED && !converged && total < maxiter && outer < 100) {
         const int kx = kp == ST_F64 ? ST_F64 : ST_F32;
         if (W->kp != kp) W.reset(new CgWork(op, kx, kp, 1));
@@ -281,11 +290,29 @@ int solve(const dwf_op* op, void* x5, const void* b5, const dwf_solve_params* pr
         // FP64: the first step is the textbook CGNR stop; restarts are calibrated
         const bool plain = prm->paper_mode || (kp == ST_F64 && outer == 0);
         const double itol = plain ? inner_tol : dc_target(tol, rel5, kp, inner_tol, f_ratio);
-        int it = cgnr(op, *W, rin.p, itol, maxiter - total, prm->check_every, st, &last_inner_rel, &nan_seen);
-        total += it;
+        int it = 0;
+        const void* xin = nullptr;
+        if (use_fgcr) {
+            bool failed = false;
+            it = fgcr(op, static_cast<dwf_ptc*>(prm->ptc_model), *FW, rin.p, itol, maxiter - total, prm->check_every,
+                      st, &last_inner_rel, &failed);
+            total += it;
+            if (failed) {
+                // the learned step is discarded; CGNR takes over from the current x
+                use_fgcr = false;
+                fallback = 1;
+                if (trace_on()) std::fprintf(stderr, "dwf trace: FGCR failed after %d iterations, CGNR fallback\n", it);
+                continue;
+            }
+            xin = FW->x.p;
+        } else {
+            it = cgnr(op, *W, rin.p, itol, maxiter - total, prm->check_every, st, &last_inner_rel, &nan_seen);
+            total += it;
+            xin = W->x.p;
+        }
         ++outer;
         if (nan_seen) break;
-        axpby(ST_F64, kx, xe.p, W->x.p, n, nullptr, 1.0, nullptr, 1.0, nullptr, st);
+        axpby(ST_F64, kx, xe.p, xin, n, nullptr, 1.0, nullptr, 1.0, nullptr, st);
         // rh = b~ - D^ xe (FP64); r5_e = -M rh, r5_o = 0 exactly after reconstruction
         apply_dhat(op, ST_F64, 0, te.p, xe.p, to.p, rh.p, 1, st);
         convert(ST_F64, ST_F64, rh.p, bt.p, n, st);
@@ -302,9 +329,10 @@ int solve(const dwf_op* op, void* x5, const void* b5, const dwf_solve_params* pr
             converged = true;
             break;
         }
-        if (rel5 > 0.5 * prev_rel && kp != ST_F64) {
-            // stagnation of the low-precision correction: step up one precision
-            kp = kp == ST_BF16 ? ST_F32 : ST_F64;
+        if (rel5 > 0.5 * prev_rel && (use_fgcr || kp != ST_F64)) {
+            // stagnation of the correction: leave FGCR for CGNR, else step up one precision
+            if (use_fgcr) use_fgcr = false;
+            else kp = kp == ST_BF16 ? ST_F32 : ST_F64;
             fallback = 1;
         }
         prev_rel = rel5;

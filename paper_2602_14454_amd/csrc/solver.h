@@ -1,6 +1,7 @@
 // CG workspace and solver entry points (solver.cpp).
 #pragma once
 
+#include <functional>
 #include <string>
 
 #include "dwf_internal.h"
@@ -18,8 +19,10 @@ struct CgWork {
 // CG on D^dag D^ e = D^dag b from e = 0; b in storage kp.  Stops when the
 // recursive residual |r| <= tol_rel |r0| or after maxiter iterations.
 // Result in W.x.  Returns the iteration count.
+// on_iter (optional) is called after iteration k with the device pointer of x_k.
+using IterHook = std::function<void(int, const void*)>;
 int cgnr(const dwf_op* op, CgWork& W, const void* b_kp, double tol_rel, int maxiter, int check_every,
-         hipStream_t st, double* final_rel, bool* nan_seen);
+         hipStream_t st, double* final_rel, bool* nan_seen, const IterHook& on_iter = IterHook());
 
 // defect-correction inner target and step ratio (solver.cpp); DWF_TRACE in
 // the environment prints one line per outer step to stderr

@@ -116,6 +116,40 @@ def test_gradients_match_central_differences():
                 assert abs(fd - an) < 1e-6 * max(1.0, abs(an)), (which, idx, unit, fd, an)
 
 
+def test_residual_loss_gradients_match_central_differences():
+    """Residual loss |A (M r - e)|^2 / |r|^2 with A = D^dag D^ of the C
+    oracle: analytic gradient against central differences, and the loss
+    equals |A M r - r|^2 / |r|^2 when r = A e."""
+    import oracle
+    dims, Ls = (4, 2, 2, 2), 3
+    U = dwfgen.random_su3_links(dims, 0.6, 21)
+    p = oracle.Params(dims=dims, Ls=Ls, M0=1.6, m=0.1, b=1.0, c=0.0, alpha=0.7)
+
+    def A(v):
+        return oracle.dhat(p, U, oracle.dhat(p, U, v), dagger=True)
+    W1, W2 = ptc.random_weights(3, 22)
+    e = ptc.restrict_even(dims, _rand_full(dims, Ls, 23))
+    r = A(e)
+    L, g1, g2 = ptc.gradients(U, dims, W1, W2, r, e, kind=1, apply_A=A)
+    y, _ = ptc.forward(U, dims, W1, W2, r)
+    res = A(y) - r
+    assert abs(L - np.vdot(res, res).real / np.vdot(r, r).real) < 1e-12 * L
+    rng = np.random.default_rng(24)
+    h = 1e-6
+    for W, G, which in ((W1, g1, 1), (W2, g2, 2)):
+        for _ in range(8):
+            idx = tuple(rng.integers(0, n) for n in W.shape)
+            for unit in (1.0, 1j):
+                Wp, Wm = W.copy(), W.copy()
+                Wp[idx] += h * unit
+                Wm[idx] -= h * unit
+                args = (Wp, W2) if which == 1 else (W1, Wp)
+                argm = (Wm, W2) if which == 1 else (W1, Wm)
+                fd = (ptc.loss_residual(U, dims, *args, r, e, A) - ptc.loss_residual(U, dims, *argm, r, e, A)) / (2 * h)
+                an = G[idx].real if unit == 1.0 else G[idx].imag
+                assert abs(fd - an) < 1e-6 * max(1.0, abs(an)), (which, idx, unit, fd, an)
+
+
 def test_adam_first_step_is_signed_lr():
     """From m = v = 0 the bias-corrected first Adam step is -lr sign(g)
     (up to eps), per real component."""
