@@ -215,6 +215,137 @@ def run_batch(args):
     print(json.dumps(out))
 
 
+# Learned preconditioner: 16^3x32, Ls = 16, M0 = 1.6, m = 0.01, Shamir, Neff
+# alpha = 0.5, links exp(i 0.5 H) + 3 stout rho = 0.1; training fields seeds
+# 501..532, held-out fields 601..604, 4D Gaussian sources.
+LEARNED = dict(dims=(16, 16, 16, 32), Ls=16, M0=1.6, m=0.01, alpha=0.5, train_seeds=range(501, 533),
+               test_seeds=range(601, 605))
+
+
+def _links_job(a):
+    import dwfgen
+    dims, seed = a
+    return dwfgen.make_links(dims, 0.5, seed, rho=0.1, nsmear=3)
+
+
+def make_fields(dims, seeds):
+    """Gauge fields generated on the host in parallel worker processes."""
+    import multiprocessing as mp
+    ctx = mp.get_context("spawn")
+    with ctx.Pool(min(16, max(1, len(seeds)))) as pool:
+        return pool.map(_links_job, [(dims, s) for s in seeds])
+
+
+def run_learned(args):
+    import numpy as np
+    import torch
+
+    import dwfgen
+    import paper_2602_14454_amd as dwf
+
+    dev = "cuda:0"
+    c = LEARNED
+    dims, Ls = c["dims"], c["Ls"]
+    V = int(np.prod(dims))
+    seeds = list(c["train_seeds"])[: args.train_fields]
+    t0 = time.time()
+    fields = make_fields(dims, seeds + list(c["test_seeds"]))
+    log(f"{len(fields)} gauge fields in {time.time() - t0:.1f}s")
+    train_f, test_f = fields[: len(seeds)], fields[len(seeds):]
+
+    def op_of(U):
+        lat = dwf.Lattice(dims)
+        lat.set_gauge(U)
+        return lat, dwf.Op(lat, Ls, c["M0"], c["m"], 1.0, 0.0, c["alpha"])
+
+    def source(op, seed):
+        b4 = torch.from_numpy(dwfgen.gaussian_source_4d(dims, seed)).to(dev)
+        b5 = torch.empty((Ls, V, 4, 3), dtype=torch.complex128, device=dev)
+        op.source_4d(b5, b4)
+        return b4, b5
+
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    sets, keep = [], []
+    for k, U in enumerate(train_f):
+        lat, op = op_of(U)
+        keep.append((lat, op))
+        sets.append(dwf.PtcPairs(op, None, [0, 1, 2, 4, 8], seed=1000 + k))
+        _, b5 = source(op, 2000 + k)
+        sets.append(dwf.PtcPairs(op, b5, [0, 4, 16, 64]))
+        del b5
+    torch.cuda.synchronize()
+    t_pairs = time.perf_counter() - t0
+    log(f"pairs: {sum(s.count for s in sets)} in {t_pairs:.1f}s")
+    M = dwf.PtcModel(8, seed=1, init_scale=0.02)
+    loss0 = M.eval(sets)
+    t0 = time.perf_counter()
+    n1 = (2 * args.train_steps) // 3
+    h1 = M.train(sets, n1, lr=2e-3, seed=11)
+    h2 = M.train(sets, args.train_steps - n1, lr=5e-4, seed=12)
+    torch.cuda.synchronize()
+    t_train = time.perf_counter() - t0
+    loss1 = M.eval(sets)
+    log(f"training: {args.train_steps} steps in {t_train:.1f}s, loss {loss0:.4f} -> {loss1:.4f}")
+    del sets
+
+    def solve(op, b4, b5, prm):
+        x5 = torch.zeros_like(b5)
+        x4 = torch.empty((V, 4, 3), dtype=torch.complex128, device=dev)
+        op.solve(x5, b5, prm)   # warm-up (allocations)
+        x5.zero_()
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        st, info = op.solve(x5, b5, prm)
+        op.project_4d(x4, x5)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t
+        return {"seconds": dt, "iters": info.iters, "outer": info.outer_iters, "fallback": info.fallback_used,
+                "true_res5": info.true_res5, "res4": op.residual_4d(x4, b4), "status": st}
+
+    def fgcr_params(model):
+        p = dwf.default_params(algo=dwf.ALGO_FGCR_LEARNED, tol=1e-10, check_every=8, restart=16)
+        p.ptc_model = model._h.value if model is not None else None
+        return p
+
+    M0 = dwf.PtcModel(8, seed=1, init_scale=0.02)
+    variants = {"fgcr_trained": fgcr_params(M), "fgcr_identity": fgcr_params(None),
+                "fgcr_untrained": fgcr_params(M0),
+                "dc_f32_cgnr": dwf.default_params(algo=dwf.ALGO_DC, inner_prec=dwf.F32, tol=1e-10, check_every=8),
+                "fp64_cgnr": dwf.default_params(tol=1e-10, check_every=8)}
+    res = {k: [] for k in variants}
+    for k, U in enumerate(test_f):
+        lat, op = op_of(U)
+        b4, b5 = source(op, 3000 + k)
+        for name, prm in variants.items():
+            r = solve(op, b4, b5, prm)
+            res[name].append(r)
+            log(f"held-out {k} {name}: {r['seconds']:.3f}s iters {r['iters']} fallback {r['fallback']} "
+                f"res4 {r['res4']:.2e}")
+    summary = {}
+    for name, rs in res.items():
+        summary[name] = {"mean_seconds": float(np.mean([r["seconds"] for r in rs])),
+                         "mean_iters": float(np.mean([r["iters"] for r in rs])),
+                         "fallbacks": int(sum(r["fallback"] for r in rs)),
+                         "max_true_res5": max(r["true_res5"] for r in rs), "max_res4": max(r["res4"] for r in rs),
+                         "runs": rs}
+    base = summary["fgcr_identity"]["mean_iters"]
+    out = {"metric": "time to 1e-10 true 5D residual per held-out solve: FGCR with the learned preconditioner vs "
+                     "without it vs CGNR", "unit": "s", "higher_is_better": False, "n_gpus": 1,
+           "data": "synthetic", "dtype": "f32",
+           "value": summary["fgcr_trained"]["mean_seconds"],
+           "config": {"workload": ("16^3x32 Ls=16 M0=1.6 m=0.01 Shamir Neff alpha=0.5; links exp(i*0.5*H) + 3 stout "
+                                   f"rho=0.1; train seeds 501..{500 + len(seeds)}, held-out 601..604; "
+                                   "4D Gaussian sources"), "hidden": 8, "paths": 11, "restart": 16},
+           "training": {"fields": len(seeds), "pairs_seconds": t_pairs, "steps": args.train_steps,
+                        "seconds": t_train, "loss_before": loss0, "loss_after": loss1,
+                        "loss_first10": float(np.mean(h1[:10])), "loss_last50": float(np.mean(h2[-50:]))},
+           "iteration_reduction_vs_identity": 1.0 - summary["fgcr_trained"]["mean_iters"] / base,
+           "speedup_vs_fp64": summary["fp64_cgnr"]["mean_seconds"] / summary["fgcr_trained"]["mean_seconds"],
+           "variants": summary}
+    print(json.dumps(out))
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -230,6 +361,10 @@ def main():
     ap.add_argument("--batch", action="store_true",
                     help="run the batched workloads instead: 12 point sources on 16^3x32 Ls=12, and an uneven "
                          "batch of 8 lattices; each against sequential single solves and FP64 CGNR")
+    ap.add_argument("--learned", action="store_true",
+                    help="run the learned-preconditioner workload instead: train on 32 fields, FGCR on held-out ones")
+    ap.add_argument("--train-fields", type=int, default=32)
+    ap.add_argument("--train-steps", type=int, default=1500)
     ap.add_argument("--spectrum", action="store_true",
                     help="also measure lambda_min, lambda_max and kappa of D^dag D^ (Lanczos) for alpha and 1")
     args = ap.parse_args()
@@ -247,6 +382,9 @@ def main():
     torch.cuda.set_device(0)
     if args.batch:
         run_batch(args)
+        return
+    if args.learned:
+        run_learned(args)
         return
     dev = "cuda:0"
     cfg = dict(CONFIGS[args.config])
