@@ -515,7 +515,9 @@ int solve_batch(int n, const dwf_op* const* ops, void* const* x5, const void* co
         for (const Item& it : B.items)
             apply_dhat(it.op, ST_F64, 1, at(te.p, it.off), at(rh.p, it.off), at(to.p, it.off), at(tmp.p, it.off),
                        it.nrhs, cs.s);
-        convert(I->kx, ST_F64, I->r.p, te.p, N, cs.s);
+        for (const Item& it : B.items)   // per operator: the layout change needs its row stride
+            convert(I->kx, ST_F64, static_cast<char*>(I->r.p) + complex_bytes_of(I->kx) * it.off, at(te.p, it.off),
+                    it.n1 * it.nrhs, cs.s, it.op->lat->Vhp);
         convert(I->kp, I->kx, I->p.p, I->r.p, N, cs.s);
         DWF_HIP(hipMemsetAsync(I->x.p, 0, complex_bytes_of(I->kx) * N, cs.s));
         const double itol = inner_tol_of(I->kp);
@@ -555,7 +557,9 @@ int solve_batch(int n, const dwf_op* const* ops, void* const* x5, const void* co
         }
         if (nan_seen) break;
         // x^ += x (slots that were already done add their zero correction)
-        axpby(ST_F64, I->kx, xe.p, I->x.p, N, nullptr, 1.0, nullptr, 1.0, nullptr, cs.s);
+        for (const Item& it : B.items)
+            axpby(ST_F64, I->kx, at(xe.p, it.off), static_cast<char*>(I->x.p) + complex_bytes_of(I->kx) * it.off,
+                  it.n1 * it.nrhs, nullptr, 1.0, nullptr, 1.0, nullptr, cs.s, it.op->lat->Vhp);
         // r^ = b~ - D^ x^, 5D residual |M r^| / |b5|
         for (const Item& it : B.items)
             apply_dhat(it.op, ST_F64, 0, at(te.p, it.off), at(xe.p, it.off), at(to.p, it.off), nullptr, it.nrhs, cs.s);

@@ -23,12 +23,14 @@ void unpack_half(int kind, void* dst, const void* src, const int* lex, long Vh, 
 void pack_chiral_pair_f64(void* dst, const void* b4, const int* lex, long Vh, long Vhp, hipStream_t st);
 void project_4d(void* x4, const void* x5, long V, int Ls, hipStream_t st);
 void embed_4d(void* e5, const void* y, long V, int Ls, hipStream_t st);
-void convert(int kd, int ks, void* dst, const void* src, long n, hipStream_t st);
+// dst = src in another storage kind; Vhp (row stride) is needed when the two
+// kinds group components differently (FP64 vs FP32/BF16)
+void convert(int kd, int ks, void* dst, const void* src, long n, hipStream_t st, long Vhp = 0);
 void norm2_partial(int kind, const void* x, long n, double* partial, hipStream_t st);
 void dot_partial(int kind, const void* x, const void* y, long n, double* partial, hipStream_t st);
 // y = a x + b y; a = *sa if sa else ha (same for b); optional partial |y|^2
 void axpby(int ky, int kx, void* y, const void* x, long n, const double* sa, double ha, const double* sb,
-           double hb, double* partial, hipStream_t st);
+           double hb, double* partial, hipStream_t st, long Vhp = 0);
 void cg_update_xr(int kx, int kp, void* x, void* r, const void* p, const void* w, long n, const double* alpha,
                   double* partial, hipStream_t st);
 void cg_update_p(int kr, int kp, void* p, const void* r, long n, const double* beta, hipStream_t st);

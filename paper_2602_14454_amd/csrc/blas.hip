@@ -41,7 +41,7 @@ __global__ void pack_full_kernel(void* dst, const double2* src, const int* lex_o
 #pragma unroll
     for (int cp = 0; cp < 12; ++cp) {
         double2 v = in[cp];
-        cstore<S>(dst, (rs * 12 + cp) * Vhp + eo, (typename Traits<S>::R)v.x, (typename Traits<S>::R)v.y);
+        cstore<S>(dst, fidx(rs * 12 + cp, eo, Vhp, fpack<S>()), (typename Traits<S>::R)v.x, (typename Traits<S>::R)v.y);
     }
 }
 
@@ -56,7 +56,7 @@ __global__ void unpack_full_kernel(double2* dst, const void* src, const int* lex
 #pragma unroll
     for (int cp = 0; cp < 12; ++cp) {
         typename Traits<S>::R re, im;
-        cload<S>(src, (rs * 12 + cp) * Vhp + eo, re, im);
+        cload<S>(src, fidx(rs * 12 + cp, eo, Vhp, fpack<S>()), re, im);
         out[cp] = make_double2((double)re, (double)im);
     }
 }
@@ -73,7 +73,7 @@ __global__ void pack_half_kernel(void* dst, const double2* src, const int* lex_o
 #pragma unroll
     for (int cp = 0; cp < 12; ++cp) {
         double2 v = src[(rs * Vh + eo) * 12 + cp];
-        cstore<S>(dst, (rs * 12 + cp) * Vhp + i, (typename Traits<S>::R)v.x, (typename Traits<S>::R)v.y);
+        cstore<S>(dst, fidx(rs * 12 + cp, i, Vhp, fpack<S>()), (typename Traits<S>::R)v.x, (typename Traits<S>::R)v.y);
     }
 }
 
@@ -87,7 +87,7 @@ __global__ void unpack_half_kernel(double2* dst, const void* src, const int* lex
 #pragma unroll
     for (int cp = 0; cp < 12; ++cp) {
         typename Traits<S>::R re, im;
-        cload<S>(src, (rs * 12 + cp) * Vhp + i, re, im);
+        cload<S>(src, fidx(rs * 12 + cp, i, Vhp, fpack<S>()), re, im);
         dst[(rs * Vh + eo) * 12 + cp] = make_double2((double)re, (double)im);
     }
 }
@@ -102,8 +102,8 @@ __global__ void pack_chiral_pair_kernel(void* dst, const double2* b4, const int*
     for (int cp = 0; cp < 12; ++cp) {
         double2 v = b4[lex * 12 + cp];
         const bool up = cp < 6;
-        cstore<S>(dst, ((long)0 * 12 + cp) * Vhp + eo, up ? v.x : 0.0, up ? v.y : 0.0);
-        cstore<S>(dst, ((long)1 * 12 + cp) * Vhp + eo, up ? 0.0 : v.x, up ? 0.0 : v.y);
+        cstore<S>(dst, fidx(cp, eo, Vhp, fpack<S>()), up ? v.x : 0.0, up ? v.y : 0.0);
+        cstore<S>(dst, fidx(12 + cp, eo, Vhp, fpack<S>()), up ? 0.0 : v.x, up ? 0.0 : v.y);
     }
 }
 
@@ -142,6 +142,44 @@ __global__ void convert_kernel(void* dst, const void* src, long n) {
         typename Traits<SS>::R re, im;
         cload<SS>(src, i, re, im);
         cstore<SD>(dst, i, (typename Traits<SD>::R)re, (typename Traits<SD>::R)im);
+    }
+}
+
+// The same copy between layouts with different component grouping (FP64
+// single components, FP32/BF16 pairs): thread t handles rows 2g, 2g+1 of
+// site t % Vhp, g = t / Vhp.
+template <class SD, class SS>
+__global__ void convert_remap_kernel(void* dst, const void* src, long npairs, long Vhp) {
+    for (long t = (long)blockIdx.x * blockDim.x + threadIdx.x; t < npairs; t += (long)gridDim.x * blockDim.x) {
+        const long g = t / Vhp, site = t - g * Vhp;
+#pragma unroll
+        for (int k = 0; k < 2; ++k) {
+            typename Traits<SS>::R re, im;
+            cload<SS>(src, fidx(2 * g + k, site, Vhp, fpack<SS>()), re, im);
+            cstore<SD>(dst, fidx(2 * g + k, site, Vhp, fpack<SD>()), (typename Traits<SD>::R)re,
+                       (typename Traits<SD>::R)im);
+        }
+    }
+}
+
+// y = a x + b y between layouts with different grouping (no reduction)
+template <class SY, class SX>
+__global__ void axpby_remap_kernel(void* y, const void* x, long npairs, long Vhp, const double* sa, double ha,
+                                   const double* sb, double hb) {
+    const double a = sa ? *sa : ha;
+    const double bb = sb ? *sb : hb;
+    using RY = typename Traits<SY>::R;
+    for (long t = (long)blockIdx.x * blockDim.x + threadIdx.x; t < npairs; t += (long)gridDim.x * blockDim.x) {
+        const long g = t / Vhp, site = t - g * Vhp;
+#pragma unroll
+        for (int k = 0; k < 2; ++k) {
+            typename Traits<SX>::R xr, xi;
+            RY yr, yi;
+            const long iy = fidx(2 * g + k, site, Vhp, fpack<SY>());
+            cload<SX>(x, fidx(2 * g + k, site, Vhp, fpack<SX>()), xr, xi);
+            cload<SY>(y, iy, yr, yi);
+            cstore<SY>(y, iy, RY(a) * RY(xr) + RY(bb) * yr, RY(a) * RY(xi) + RY(bb) * yi);
+        }
     }
 }
 
@@ -226,7 +264,7 @@ __global__ void random_fill_kernel(double2* v, long rows, long Vh, long Vhp, uns
             z ^= z >> 31;
             out[h] = (double)(z >> 11) * (2.0 / 9007199254740992.0) - 1.0;
         }
-        v[row * Vhp + site] = make_double2(out[0], out[1]);
+        v[fidx(row, site, Vhp, 1)] = make_double2(out[0], out[1]);
     }
 }
 
@@ -393,20 +431,26 @@ void embed_4d(void* e5, const void* y, long V, int Ls, hipStream_t st) {
 }
 
 template <class SD, class SS>
-static void convert_t2(void* dst, const void* src, long n, hipStream_t st) {
-    hipLaunchKernelGGL((convert_kernel<SD, SS>), dim3(blas_grid(n)), dim3(BLAS_THREADS), 0, st, dst, src, n);
+static void convert_t2(void* dst, const void* src, long n, long Vhp, hipStream_t st) {
+    if (fpack<SD>() == fpack<SS>())
+        hipLaunchKernelGGL((convert_kernel<SD, SS>), dim3(blas_grid(n)), dim3(BLAS_THREADS), 0, st, dst, src, n);
+    else
+        hipLaunchKernelGGL((convert_remap_kernel<SD, SS>), dim3(blas_grid(n / 2)), dim3(BLAS_THREADS), 0, st, dst,
+                           src, n / 2, Vhp);
 }
 template <class SD>
-static void convert_t1(int ks, void* dst, const void* src, long n, hipStream_t st) {
+static void convert_t1(int ks, void* dst, const void* src, long n, long Vhp, hipStream_t st) {
     switch (ks) {
-        case ST_F64: convert_t2<SD, double>(dst, src, n, st); break;
-        case ST_F32: convert_t2<SD, float>(dst, src, n, st); break;
-        case ST_BF16: convert_t2<SD, bf16s>(dst, src, n, st); break;
+        case ST_F64: convert_t2<SD, double>(dst, src, n, Vhp, st); break;
+        case ST_F32: convert_t2<SD, float>(dst, src, n, Vhp, st); break;
+        case ST_BF16: convert_t2<SD, bf16s>(dst, src, n, Vhp, st); break;
         default: throw Error{DWF_EINVAL, "bad storage kind"};
     }
 }
-void convert(int kd, int ks, void* dst, const void* src, long n, hipStream_t st) {
-    DISPATCH1(kd, convert_t1, ks, dst, src, n, st);
+void convert(int kd, int ks, void* dst, const void* src, long n, hipStream_t st, long Vhp) {
+    if (fpack_of(kd) != fpack_of(ks))
+        DWF_REQUIRE(Vhp > 0 && n % (2 * Vhp) == 0, DWF_EINVAL, "layout change needs the row stride");
+    DISPATCH1(kd, convert_t1, ks, dst, src, n, Vhp, st);
     DWF_HIP(hipGetLastError());
 }
 
@@ -434,6 +478,12 @@ static void axpby_t2(void* y, const void* x, long n, const double* sa, double ha
     hipLaunchKernelGGL((axpby_kernel<SY, SX>), dim3(blas_grid(n)), dim3(BLAS_THREADS), 0, st, y, x, n, sa, ha,
                        sb, hb, partial);
 }
+template <class SY, class SX>
+static void axpby_remap_t(void* y, const void* x, long n, long Vhp, const double* sa, double ha, const double* sb,
+                          double hb, hipStream_t st) {
+    hipLaunchKernelGGL((axpby_remap_kernel<SY, SX>), dim3(blas_grid(n / 2)), dim3(BLAS_THREADS), 0, st, y, x, n / 2,
+                       Vhp, sa, ha, sb, hb);
+}
 template <class SY>
 static void axpby_t1(int kx, void* y, const void* x, long n, const double* sa, double ha, const double* sb,
                      double hb, double* partial, hipStream_t st) {
@@ -445,7 +495,17 @@ static void axpby_t1(int kx, void* y, const void* x, long n, const double* sa, d
     }
 }
 void axpby(int ky, int kx, void* y, const void* x, long n, const double* sa, double ha, const double* sb,
-           double hb, double* partial, hipStream_t st) {
+           double hb, double* partial, hipStream_t st, long Vhp) {
+    if (fpack_of(ky) != fpack_of(kx)) {
+        DWF_REQUIRE(Vhp > 0 && n % (2 * Vhp) == 0 && !partial, DWF_EINVAL, "layout change needs the row stride");
+        // only FP64 <-> FP32/BF16 differ in layout
+        if (ky == ST_F64 && kx == ST_F32) axpby_remap_t<double, float>(y, x, n, Vhp, sa, ha, sb, hb, st);
+        else if (ky == ST_F64 && kx == ST_BF16) axpby_remap_t<double, bf16s>(y, x, n, Vhp, sa, ha, sb, hb, st);
+        else if (ky == ST_F32) axpby_remap_t<float, double>(y, x, n, Vhp, sa, ha, sb, hb, st);
+        else axpby_remap_t<bf16s, double>(y, x, n, Vhp, sa, ha, sb, hb, st);
+        DWF_HIP(hipGetLastError());
+        return;
+    }
     DISPATCH1(ky, axpby_t1, kx, y, x, n, sa, ha, sb, hb, partial, st);
     DWF_HIP(hipGetLastError());
 }

@@ -17,14 +17,18 @@
 // or the cyclic bidiagonal pattern of K = (b + c M5) T.
 //
 // Wave layout (64 lanes): lane = 16 * sc + j, j = site within a group of 16
-// consecutive even-odd sites, sc = 0..3.  A lane computes the hop for
-// s = sc, sc+4, sc+8, sc+12; each link is loaded once per lane and used for
-// those four slices.  The hop results h[kk][.] are then exactly the B operand
-// of v_mfma_*_16x16x4 (B[k][n] with k = s mod 4 block, n = site), so the
-// dense s-mixing C = A * h runs on the matrix cores straight from registers,
-// with no LDS round trip.  After the MFMA a lane holds rows s = 4*sc + i,
-// i = 0..3, of the result for its site (f32); the f64 MFMA leaves rows
-// sc + 4*i instead (see out_row).
+// consecutive even-odd sites, sc = 0..3; a wave computes the hop for one
+// group of 4 slices s = 4 kk + sc (or KPW groups).  Memory access: every
+// lane-dependent offset (site, slice) is in the vector offset of a buffer
+// load and only wave-uniform offsets are scalar, so no load is serialised
+// over lanes; FP32 and BF16 fields hold spin-colour components in pairs
+// (16 / 8 bytes per site), so a wave reads 16 consecutive sites of a pair
+// with one 128-bit / 64-bit load per lane.  The hop results go to LDS as
+// hs[kk][real][lane], which is exactly the B operand of v_mfma_*_16x16x4
+// (B[k][n] = lane n + 16 k: k = slice within the group, n = site), so the
+// dense s-mixing C = A * h reads each operand with one LDS load per MFMA.
+// After the MFMA a lane holds rows s = 4*sc + i, i = 0..3, of the result for
+// its site (f32); the f64 MFMA leaves rows sc + 4*i instead (see out_row).
 #include "dwf_internal.h"
 #include "hop.h"
 #include "precision.h"
@@ -32,21 +36,24 @@
 namespace dwf {
 
 // Tuning knobs (compile time): occupancy target per precision, 4-slice
-// groups per wave in the hop phase (KPW: each link load then serves 2 slices),
-// unrolling of the direction loop, and whether the 8 neighbour indices are
-// loaded up front.  Defaults are the best of a sweep on MI355X (FP32 hop,
-// 16^3x32 and 24^3x48, Ls = 16).
+// groups per wave in the hop phase (KPW > 1: each link load serves KPW
+// groups), unrolling of the direction loop, and whether the 8 neighbour
+// indices are loaded up front.  Defaults are the best of sweeps on MI355X
+// (16^3x32, Ls = 16): with one slice group per wave and no unrolling of the
+// direction loop the FP32/BF16 kernels need ~122 VGPRs (4 waves per SIMD, no
+// spills); unrolling lets the compiler hoist the loads of several directions
+// and spill.
 #ifndef DWF_HOP_WAVES_PER_EU
-#define DWF_HOP_WAVES_PER_EU 3
+#define DWF_HOP_WAVES_PER_EU 4
 #endif
 #ifndef DWF_HOP_WAVES_PER_EU64
 #define DWF_HOP_WAVES_PER_EU64 2
 #endif
 #ifndef DWF_HOP_UNROLL
-#define DWF_HOP_UNROLL 8
+#define DWF_HOP_UNROLL 1
 #endif
 #ifndef DWF_HOP_KPW
-#define DWF_HOP_KPW 2
+#define DWF_HOP_KPW 1
 #endif
 #ifndef DWF_HOP_KPW64
 #define DWF_HOP_KPW64 1
@@ -167,28 +174,42 @@ struct HopRes {
 };
 
 template <class S, int G>
-__device__ __forceinline__ void hop_direction(const HopParams& P, const HopRes& R_, unsigned rowb, unsigned sx,
+__device__ __forceinline__ void hop_direction(const HopParams& P, const HopRes& R_, unsigned gb, unsigned sx,
                                               int D, unsigned ynb, const int (&s)[G],
                                               const typename Traits<S>::R (&pd)[G][2],
                                               const typename Traits<S>::R (&pe)[G][2],
                                               typename Traits<S>::R (&h)[G][24]) {
     using R = typename Traits<S>::R;
     constexpr unsigned CB = cbytes<S>();
+    constexpr unsigned NG = link_ng(CB);
     const int Ls = P.Ls;
-    const unsigned Vh = rowb / CB;
+    const unsigned Vhp = (unsigned)P.Vhp;
     const unsigned y = DWF_HOP_NBR_PRELOAD ? ynb
-                                           : __builtin_amdgcn_raw_buffer_load_b32(R_.nbr, sx * 4u, (unsigned)D * Vh * 4u, 0);
+                                           : __builtin_amdgcn_raw_buffer_load_b32(R_.nbr, sx * 4u, (unsigned)D * Vhp * 4u, 0);
     R U[18];
-#pragma unroll
-    for (int e = 0; e < 9; ++e) bload<S>(R_.links, sx * CB, (unsigned)(D * 9 + e) * rowb, U[2 * e], U[2 * e + 1]);
-    const unsigned yb = y * CB;
+    constexpr unsigned LGB = link_lp(CB) * CB;   // bytes of one link group per site
+    bload_link<S>(R_.links, sx * LGB, (unsigned)D * NG * Vhp * LGB, Vhp * LGB, U);
+    constexpr int PK = fpack<S>();             // components per group
+    constexpr int NGR = 12 / PK;               // groups per slice
+    const unsigned yg = y * (unsigned)PK * CB; // byte offset of the neighbour in a group row
 #pragma unroll
     for (int g = 0; g < G; ++g) {
-        if (s[g] >= Ls) continue;
+        // Slices beyond Ls (Ls not a multiple of 4) read slice 0 and are zeroed:
+        // branch-free, so the loads of all lanes are issued together; their
+        // hop results meet zero columns of the post-mix.
+        const bool sv = s[g] < Ls;
+        const int sg_ = sv ? s[g] : 0;
         R p[24];
-        const unsigned sb = (unsigned)s[g] * 12u * rowb + yb;
+        // lane-dependent offsets (site, slice) go to the vector operand, the
+        // wave-uniform group offset to the scalar one
+        const unsigned vb = yg + (unsigned)sg_ * NGR * gb;
 #pragma unroll
-        for (int cp = 0; cp < 12; ++cp) bload<S>(R_.in, sb, (unsigned)cp * rowb, p[2 * cp], p[2 * cp + 1]);
+        for (int q = 0; q < NGR; ++q) {
+            R v[4];
+            bload_group<S>(R_.in, vb, (unsigned)q * gb, v);
+#pragma unroll
+            for (int k = 0; k < 2 * PK; ++k) p[2 * PK * q + k] = v[k];
+        }
         if (P.pre_mode >= 1) {
 #pragma unroll
             for (int k = 0; k < 12; ++k) p[k] *= pd[g][0];
@@ -196,24 +217,27 @@ __device__ __forceinline__ void hop_direction(const HopParams& P, const HopRes& 
             for (int k = 12; k < 24; ++k) p[k] *= pd[g][1];
         }
         if (P.pre_mode == 2) {
-            // K pattern: upper chirality couples s-1, lower chirality s+1 (cyclic)
-            const unsigned sm = (unsigned)(s[g] == 0 ? Ls - 1 : s[g] - 1) * 12u * rowb + yb;
-            const unsigned sp = (unsigned)(s[g] == Ls - 1 ? 0 : s[g] + 1) * 12u * rowb + yb;
+            // K pattern: upper chirality (components 0-5) couples s-1, lower (6-11) s+1 (cyclic);
+            // the chirality boundary falls on a group boundary
+            const unsigned sm = (unsigned)(sg_ == 0 ? Ls - 1 : sg_ - 1) * NGR * gb;
+            const unsigned sp = (unsigned)(sg_ == Ls - 1 ? 0 : sg_ + 1) * NGR * gb;
 #pragma unroll
-            for (int cp = 0; cp < 6; ++cp) {
-                R re, im;
-                bload<S>(R_.in, sm, (unsigned)cp * rowb, re, im);
-                p[2 * cp] += pe[g][0] * re;
-                p[2 * cp + 1] += pe[g][0] * im;
+            for (int q = 0; q < NGR / 2; ++q) {
+                R v[4];
+                bload_group<S>(R_.in, yg + sm, (unsigned)q * gb, v);
+#pragma unroll
+                for (int k = 0; k < 2 * PK; ++k) p[2 * PK * q + k] += pe[g][0] * v[k];
             }
 #pragma unroll
-            for (int cp = 6; cp < 12; ++cp) {
-                R re, im;
-                bload<S>(R_.in, sp, (unsigned)cp * rowb, re, im);
-                p[2 * cp] += pe[g][1] * re;
-                p[2 * cp + 1] += pe[g][1] * im;
+            for (int q = NGR / 2; q < NGR; ++q) {
+                R v[4];
+                bload_group<S>(R_.in, yg + sp, (unsigned)q * gb, v);
+#pragma unroll
+                for (int k = 0; k < 2 * PK; ++k) p[2 * PK * q + k] += pe[g][1] * v[k];
             }
         }
+#pragma unroll
+        for (int k = 0; k < 24; ++k) p[k] = sv ? p[k] : R(0);
         switch (D) {   // wave-uniform
             case 0: hop_dir<0, -1, R>(U, p, h[g]); break;
             case 1: hop_dir<1, -1, R>(U, p, h[g]); break;
@@ -264,16 +288,17 @@ __device__ __forceinline__ void hop_tile(const HopParams& P, long tile, int rhs,
     const bool valid = site < Vh;
     const long sx = valid ? site : Vh - 1;
     constexpr unsigned CB = cbytes<S>();
-    const unsigned rowb = (unsigned)P.Vhp * CB;                // bytes of one (s, comp) row
-    const unsigned fieldb = (unsigned)Ls * 12u * rowb;         // bytes of one right-hand side
+    constexpr unsigned PK = fpack<S>();
+    const unsigned gb = (unsigned)P.Vhp * PK * CB;             // bytes of one group row (PK components of a slice)
+    const unsigned fieldb = (unsigned)Ls * (12u / PK) * gb;    // bytes of one right-hand side
     const size_t rhsb = (size_t)rhs * fieldb;                  // bytes of the preceding RHS
-    const unsigned sxb = (unsigned)sx * CB;
+    const unsigned sxb = (unsigned)sx * PK * CB;               // this site's offset in a group row
     HopRes R_;
     R_.in = make_rsrc(static_cast<const char*>(P.in) + rhsb, fieldb);
     R_.loc = make_rsrc(P.loc ? static_cast<const char*>(P.loc) + rhsb : nullptr, P.loc ? fieldb : 0u);
     R_.out = make_rsrc(P.out ? static_cast<const char*>(P.out) + rhsb : nullptr, P.out ? fieldb : 0u);
     R_.out2 = make_rsrc(P.out2 ? static_cast<const char*>(P.out2) + rhsb : nullptr, P.out2 ? fieldb : 0u);
-    R_.links = make_rsrc(P.links, 72u * rowb);
+    R_.links = make_rsrc(P.links, 8u * link_ng(CB) * (unsigned)P.Vhp * link_lp(CB) * CB);
     R_.nbr = make_rsrc(P.nbr, 8u * (unsigned)P.Vhp * 4u);
 
     {
@@ -303,7 +328,7 @@ __device__ __forceinline__ void hop_tile(const HopParams& P, long tile, int rhs,
                          ? __builtin_amdgcn_raw_buffer_load_b32(R_.nbr, (unsigned)sx * 4u, (unsigned)d * (unsigned)P.Vhp * 4u, 0)
                          : 0u;
 #pragma unroll DWF_HOP_UNROLL
-        for (int d = 0; d < 8; ++d) hop_direction<S, G>(P, R_, rowb, (unsigned)sx, d, ynb[d], sg, pd, pe, h);
+        for (int d = 0; d < 8; ++d) hop_direction<S, G>(P, R_, gb, (unsigned)sx, d, ynb[d], sg, pd, pe, h);
 #pragma unroll
         for (int g = 0; g < G; ++g)
 #pragma unroll
@@ -343,7 +368,7 @@ __device__ __forceinline__ void hop_tile(const HopParams& P, long tile, int rhs,
 #pragma unroll
             for (int kk = 0; kk < KK; ++kk) {
                 const int s = sc + 4 * kk;
-                if (s < Ls) bload<S>(R_.loc, sxb, ((unsigned)s * 12u + cp) * rowb, lr[kk], li[kk]);
+                if (s < Ls) bload<S>(R_.loc, sxb + (unsigned)s * (12u / PK) * gb, (cp / PK) * gb + (cp % PK) * CB, lr[kk], li[kk]);
             }
         }
         V cr = {0, 0, 0, 0}, ci = {0, 0, 0, 0};
@@ -365,12 +390,12 @@ __device__ __forceinline__ void hop_tile(const HopParams& P, long tile, int rhs,
             R orr = cr[i], oi = ci[i];
             if (has_loc && !dense_loc && s < Ls) {
                 R xr, xi;
-                bload<S>(R_.loc, sxb, ((unsigned)s * 12u + cp) * rowb, xr, xi);
+                bload<S>(R_.loc, sxb + (unsigned)s * (12u / PK) * gb, (cp / PK) * gb + (cp % PK) * CB, xr, xi);
                 orr += lscale * xr;
                 oi += lscale * xi;
             }
             if (valid && s < Ls) {
-                if (P.out) bstore<S>(R_.out, sxb, ((unsigned)s * 12u + cp) * rowb, orr, oi);
+                if (P.out) bstore<S>(R_.out, sxb + (unsigned)s * (12u / PK) * gb, (cp / PK) * gb + (cp % PK) * CB, orr, oi);
                 if (P.reduce == 1) nrm += double(orr) * double(orr) + double(oi) * double(oi);
             }
         }
@@ -392,7 +417,7 @@ __device__ __forceinline__ void hop_tile(const HopParams& P, long tile, int rhs,
             for (int i = 0; i < 4; ++i) {
                 const int s = out_row<R>(sc, i);
                 if (valid && s < Ls) {
-                    bstore<S>(R_.out2, sxb, ((unsigned)s * 12u + cp) * rowb, dr[i], di[i]);
+                    bstore<S>(R_.out2, sxb + (unsigned)s * (12u / PK) * gb, (cp / PK) * gb + (cp % PK) * CB, dr[i], di[i]);
                     if (P.reduce == 2) nrm += double(dr[i]) * double(dr[i]) + double(di[i]) * double(di[i]);
                 }
             }
@@ -494,7 +519,7 @@ __global__ __launch_bounds__(256) void mix_mfma_kernel(MixParams P) {
         for (int kk = 0; kk < KK; ++kk) {
             const int s = sc + 4 * kk;
             R xr = 0, xi = 0;
-            if (s < Ls) cload<S>(P.in, roff + ((long)s * 12 + cp) * Vhp + sx, xr, xi);
+            if (s < Ls) cload<S>(P.in, roff + fidx((long)s * 12 + cp, sx, Vhp, fpack<S>()), xr, xi);
             cr = mfma4(a[chi][kk], xr, cr);
             ci = mfma4(a[chi][kk], xi, ci);
         }
@@ -502,7 +527,7 @@ __global__ __launch_bounds__(256) void mix_mfma_kernel(MixParams P) {
         for (int i = 0; i < 4; ++i) {
             const int s = out_row<R>(sc, i);
             if (valid && s < Ls) {
-                cstore<S>(P.out, roff + ((long)s * 12 + cp) * Vhp + site, cr[i], ci[i]);
+                cstore<S>(P.out, roff + fidx((long)s * 12 + cp, site, Vhp, fpack<S>()), cr[i], ci[i]);
                 nrm += double(cr[i]) * double(cr[i]) + double(ci[i]) * double(ci[i]);
             }
         }

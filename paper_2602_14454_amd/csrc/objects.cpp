@@ -124,20 +124,39 @@ void upload_gauge(dwf_lattice* L, const cd* U) {
                     }
             }
         }
-    L->links[ST_F64].alloc(nl * 16);
-    DWF_HIP(hipMemcpy(L->links[ST_F64].p, hl.data(), nl * 16, hipMemcpyHostToDevice));
-    std::vector<float> h32(2 * nl);
-    std::vector<uint16_t> h16(2 * nl);
-    for (size_t k = 0; k < nl; ++k) {
-        h32[2 * k] = (float)hl[k].real();
-        h32[2 * k + 1] = (float)hl[k].imag();
-        h16[2 * k] = host_f32_to_bf16(h32[2 * k]);
-        h16[2 * k + 1] = host_f32_to_bf16(h32[2 * k + 1]);
+    // per storage kind: 16-byte groups of link elements (see precision.h)
+    for (int kind : {ST_F64, ST_F32, ST_BF16}) {
+        const int cb = (int)complex_bytes(kind);
+        const long per = link_elems_parity(Vhp, cb);
+        std::vector<double> re(2 * (size_t)per, 0.0), im(2 * (size_t)per, 0.0);
+        for (int p = 0; p < 2; ++p)
+            for (int d = 0; d < 8; ++d)
+                for (int e = 0; e < 9; ++e)
+                    for (long i = 0; i < Vh; ++i) {
+                        const cd u = hl[((size_t)(p * 8 + d) * 9 + e) * Vhp + i];
+                        const size_t k = (size_t)p * per + lidx(d, e, i, Vhp, cb);
+                        re[k] = u.real();
+                        im[k] = u.imag();
+                    }
+        const size_t n = 2 * (size_t)per;
+        L->links[kind].alloc(n * cb);
+        if (kind == ST_F64) {
+            std::vector<double> h(2 * n);
+            for (size_t k = 0; k < n; ++k) { h[2 * k] = re[k]; h[2 * k + 1] = im[k]; }
+            DWF_HIP(hipMemcpy(L->links[kind].p, h.data(), n * cb, hipMemcpyHostToDevice));
+        } else if (kind == ST_F32) {
+            std::vector<float> h(2 * n);
+            for (size_t k = 0; k < n; ++k) { h[2 * k] = (float)re[k]; h[2 * k + 1] = (float)im[k]; }
+            DWF_HIP(hipMemcpy(L->links[kind].p, h.data(), n * cb, hipMemcpyHostToDevice));
+        } else {
+            std::vector<uint16_t> h(2 * n);
+            for (size_t k = 0; k < n; ++k) {
+                h[2 * k] = host_f32_to_bf16((float)re[k]);
+                h[2 * k + 1] = host_f32_to_bf16((float)im[k]);
+            }
+            DWF_HIP(hipMemcpy(L->links[kind].p, h.data(), n * cb, hipMemcpyHostToDevice));
+        }
     }
-    L->links[ST_F32].alloc(nl * 8);
-    DWF_HIP(hipMemcpy(L->links[ST_F32].p, h32.data(), nl * 8, hipMemcpyHostToDevice));
-    L->links[ST_BF16].alloc(nl * 4);
-    DWF_HIP(hipMemcpy(L->links[ST_BF16].p, h16.data(), nl * 4, hipMemcpyHostToDevice));
     L->has_gauge = true;
 }
 

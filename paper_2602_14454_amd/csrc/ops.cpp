@@ -16,6 +16,7 @@
 
 #include "blas.h"
 #include "hop.h"
+#include "precision.h"
 
 namespace dwf {
 
@@ -31,7 +32,7 @@ HopParams hop_params(const dwf_op* op, int kind, int out_parity, const void* in,
     P.loc = loc;
     P.out = out;
     P.out2 = out2;
-    P.links = static_cast<const char*>(L->links[kind].p) + (size_t)out_parity * 8 * 9 * Vhp * cb;
+    P.links = static_cast<const char*>(L->links[kind].p) + (size_t)out_parity * link_elems_parity(Vhp, (int)cb) * cb;
     P.nbr = L->nbr.as<int>() + (size_t)out_parity * 8 * Vhp;
     P.pre = pre_slot >= 0 ? op->pre(kind, pre_slot) : nullptr;
     P.pre_mode = pre_slot < 0 ? 0 : (pre_slot == PRE_K && op->c != 0.0 ? 2 : 1);

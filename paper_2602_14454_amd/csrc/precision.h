@@ -180,6 +180,104 @@ __device__ __forceinline__ void bstore(__amdgpu_buffer_rsrc_t r, unsigned voff, 
 // bytes of one stored complex
 template <class S> constexpr unsigned cbytes() { return sizeof(S) == 8 ? 16u : sizeof(S) == 4 ? 8u : 4u; }
 
+// ---------------------------------------------------------------------
+// Internal layouts.
+//
+// Fields: element (row, site), row = s * 12 + comp (further right-hand sides
+// and channels continue the row count), at complex index
+//   ((row / P) * Vhp + site) * P + row % P
+// with P = 1 for FP64 and P = 2 for FP32 and BF16: P consecutive spin-colour
+// components of a site are contiguous (16 bytes in FP64 and FP32, 8 in BF16)
+// and consecutive sites follow each other, so a wave's load of one group of
+// P components for 16 consecutive sites reads one contiguous 256-byte (BF16:
+// 128-byte) run with a single 128-bit (BF16: 64-bit) load per lane.  FP32
+// and BF16 share the layout, so the CG kernels that mix them stay flat;
+// FP64 <-> FP32/BF16 copies go through remap kernels (blas.hip).
+//
+// Links: LP = 16 / (complex bytes) elements of one site's 3x3 matrix share
+// a 16-byte group; direction d has NG = ceil(9 / LP) groups:
+//   element (d, e, site) at ((d * NG + e / LP) * Vhp + site) * LP + e % LP.
+// ---------------------------------------------------------------------
+// Compile-time layout switches (measured on MI355X, see the hop kernel):
+// DWF_FIELD_PAIRS groups FP32/BF16 components in pairs, DWF_LINK_PACK packs
+// link elements in 16-byte groups.
+#ifndef DWF_FIELD_PAIRS
+#define DWF_FIELD_PAIRS 1
+#endif
+#ifndef DWF_LINK_PACK
+#define DWF_LINK_PACK 1
+#endif
+__host__ __device__ __forceinline__ long fidx(long row, long site, long Vhp, int P) {
+    return P == 1 ? row * Vhp + site : ((row >> 1) * Vhp + site) * 2 + (row & 1);
+}
+template <class S> constexpr int fpack() { return (sizeof(S) == 8 || !DWF_FIELD_PAIRS) ? 1 : 2; }
+inline int fpack_of(int kind) { return (kind == 0 || !DWF_FIELD_PAIRS) ? 1 : 2; }
+__host__ __device__ constexpr int link_lp(int cb) { return DWF_LINK_PACK ? 16 / cb : 1; }
+__host__ __device__ constexpr int link_ng(int cb) { return (9 + link_lp(cb) - 1) / link_lp(cb); }
+__host__ __device__ __forceinline__ long lidx(int d, int e, long site, long Vhp, int cb) {
+    return (((long)d * link_ng(cb) + e / link_lp(cb)) * Vhp + site) * link_lp(cb) + e % link_lp(cb);
+}
+// complex elements of the link table of one parity
+inline long link_elems_parity(long Vhp, int cb) { return 8L * link_ng(cb) * link_lp(cb) * Vhp; }
+
+// One group of fpack<S>() complex (voff = site * group bytes, soff = the
+// group row's byte offset).  v = re0, im0 (, re1, im1).
+template <class S>
+__device__ __forceinline__ void bload_group(__amdgpu_buffer_rsrc_t r, unsigned voff, unsigned soff,
+                                            typename Traits<S>::R (&v)[4]) {
+    if constexpr (fpack<S>() == 1) {
+        bload<S>(r, voff, soff, v[0], v[1]);
+    } else if constexpr (sizeof(S) == 4) {
+        u32x4 w = __builtin_amdgcn_raw_buffer_load_b128(r, voff, soff, 0);
+        v[0] = __uint_as_float(w.x);
+        v[1] = __uint_as_float(w.y);
+        v[2] = __uint_as_float(w.z);
+        v[3] = __uint_as_float(w.w);
+    } else {
+        u32x2 w = __builtin_amdgcn_raw_buffer_load_b64(r, voff, soff, 0);
+        v[0] = bf16_to_f32(w.x & 0xffffu);
+        v[1] = bf16_to_f32(w.x >> 16);
+        v[2] = bf16_to_f32(w.y & 0xffffu);
+        v[3] = bf16_to_f32(w.y >> 16);
+    }
+}
+
+// The 3x3 link of direction d at one site: voff = site * group bytes,
+// soff = d * NG * group row bytes, gstride = group row bytes.  U = re, im of
+// elements 0..8.
+template <class S>
+__device__ __forceinline__ void bload_link(__amdgpu_buffer_rsrc_t r, unsigned voff, unsigned soff, unsigned gstride,
+                                           typename Traits<S>::R (&U)[18]) {
+    constexpr int CB = cbytes<S>(), LP = link_lp(CB), NG = link_ng(CB);
+#pragma unroll
+    for (int g = 0; g < NG; ++g) {
+        if constexpr (LP == 1) {
+            bload<S>(r, voff, soff + (unsigned)g * gstride, U[2 * g], U[2 * g + 1]);
+        } else {
+            u32x4 w = __builtin_amdgcn_raw_buffer_load_b128(r, voff, soff + (unsigned)g * gstride, 0);
+            if constexpr (sizeof(S) == 8) {
+                U[2 * g] = __hiloint2double(w.y, w.x);
+                U[2 * g + 1] = __hiloint2double(w.w, w.z);
+            } else if constexpr (sizeof(S) == 4) {
+                U[4 * g] = __uint_as_float(w.x);
+                U[4 * g + 1] = __uint_as_float(w.y);
+                if (2 * g + 1 < 9) {
+                    U[4 * g + 2] = __uint_as_float(w.z);
+                    U[4 * g + 3] = __uint_as_float(w.w);
+                }
+            } else {
+                const unsigned u[4] = {w.x, w.y, w.z, w.w};
+#pragma unroll
+                for (int k = 0; k < 4; ++k)
+                    if (LP * g + k < 9) {
+                        U[2 * (LP * g + k)] = bf16_to_f32(u[k] & 0xffffu);
+                        U[2 * (LP * g + k) + 1] = bf16_to_f32(u[k] >> 16);
+                    }
+            }
+        }
+    }
+}
+
 inline size_t complex_bytes(int kind) { return kind == 0 ? 16 : kind == 1 ? 8 : 4; }
 
 }  // namespace dwf

@@ -16,6 +16,7 @@
 
 #include "blas.h"
 #include "ops.h"
+#include "precision.h"
 #include "ptc.h"
 #include "solver.h"
 
@@ -25,7 +26,7 @@ namespace dwf {
 
 static const float2* links32(const dwf_op* op, int parity) {
     const dwf_lattice* L = op->lat;
-    return static_cast<const float2*>(L->links[ST_F32].p) + (size_t)parity * 8 * 9 * L->Vhp;
+    return static_cast<const float2*>(L->links[ST_F32].p) + (size_t)parity * link_elems_parity(L->Vhp, 8);
 }
 static const int* nbr_of(const dwf_op* op, int parity) {
     return op->lat->nbr.as<int>() + (size_t)parity * 8 * op->lat->Vhp;
@@ -239,7 +240,7 @@ dwf_ptc_pairs* ptc_pairs_create(const dwf_op* op, const void* b5, unsigned long 
             float2* r = P->r.as<float2>() + (size_t)i * n;
             convert(ST_F64, ST_F64, tmp.p, xs.p, n, st);
             axpby(ST_F64, ST_F64, tmp.p, xk, n, nullptr, -1.0, nullptr, 1.0, nullptr, st);
-            convert(ST_F32, ST_F64, e, tmp.p, n, st);
+            convert(ST_F32, ST_F64, e, tmp.p, n, st, L->Vhp);
             apply_normal(op, ST_F32, r, e, t1.p, t2.p, nullptr, 1, st);
         }
     };

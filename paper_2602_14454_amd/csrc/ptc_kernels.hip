@@ -29,18 +29,50 @@ __device__ __forceinline__ void cfma(float2& acc, float2 a, float2 b) {
     acc.y += a.x * b.y + a.y * b.x;
 }
 
-// v (12 complex, spin-major) of channel b, slice s at internal site i
-__device__ __forceinline__ void load12(const float2* f, long base, long Vhp, float2 (&v)[12]) {
+// v (12 complex, spin-major) of the slice whose first row is row0, at internal
+// site i (FP32 field layout: pairs of components, or single components)
+__device__ __forceinline__ void load12(const float2* f, long row0, long i, long Vhp, float2 (&v)[12]) {
+    if constexpr (fpack<float>() == 2) {
 #pragma unroll
-    for (int k = 0; k < 12; ++k) v[k] = f[base + (long)k * Vhp];
+        for (int q = 0; q < 6; ++q) {
+            const float4 a = *reinterpret_cast<const float4*>(f + fidx(row0 + 2 * q, i, Vhp, 2));
+            v[2 * q] = make_float2(a.x, a.y);
+            v[2 * q + 1] = make_float2(a.z, a.w);
+        }
+    } else {
+#pragma unroll
+        for (int k = 0; k < 12; ++k) v[k] = f[fidx(row0 + k, i, Vhp, 1)];
+    }
 }
 
-// t = L v on every spin (L: 9 complex of direction d at site i)
+__device__ __forceinline__ void store12(float2* f, long row0, long i, long Vhp, const float2 (&v)[12]) {
+    if constexpr (fpack<float>() == 2) {
+#pragma unroll
+        for (int q = 0; q < 6; ++q)
+            *reinterpret_cast<float4*>(f + fidx(row0 + 2 * q, i, Vhp, 2)) =
+                make_float4(v[2 * q].x, v[2 * q].y, v[2 * q + 1].x, v[2 * q + 1].y);
+    } else {
+#pragma unroll
+        for (int k = 0; k < 12; ++k) f[fidx(row0 + k, i, Vhp, 1)] = v[k];
+    }
+}
+
+// t = L v on every spin (L: 9 complex of direction d at site i; FP32 links
+// in pairs, one 16-byte load per pair)
 __device__ __forceinline__ void transport(const float2* links, int d, long i, long Vhp, const float2 (&v)[12],
                                           float2 (&t)[12]) {
-    float2 L[9];
+    float2 L[10];
+    if constexpr (link_lp(8) == 2) {
 #pragma unroll
-    for (int e = 0; e < 9; ++e) L[e] = links[((long)d * 9 + e) * Vhp + i];
+        for (int g = 0; g < 5; ++g) {
+            const float4 a = *reinterpret_cast<const float4*>(links + lidx(d, 2 * g, i, Vhp, 8));
+            L[2 * g] = make_float2(a.x, a.y);
+            L[2 * g + 1] = make_float2(a.z, a.w);
+        }
+    } else {
+#pragma unroll
+        for (int e = 0; e < 9; ++e) L[e] = links[lidx(d, e, i, Vhp, 8)];
+    }
 #pragma unroll
     for (int sp = 0; sp < 4; ++sp)
 #pragma unroll
@@ -71,14 +103,14 @@ __device__ __forceinline__ bool path_input(const PtcLayerParams& P, int q, int b
         if (!P.in_loc) return false;
         const int ss = q == 0 ? s : (q == 9 ? s + 1 : s - 1);
         if (ss < 0 || ss >= P.Ls) return false;
-        load12(P.in_loc, ((long)b * P.Ls + ss) * 12 * Vhp + i, Vhp, t);
+        load12(P.in_loc, ((long)b * P.Ls + ss) * 12, i, Vhp, t);
         return true;
     }
     if (!P.in_hop) return false;
     const int d = q - 1;
     const long y = P.nbr[(long)d * Vhp + i];
     float2 v[12];
-    load12(P.in_hop, ((long)b * P.Ls + s) * 12 * Vhp + y, Vhp, v);
+    load12(P.in_hop, ((long)b * P.Ls + s) * 12, y, Vhp, v);
     transport(P.links, d, i, Vhp, v, t);
     return true;
 }
@@ -106,17 +138,17 @@ __global__ __launch_bounds__(PT) void ptc_layer_kernel(PtcLayerParams P) {
     }
 #pragma unroll
     for (int a = 0; a < AC; ++a) {
-        const long base = ((long)(a0 + a) * P.Ls + s) * 12 * P.Vhp + i;
+        const long row0 = ((long)(a0 + a) * P.Ls + s) * 12;
+        if (P.accumulate) {
+            float2 o[12];
+            load12(P.out, row0, i, P.Vhp, o);
 #pragma unroll
-        for (int k = 0; k < 12; ++k) {
-            float2 v = acc[a][k];
-            if (P.accumulate) {
-                const float2 o = P.out[base + (long)k * P.Vhp];
-                v.x += o.x;
-                v.y += o.y;
+            for (int k = 0; k < 12; ++k) {
+                acc[a][k].x += o[k].x;
+                acc[a][k].y += o[k].y;
             }
-            P.out[base + (long)k * P.Vhp] = v;
         }
+        store12(P.out, row0, i, P.Vhp, acc[a]);
     }
 }
 
@@ -146,7 +178,7 @@ __global__ __launch_bounds__(PT) void ptc_wgrad_kernel(PtcLayerParams P, const f
 #pragma unroll
             for (int a = 0; a < AC; ++a) {
                 float2 gv[12];
-                load12(g, ((long)(a0 + a) * P.Ls + s) * 12 * Vhp + i, Vhp, gv);
+                load12(g, ((long)(a0 + a) * P.Ls + s) * 12, i, Vhp, gv);
 #pragma unroll
                 for (int ii = 0; ii < 4; ++ii)
 #pragma unroll

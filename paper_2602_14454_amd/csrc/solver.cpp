@@ -63,8 +63,8 @@ int cgnr(const dwf_op* op, CgWork& W, const void* b_kp, double tol_rel, int maxi
     DWF_HIP(hipMemsetAsync(W.scal.p, 0, CG_NSLOTS * sizeof(double), st));
     // r = D^dag b, p = r, x = 0
     apply_dhat(op, W.kp, 1, W.w.p, b_kp, W.t.p, W.v.p, W.nrhs, st);
-    convert(W.kx, W.kp, W.r.p, W.w.p, n, st);
-    convert(W.kp, W.kx, W.p.p, W.r.p, n, st);
+    convert(W.kx, W.kp, W.r.p, W.w.p, n, st, op->lat->Vhp);
+    convert(W.kp, W.kx, W.p.p, W.r.p, n, st, op->lat->Vhp);
     DWF_HIP(hipMemsetAsync(W.x.p, 0, complex_bytes_of(W.kx) * n, st));
     norm2_partial(W.kx, W.r.p, n, partial, st);
     finalize(partial, blas_grid(n), 1, scal + CG_RR, 0, st);
@@ -134,8 +134,8 @@ static int cgnr_reliable(const dwf_op* op, CgWork& W, void* xe, const void* bt, 
     // r^ = b~ (x_hi = 0), r = D^dag r^
     convert(ST_F64, ST_F64, rh, bt, n, st);
     apply_dhat(op, ST_F64, 1, te, rh, to, tmp_e, 1, st);
-    convert(W.kx, ST_F64, W.r.p, te, n, st);
-    convert(W.kp, W.kx, W.p.p, W.r.p, n, st);
+    convert(W.kx, ST_F64, W.r.p, te, n, st, op->lat->Vhp);
+    convert(W.kp, W.kx, W.p.p, W.r.p, n, st, op->lat->Vhp);
     DWF_HIP(hipMemsetAsync(W.x.p, 0, complex_bytes_of(W.kx) * n, st));
     norm2_partial(W.kx, W.r.p, n, partial, st);
     finalize(partial, blas_grid(n), 1, scal + CG_RR, 0, st);
@@ -159,7 +159,7 @@ static int cgnr_reliable(const dwf_op* op, CgWork& W, void* xe, const void* bt, 
             if (hs.h[CG_NANFLAG] != 0.0 || !std::isfinite(rr)) { *nan_seen = true; break; }
             if (rr < delta * delta * rmax2 || rr < target || k == maxiter) {
                 // reliable update: fold x_lo into x_hi and recompute the residual in FP64
-                axpby(ST_F64, W.kx, xe, W.x.p, n, nullptr, 1.0, nullptr, 1.0, nullptr, st);
+                axpby(ST_F64, W.kx, xe, W.x.p, n, nullptr, 1.0, nullptr, 1.0, nullptr, st, op->lat->Vhp);
                 DWF_HIP(hipMemsetAsync(W.x.p, 0, complex_bytes_of(W.kx) * n, st));
                 apply_dhat(op, ST_F64, 0, te, xe, to, tmp_e, 1, st);
                 convert(ST_F64, ST_F64, rh, bt, n, st);
@@ -169,7 +169,7 @@ static int cgnr_reliable(const dwf_op* op, CgWork& W, void* xe, const void* bt, 
                 ++*nupdates;
                 if (rel5 <= tol || k == maxiter) break;
                 apply_dhat(op, ST_F64, 1, te, rh, to, tmp_e, 1, st);
-                convert(W.kx, ST_F64, W.r.p, te, n, st);
+                convert(W.kx, ST_F64, W.r.p, te, n, st, op->lat->Vhp);
                 norm2_partial(W.kx, W.r.p, n, partial, st);
                 finalize(partial, blas_grid(n), 1, scal, 3, st);
                 read_scalars(scal, hs, st);
@@ -286,7 +286,7 @@ int solve(const dwf_op* op, void* x5, const void* b5, const dwf_solve_params* pr
     while (prm->algo != DWF_ALGO_MIXED && !converged && total < maxiter && outer < 100) {
         const int kx = kp == ST_F64 ? ST_F64 : ST_F32;
         if (W->kp != kp) W.reset(new CgWork(op, kx, kp, 1));
-        convert(kp, ST_F64, rin.p, rh.p, n, st);
+        convert(kp, ST_F64, rin.p, rh.p, n, st, Vhp);
         // FP64: the first step is the textbook CGNR stop; restarts are calibrated
         const bool plain = prm->paper_mode || (kp == ST_F64 && outer == 0);
         const double itol = plain ? inner_tol : dc_target(tol, rel5, kp, inner_tol, f_ratio);
@@ -312,7 +312,7 @@ int solve(const dwf_op* op, void* x5, const void* b5, const dwf_solve_params* pr
         }
         ++outer;
         if (nan_seen) break;
-        axpby(ST_F64, kx, xe.p, xin, n, nullptr, 1.0, nullptr, 1.0, nullptr, st);
+        axpby(ST_F64, kx, xe.p, xin, n, nullptr, 1.0, nullptr, 1.0, nullptr, st, Vhp);
         // rh = b~ - D^ xe (FP64); r5_e = -M rh, r5_o = 0 exactly after reconstruction
         apply_dhat(op, ST_F64, 0, te.p, xe.p, to.p, rh.p, 1, st);
         convert(ST_F64, ST_F64, rh.p, bt.p, n, st);
