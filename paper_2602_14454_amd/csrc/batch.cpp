@@ -286,6 +286,7 @@ void make_batch(Batch& B, int n, const dwf_op* const* ops, const int* nrhs) {
             d.nb = slot_blocks(it.n1);
             d.block0 = B.vblocks;
             d.nhop = hop_grid_blocks(op->lat->Vh);
+            d.Vhp = op->lat->Vhp;
             B.vblocks += d.nb;
             pst = std::max<long>(pst, std::max(d.nb, d.nhop));
             B.slots.push_back(d);
@@ -518,7 +519,10 @@ int solve_batch(int n, const dwf_op* const* ops, void* const* x5, const void* co
         for (const Item& it : B.items)   // per operator: the layout change needs its row stride
             convert(I->kx, ST_F64, static_cast<char*>(I->r.p) + complex_bytes_of(I->kx) * it.off, at(te.p, it.off),
                     it.n1 * it.nrhs, cs.s, it.op->lat->Vhp);
-        convert(I->kp, I->kx, I->p.p, I->r.p, N, cs.s);
+        for (const Item& it : B.items)
+            convert(I->kp, I->kx, static_cast<char*>(I->p.p) + complex_bytes_of(I->kp) * it.off,
+                    static_cast<char*>(I->r.p) + complex_bytes_of(I->kx) * it.off, it.n1 * it.nrhs, cs.s,
+                    it.op->lat->Vhp);
         DWF_HIP(hipMemsetAsync(I->x.p, 0, complex_bytes_of(I->kx) * N, cs.s));
         const double itol = inner_tol_of(I->kp);
         for (int v = 0; v < ns; ++v) {

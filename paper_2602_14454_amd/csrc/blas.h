@@ -31,9 +31,10 @@ void dot_partial(int kind, const void* x, const void* y, long n, double* partial
 // y = a x + b y; a = *sa if sa else ha (same for b); optional partial |y|^2
 void axpby(int ky, int kx, void* y, const void* x, long n, const double* sa, double ha, const double* sb,
            double hb, double* partial, hipStream_t st, long Vhp = 0);
+// (Vhp: row stride, needed when the operands' layouts differ, FP32 with BF16)
 void cg_update_xr(int kx, int kp, void* x, void* r, const void* p, const void* w, long n, const double* alpha,
-                  double* partial, hipStream_t st);
-void cg_update_p(int kr, int kp, void* p, const void* r, long n, const double* beta, hipStream_t st);
+                  double* partial, hipStream_t st, long Vhp = 0);
+void cg_update_p(int kr, int kp, void* p, const void* r, long n, const double* beta, hipStream_t st, long Vhp = 0);
 // y += (ar + i ai) x
 void caxpy(int kind, void* y, const void* x, long n, double ar, double ai, hipStream_t st);
 // FP64 half field(s) of `rows` rows: uniform [-1,1) real and imaginary parts on valid sites

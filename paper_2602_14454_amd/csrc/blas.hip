@@ -146,40 +146,84 @@ __global__ void convert_kernel(void* dst, const void* src, long n) {
 }
 
 // The same copy between layouts with different component grouping (FP64
-// single components, FP32/BF16 pairs): thread t handles rows 2g, 2g+1 of
-// site t % Vhp, g = t / Vhp.
+// single components, FP32 pairs, BF16 quads): thread t handles rows 4g..4g+3
+// of site t % Vhp, g = t / Vhp.
 template <class SD, class SS>
-__global__ void convert_remap_kernel(void* dst, const void* src, long npairs, long Vhp) {
-    for (long t = (long)blockIdx.x * blockDim.x + threadIdx.x; t < npairs; t += (long)gridDim.x * blockDim.x) {
+__global__ void convert_remap_kernel(void* dst, const void* src, long nquads, long Vhp) {
+    for (long t = (long)blockIdx.x * blockDim.x + threadIdx.x; t < nquads; t += (long)gridDim.x * blockDim.x) {
         const long g = t / Vhp, site = t - g * Vhp;
+        typename Traits<SS>::R a[8];
+        typename Traits<SD>::R c[8];
+        load4<SS>(src, g, site, Vhp, a);
 #pragma unroll
-        for (int k = 0; k < 2; ++k) {
-            typename Traits<SS>::R re, im;
-            cload<SS>(src, fidx(2 * g + k, site, Vhp, fpack<SS>()), re, im);
-            cstore<SD>(dst, fidx(2 * g + k, site, Vhp, fpack<SD>()), (typename Traits<SD>::R)re,
-                       (typename Traits<SD>::R)im);
-        }
+        for (int k = 0; k < 8; ++k) c[k] = (typename Traits<SD>::R)a[k];
+        store4<SD>(dst, g, site, Vhp, c);
     }
 }
 
 // y = a x + b y between layouts with different grouping (no reduction)
 template <class SY, class SX>
-__global__ void axpby_remap_kernel(void* y, const void* x, long npairs, long Vhp, const double* sa, double ha,
+__global__ void axpby_remap_kernel(void* y, const void* x, long nquads, long Vhp, const double* sa, double ha,
                                    const double* sb, double hb) {
     const double a = sa ? *sa : ha;
     const double bb = sb ? *sb : hb;
     using RY = typename Traits<SY>::R;
-    for (long t = (long)blockIdx.x * blockDim.x + threadIdx.x; t < npairs; t += (long)gridDim.x * blockDim.x) {
+    for (long t = (long)blockIdx.x * blockDim.x + threadIdx.x; t < nquads; t += (long)gridDim.x * blockDim.x) {
         const long g = t / Vhp, site = t - g * Vhp;
+        typename Traits<SX>::R xv[8];
+        RY yv[8];
+        load4<SX>(x, g, site, Vhp, xv);
+        load4<SY>(y, g, site, Vhp, yv);
 #pragma unroll
-        for (int k = 0; k < 2; ++k) {
-            typename Traits<SX>::R xr, xi;
-            RY yr, yi;
-            const long iy = fidx(2 * g + k, site, Vhp, fpack<SY>());
-            cload<SX>(x, fidx(2 * g + k, site, Vhp, fpack<SX>()), xr, xi);
-            cload<SY>(y, iy, yr, yi);
-            cstore<SY>(y, iy, RY(a) * RY(xr) + RY(bb) * yr, RY(a) * RY(xi) + RY(bb) * yi);
+        for (int k = 0; k < 8; ++k) yv[k] = RY(a) * RY(xv[k]) + RY(bb) * yv[k];
+        store4<SY>(y, g, site, Vhp, yv);
+    }
+}
+
+// CG updates whose operands differ in layout (FP32 x, r with BF16 p, w):
+// same arithmetic as cg_xr_kernel / cg_p_kernel, each operand read in its own
+// layout with whole-group accesses, four components of one site per thread.
+template <class SX, class SP>
+__global__ void cg_xr_remap_kernel(void* x, void* r, const void* p, const void* w, long nquads, long Vhp,
+                                   const double* alpha, double* partial) {
+    __shared__ double red[BLAS_THREADS / 64];
+    using RX = typename Traits<SX>::R;
+    const RX a = RX(*alpha);
+    double acc = 0.0;
+    for (long t = (long)blockIdx.x * blockDim.x + threadIdx.x; t < nquads; t += (long)gridDim.x * blockDim.x) {
+        const long g = t / Vhp, site = t - g * Vhp;
+        typename Traits<SP>::R pv[8], wv[8];
+        RX xv[8], rv[8];
+        load4<SP>(p, g, site, Vhp, pv);
+        load4<SP>(w, g, site, Vhp, wv);
+        load4<SX>(x, g, site, Vhp, xv);
+        load4<SX>(r, g, site, Vhp, rv);
+#pragma unroll
+        for (int k = 0; k < 8; ++k) {
+            xv[k] += a * RX(pv[k]);
+            rv[k] -= a * RX(wv[k]);
+            acc += double(rv[k]) * double(rv[k]);
         }
+        store4<SX>(x, g, site, Vhp, xv);
+        store4<SX>(r, g, site, Vhp, rv);
+    }
+    double tt = block_sum(acc, red);
+    if (threadIdx.x == 0) partial[blockIdx.x] = tt;
+}
+
+template <class SR, class SP>
+__global__ void cg_p_remap_kernel(void* p, const void* r, long nquads, long Vhp, const double* beta) {
+    using RP = typename Traits<SP>::R;
+    const RP b = RP(*beta);
+    for (long t = (long)blockIdx.x * blockDim.x + threadIdx.x; t < nquads; t += (long)gridDim.x * blockDim.x) {
+        const long g = t / Vhp, site = t - g * Vhp;
+        typename Traits<SR>::R rv[8];
+        RP pv[8];
+        load4<SR>(r, g, site, Vhp, rv);
+        load4<SP>(p, g, site, Vhp, pv);
+#pragma unroll
+        for (int k = 0; k < 8; ++k) pv[k] = RP(rv[k]) + b * pv[k];
+        store4<SP>(p, g, site, Vhp, pv);
     }
 }
 
@@ -435,8 +479,8 @@ static void convert_t2(void* dst, const void* src, long n, long Vhp, hipStream_t
     if (fpack<SD>() == fpack<SS>())
         hipLaunchKernelGGL((convert_kernel<SD, SS>), dim3(blas_grid(n)), dim3(BLAS_THREADS), 0, st, dst, src, n);
     else
-        hipLaunchKernelGGL((convert_remap_kernel<SD, SS>), dim3(blas_grid(n / 2)), dim3(BLAS_THREADS), 0, st, dst,
-                           src, n / 2, Vhp);
+        hipLaunchKernelGGL((convert_remap_kernel<SD, SS>), dim3(blas_grid(n / 4)), dim3(BLAS_THREADS), 0, st, dst,
+                           src, n / 4, Vhp);
 }
 template <class SD>
 static void convert_t1(int ks, void* dst, const void* src, long n, long Vhp, hipStream_t st) {
@@ -449,7 +493,7 @@ static void convert_t1(int ks, void* dst, const void* src, long n, long Vhp, hip
 }
 void convert(int kd, int ks, void* dst, const void* src, long n, hipStream_t st, long Vhp) {
     if (fpack_of(kd) != fpack_of(ks))
-        DWF_REQUIRE(Vhp > 0 && n % (2 * Vhp) == 0, DWF_EINVAL, "layout change needs the row stride");
+        DWF_REQUIRE(Vhp > 0 && n % (4 * Vhp) == 0, DWF_EINVAL, "layout change needs the row stride");
     DISPATCH1(kd, convert_t1, ks, dst, src, n, Vhp, st);
     DWF_HIP(hipGetLastError());
 }
@@ -481,7 +525,7 @@ static void axpby_t2(void* y, const void* x, long n, const double* sa, double ha
 template <class SY, class SX>
 static void axpby_remap_t(void* y, const void* x, long n, long Vhp, const double* sa, double ha, const double* sb,
                           double hb, hipStream_t st) {
-    hipLaunchKernelGGL((axpby_remap_kernel<SY, SX>), dim3(blas_grid(n / 2)), dim3(BLAS_THREADS), 0, st, y, x, n / 2,
+    hipLaunchKernelGGL((axpby_remap_kernel<SY, SX>), dim3(blas_grid(n / 4)), dim3(BLAS_THREADS), 0, st, y, x, n / 4,
                        Vhp, sa, ha, sb, hb);
 }
 template <class SY>
@@ -497,12 +541,15 @@ static void axpby_t1(int kx, void* y, const void* x, long n, const double* sa, d
 void axpby(int ky, int kx, void* y, const void* x, long n, const double* sa, double ha, const double* sb,
            double hb, double* partial, hipStream_t st, long Vhp) {
     if (fpack_of(ky) != fpack_of(kx)) {
-        DWF_REQUIRE(Vhp > 0 && n % (2 * Vhp) == 0 && !partial, DWF_EINVAL, "layout change needs the row stride");
-        // only FP64 <-> FP32/BF16 differ in layout
-        if (ky == ST_F64 && kx == ST_F32) axpby_remap_t<double, float>(y, x, n, Vhp, sa, ha, sb, hb, st);
-        else if (ky == ST_F64 && kx == ST_BF16) axpby_remap_t<double, bf16s>(y, x, n, Vhp, sa, ha, sb, hb, st);
-        else if (ky == ST_F32) axpby_remap_t<float, double>(y, x, n, Vhp, sa, ha, sb, hb, st);
-        else axpby_remap_t<bf16s, double>(y, x, n, Vhp, sa, ha, sb, hb, st);
+        DWF_REQUIRE(Vhp > 0 && n % (4 * Vhp) == 0 && !partial, DWF_EINVAL, "layout change needs the row stride");
+        switch (ky * 3 + kx) {
+            case ST_F64 * 3 + ST_F32: axpby_remap_t<double, float>(y, x, n, Vhp, sa, ha, sb, hb, st); break;
+            case ST_F64 * 3 + ST_BF16: axpby_remap_t<double, bf16s>(y, x, n, Vhp, sa, ha, sb, hb, st); break;
+            case ST_F32 * 3 + ST_F64: axpby_remap_t<float, double>(y, x, n, Vhp, sa, ha, sb, hb, st); break;
+            case ST_F32 * 3 + ST_BF16: axpby_remap_t<float, bf16s>(y, x, n, Vhp, sa, ha, sb, hb, st); break;
+            case ST_BF16 * 3 + ST_F64: axpby_remap_t<bf16s, double>(y, x, n, Vhp, sa, ha, sb, hb, st); break;
+            default: axpby_remap_t<bf16s, float>(y, x, n, Vhp, sa, ha, sb, hb, st); break;
+        }
         DWF_HIP(hipGetLastError());
         return;
     }
@@ -511,42 +558,55 @@ void axpby(int ky, int kx, void* y, const void* x, long n, const double* sa, dou
 }
 
 template <class SX, class SP>
-static void cg_xr_t2(void* x, void* r, const void* p, const void* w, long n, const double* alpha,
+static void cg_xr_t2(void* x, void* r, const void* p, const void* w, long n, long Vhp, const double* alpha,
                      double* partial, hipStream_t st) {
-    hipLaunchKernelGGL((cg_xr_kernel<SX, SP>), dim3(blas_grid(n)), dim3(BLAS_THREADS), 0, st, x, r, p, w, n,
-                       alpha, partial);
+    // same block count in both forms: callers reduce blas_grid(n) partials
+    if (fpack<SX>() == fpack<SP>())
+        hipLaunchKernelGGL((cg_xr_kernel<SX, SP>), dim3(blas_grid(n)), dim3(BLAS_THREADS), 0, st, x, r, p, w, n,
+                           alpha, partial);
+    else
+        hipLaunchKernelGGL((cg_xr_remap_kernel<SX, SP>), dim3(blas_grid(n)), dim3(BLAS_THREADS), 0, st, x, r, p, w,
+                           n / 4, Vhp, alpha, partial);
 }
 template <class SX>
-static void cg_xr_t1(int kp, void* x, void* r, const void* p, const void* w, long n, const double* alpha,
+static void cg_xr_t1(int kp, void* x, void* r, const void* p, const void* w, long n, long Vhp, const double* alpha,
                      double* partial, hipStream_t st) {
     switch (kp) {
-        case ST_F64: cg_xr_t2<SX, double>(x, r, p, w, n, alpha, partial, st); break;
-        case ST_F32: cg_xr_t2<SX, float>(x, r, p, w, n, alpha, partial, st); break;
-        case ST_BF16: cg_xr_t2<SX, bf16s>(x, r, p, w, n, alpha, partial, st); break;
+        case ST_F64: cg_xr_t2<SX, double>(x, r, p, w, n, Vhp, alpha, partial, st); break;
+        case ST_F32: cg_xr_t2<SX, float>(x, r, p, w, n, Vhp, alpha, partial, st); break;
+        case ST_BF16: cg_xr_t2<SX, bf16s>(x, r, p, w, n, Vhp, alpha, partial, st); break;
         default: throw Error{DWF_EINVAL, "bad storage kind"};
     }
 }
 void cg_update_xr(int kx, int kp, void* x, void* r, const void* p, const void* w, long n,
-                  const double* alpha, double* partial, hipStream_t st) {
-    DISPATCH1(kx, cg_xr_t1, kp, x, r, p, w, n, alpha, partial, st);
+                  const double* alpha, double* partial, hipStream_t st, long Vhp) {
+    if (fpack_of(kx) != fpack_of(kp))
+        DWF_REQUIRE(Vhp > 0 && n % (4 * Vhp) == 0, DWF_EINVAL, "layout change needs the row stride");
+    DISPATCH1(kx, cg_xr_t1, kp, x, r, p, w, n, Vhp, alpha, partial, st);
     DWF_HIP(hipGetLastError());
 }
 
 template <class SR, class SP>
-static void cg_p_t2(void* p, const void* r, long n, const double* beta, hipStream_t st) {
-    hipLaunchKernelGGL((cg_p_kernel<SR, SP>), dim3(blas_grid(n)), dim3(BLAS_THREADS), 0, st, p, r, n, beta);
+static void cg_p_t2(void* p, const void* r, long n, long Vhp, const double* beta, hipStream_t st) {
+    if (fpack<SR>() == fpack<SP>())
+        hipLaunchKernelGGL((cg_p_kernel<SR, SP>), dim3(blas_grid(n)), dim3(BLAS_THREADS), 0, st, p, r, n, beta);
+    else
+        hipLaunchKernelGGL((cg_p_remap_kernel<SR, SP>), dim3(blas_grid(n)), dim3(BLAS_THREADS), 0, st, p, r, n / 4,
+                           Vhp, beta);
 }
 template <class SR>
-static void cg_p_t1(int kp, void* p, const void* r, long n, const double* beta, hipStream_t st) {
+static void cg_p_t1(int kp, void* p, const void* r, long n, long Vhp, const double* beta, hipStream_t st) {
     switch (kp) {
-        case ST_F64: cg_p_t2<SR, double>(p, r, n, beta, st); break;
-        case ST_F32: cg_p_t2<SR, float>(p, r, n, beta, st); break;
-        case ST_BF16: cg_p_t2<SR, bf16s>(p, r, n, beta, st); break;
+        case ST_F64: cg_p_t2<SR, double>(p, r, n, Vhp, beta, st); break;
+        case ST_F32: cg_p_t2<SR, float>(p, r, n, Vhp, beta, st); break;
+        case ST_BF16: cg_p_t2<SR, bf16s>(p, r, n, Vhp, beta, st); break;
         default: throw Error{DWF_EINVAL, "bad storage kind"};
     }
 }
-void cg_update_p(int kr, int kp, void* p, const void* r, long n, const double* beta, hipStream_t st) {
-    DISPATCH1(kr, cg_p_t1, kp, p, r, n, beta, st);
+void cg_update_p(int kr, int kp, void* p, const void* r, long n, const double* beta, hipStream_t st, long Vhp) {
+    if (fpack_of(kr) != fpack_of(kp))
+        DWF_REQUIRE(Vhp > 0 && n % (4 * Vhp) == 0, DWF_EINVAL, "layout change needs the row stride");
+    DISPATCH1(kr, cg_p_t1, kp, p, r, n, Vhp, beta, st);
     DWF_HIP(hipGetLastError());
 }
 

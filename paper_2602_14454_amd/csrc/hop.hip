@@ -205,7 +205,7 @@ __device__ __forceinline__ void hop_direction(const HopParams& P, const HopRes& 
         const unsigned vb = yg + (unsigned)sg_ * NGR * gb;
 #pragma unroll
         for (int q = 0; q < NGR; ++q) {
-            R v[4];
+            R v[8];
             bload_group<S>(R_.in, vb, (unsigned)q * gb, v);
 #pragma unroll
             for (int k = 0; k < 2 * PK; ++k) p[2 * PK * q + k] = v[k];
@@ -217,23 +217,33 @@ __device__ __forceinline__ void hop_direction(const HopParams& P, const HopRes& 
             for (int k = 12; k < 24; ++k) p[k] *= pd[g][1];
         }
         if (P.pre_mode == 2) {
-            // K pattern: upper chirality (components 0-5) couples s-1, lower (6-11) s+1 (cyclic);
-            // the chirality boundary falls on a group boundary
+            // K pattern: upper chirality (components 0-5) couples s-1, lower
+            // (6-11) s+1 (cyclic); groups that straddle the boundary are read
+            // from both slices
             const unsigned sm = (unsigned)(sg_ == 0 ? Ls - 1 : sg_ - 1) * NGR * gb;
             const unsigned sp = (unsigned)(sg_ == Ls - 1 ? 0 : sg_ + 1) * NGR * gb;
 #pragma unroll
-            for (int q = 0; q < NGR / 2; ++q) {
-                R v[4];
-                bload_group<S>(R_.in, yg + sm, (unsigned)q * gb, v);
+            for (int q = 0; q < NGR; ++q) {
+                if (PK * q < 6) {
+                    R v[8];
+                    bload_group<S>(R_.in, yg + sm, (unsigned)q * gb, v);
 #pragma unroll
-                for (int k = 0; k < 2 * PK; ++k) p[2 * PK * q + k] += pe[g][0] * v[k];
-            }
+                    for (int k = 0; k < PK; ++k)
+                        if (PK * q + k < 6) {
+                            p[2 * (PK * q + k)] += pe[g][0] * v[2 * k];
+                            p[2 * (PK * q + k) + 1] += pe[g][0] * v[2 * k + 1];
+                        }
+                }
+                if (PK * q + PK > 6) {
+                    R v[8];
+                    bload_group<S>(R_.in, yg + sp, (unsigned)q * gb, v);
 #pragma unroll
-            for (int q = NGR / 2; q < NGR; ++q) {
-                R v[4];
-                bload_group<S>(R_.in, yg + sp, (unsigned)q * gb, v);
-#pragma unroll
-                for (int k = 0; k < 2 * PK; ++k) p[2 * PK * q + k] += pe[g][1] * v[k];
+                    for (int k = 0; k < PK; ++k)
+                        if (PK * q + k >= 6) {
+                            p[2 * (PK * q + k)] += pe[g][1] * v[2 * k];
+                            p[2 * (PK * q + k) + 1] += pe[g][1] * v[2 * k + 1];
+                        }
+                }
             }
         }
 #pragma unroll

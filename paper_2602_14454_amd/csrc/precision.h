@@ -186,13 +186,12 @@ template <class S> constexpr unsigned cbytes() { return sizeof(S) == 8 ? 16u : s
 // Fields: element (row, site), row = s * 12 + comp (further right-hand sides
 // and channels continue the row count), at complex index
 //   ((row / P) * Vhp + site) * P + row % P
-// with P = 1 for FP64 and P = 2 for FP32 and BF16: P consecutive spin-colour
-// components of a site are contiguous (16 bytes in FP64 and FP32, 8 in BF16)
-// and consecutive sites follow each other, so a wave's load of one group of
-// P components for 16 consecutive sites reads one contiguous 256-byte (BF16:
-// 128-byte) run with a single 128-bit (BF16: 64-bit) load per lane.  FP32
-// and BF16 share the layout, so the CG kernels that mix them stay flat;
-// FP64 <-> FP32/BF16 copies go through remap kernels (blas.hip).
+// with P = 1 for FP64, 2 for FP32 and 4 for BF16: P consecutive spin-colour
+// components of a site are contiguous (16 bytes) and consecutive sites follow
+// each other, so a wave's load of one group for 16 consecutive sites reads one
+// contiguous 256-byte run with a single 128-bit load per lane.  Kernels that
+// mix storage kinds element by element (conversions, CG updates with FP32 x, r
+// and BF16 p, w) index each operand in its own layout (blas.hip).
 //
 // Links: LP = 16 / (complex bytes) elements of one site's 3x3 matrix share
 // a 16-byte group; direction d has NG = ceil(9 / LP) groups:
@@ -208,10 +207,14 @@ template <class S> constexpr unsigned cbytes() { return sizeof(S) == 8 ? 16u : s
 #define DWF_LINK_PACK 1
 #endif
 __host__ __device__ __forceinline__ long fidx(long row, long site, long Vhp, int P) {
-    return P == 1 ? row * Vhp + site : ((row >> 1) * Vhp + site) * 2 + (row & 1);
+    return P == 1 ? row * Vhp + site : (P == 2 ? ((row >> 1) * Vhp + site) * 2 + (row & 1)
+                                               : ((row >> 2) * Vhp + site) * 4 + (row & 3));
 }
-template <class S> constexpr int fpack() { return (sizeof(S) == 8 || !DWF_FIELD_PAIRS) ? 1 : 2; }
-inline int fpack_of(int kind) { return (kind == 0 || !DWF_FIELD_PAIRS) ? 1 : 2; }
+// components per group: FP64 1, FP32 2, BF16 4 (16 bytes per site and group)
+template <class S> constexpr int fpack() {
+    return (sizeof(S) == 8 || !DWF_FIELD_PAIRS) ? 1 : (sizeof(S) == 4 ? 2 : 4);
+}
+inline int fpack_of(int kind) { return (kind == 0 || !DWF_FIELD_PAIRS) ? 1 : (kind == 1 ? 2 : 4); }
 __host__ __device__ constexpr int link_lp(int cb) { return DWF_LINK_PACK ? 16 / cb : 1; }
 __host__ __device__ constexpr int link_ng(int cb) { return (9 + link_lp(cb) - 1) / link_lp(cb); }
 __host__ __device__ __forceinline__ long lidx(int d, int e, long site, long Vhp, int cb) {
@@ -220,11 +223,62 @@ __host__ __device__ __forceinline__ long lidx(int d, int e, long site, long Vhp,
 // complex elements of the link table of one parity
 inline long link_elems_parity(long Vhp, int cb) { return 8L * link_ng(cb) * link_lp(cb) * Vhp; }
 
+// Components 4g .. 4g+3 of one site with whole-group accesses (16 bytes per
+// access when the layout packs 16 bytes per group): v = re0, im0, ..., re3, im3.
+template <class S>
+__device__ __forceinline__ void load4(const void* base, long g, long site, long Vhp,
+                                      typename Traits<S>::R (&v)[8]) {
+    constexpr int P = fpack<S>();
+    if constexpr (P == 4) {   // BF16 quads
+        const uint4 w = reinterpret_cast<const uint4*>(base)[g * Vhp + site];
+        const unsigned u[4] = {w.x, w.y, w.z, w.w};
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+            v[2 * k] = bf16_to_f32(u[k] & 0xffffu);
+            v[2 * k + 1] = bf16_to_f32(u[k] >> 16);
+        }
+    } else if constexpr (P == 2 && sizeof(S) == 4) {   // FP32 pairs
+#pragma unroll
+        for (int j = 0; j < 2; ++j) {
+            const float4 w = reinterpret_cast<const float4*>(base)[(2 * g + j) * Vhp + site];
+            v[4 * j] = w.x;
+            v[4 * j + 1] = w.y;
+            v[4 * j + 2] = w.z;
+            v[4 * j + 3] = w.w;
+        }
+    } else {
+#pragma unroll
+        for (int k = 0; k < 4; ++k) cload<S>(base, fidx(4 * g + k, site, Vhp, P), v[2 * k], v[2 * k + 1]);
+    }
+}
+
+template <class S>
+__device__ __forceinline__ void store4(void* base, long g, long site, long Vhp,
+                                       const typename Traits<S>::R (&v)[8]) {
+    constexpr int P = fpack<S>();
+    if constexpr (P == 4) {
+        uint4 w;
+        w.x = f32_to_bf16(v[0]) | (f32_to_bf16(v[1]) << 16);
+        w.y = f32_to_bf16(v[2]) | (f32_to_bf16(v[3]) << 16);
+        w.z = f32_to_bf16(v[4]) | (f32_to_bf16(v[5]) << 16);
+        w.w = f32_to_bf16(v[6]) | (f32_to_bf16(v[7]) << 16);
+        reinterpret_cast<uint4*>(base)[g * Vhp + site] = w;
+    } else if constexpr (P == 2 && sizeof(S) == 4) {
+#pragma unroll
+        for (int j = 0; j < 2; ++j)
+            reinterpret_cast<float4*>(base)[(2 * g + j) * Vhp + site] =
+                make_float4(v[4 * j], v[4 * j + 1], v[4 * j + 2], v[4 * j + 3]);
+    } else {
+#pragma unroll
+        for (int k = 0; k < 4; ++k) cstore<S>(base, fidx(4 * g + k, site, Vhp, P), v[2 * k], v[2 * k + 1]);
+    }
+}
+
 // One group of fpack<S>() complex (voff = site * group bytes, soff = the
-// group row's byte offset).  v = re0, im0 (, re1, im1).
+// group row's byte offset).  v = re0, im0, re1, im1, ...
 template <class S>
 __device__ __forceinline__ void bload_group(__amdgpu_buffer_rsrc_t r, unsigned voff, unsigned soff,
-                                            typename Traits<S>::R (&v)[4]) {
+                                            typename Traits<S>::R (&v)[8]) {
     if constexpr (fpack<S>() == 1) {
         bload<S>(r, voff, soff, v[0], v[1]);
     } else if constexpr (sizeof(S) == 4) {
@@ -233,12 +287,20 @@ __device__ __forceinline__ void bload_group(__amdgpu_buffer_rsrc_t r, unsigned v
         v[1] = __uint_as_float(w.y);
         v[2] = __uint_as_float(w.z);
         v[3] = __uint_as_float(w.w);
-    } else {
+    } else if constexpr (fpack<S>() == 2) {
         u32x2 w = __builtin_amdgcn_raw_buffer_load_b64(r, voff, soff, 0);
         v[0] = bf16_to_f32(w.x & 0xffffu);
         v[1] = bf16_to_f32(w.x >> 16);
         v[2] = bf16_to_f32(w.y & 0xffffu);
         v[3] = bf16_to_f32(w.y >> 16);
+    } else {
+        u32x4 w = __builtin_amdgcn_raw_buffer_load_b128(r, voff, soff, 0);
+        const unsigned u[4] = {w.x, w.y, w.z, w.w};
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+            v[2 * k] = bf16_to_f32(u[k] & 0xffffu);
+            v[2 * k + 1] = bf16_to_f32(u[k] >> 16);
+        }
     }
 }
 

@@ -23,6 +23,7 @@ struct SlotDesc {
     int block0;   // first vector-kernel block of the slot
     int nhop;     // partials written per hop launch (tiles of its lattice)
     int pad;
+    long Vhp;     // row stride of its lattice (layout changes between storage kinds)
 };
 
 // blocks of one slot for the vector kernels

@@ -60,19 +60,45 @@ __global__ __launch_bounds__(BT) void bcg_xr_kernel(void* x, void* r, const void
     using RX = typename Traits<SX>::R;
     const RX a = RX(sv[CG_ALPHA]);
     double acc = 0.0;
-    for (long i = (long)b * BT + threadIdx.x; i < d.n; i += (long)d.nb * BT) {
-        const long k = d.off + i;
+    auto upd = [&](long kx, long kp) {
         typename Traits<SP>::R pr, pi, wr, wi;
         RX xr, xi, rr, ri;
-        cload<SP>(p, k, pr, pi);
-        cload<SP>(w, k, wr, wi);
-        cload<SX>(x, k, xr, xi);
-        cload<SX>(r, k, rr, ri);
+        cload<SP>(p, kp, pr, pi);
+        cload<SP>(w, kp, wr, wi);
+        cload<SX>(x, kx, xr, xi);
+        cload<SX>(r, kx, rr, ri);
         xr += a * RX(pr); xi += a * RX(pi);
         rr -= a * RX(wr); ri -= a * RX(wi);
-        cstore<SX>(x, k, xr, xi);
-        cstore<SX>(r, k, rr, ri);
+        cstore<SX>(x, kx, xr, xi);
+        cstore<SX>(r, kx, rr, ri);
         acc += double(rr) * double(rr) + double(ri) * double(ri);
+    };
+    if constexpr (fpack<SX>() == fpack<SP>()) {
+        for (long i = (long)b * BT + threadIdx.x; i < d.n; i += (long)d.nb * BT) upd(d.off + i, d.off + i);
+    } else {
+        // operands in different layouts: four components of one site per step
+        // (slot offsets are multiples of 4 * Vhp complex, whole groups)
+        const char* pb = static_cast<const char*>(p) + d.off * cbytes<SP>();
+        const char* wb = static_cast<const char*>(w) + d.off * cbytes<SP>();
+        char* xb = static_cast<char*>(x) + d.off * cbytes<SX>();
+        char* rb = static_cast<char*>(r) + d.off * cbytes<SX>();
+        for (long t = (long)b * BT + threadIdx.x; t < d.n / 4; t += (long)d.nb * BT) {
+            const long g = t / d.Vhp, site = t - g * d.Vhp;
+            typename Traits<SP>::R pv[8], wv[8];
+            RX xv[8], rv[8];
+            load4<SP>(pb, g, site, d.Vhp, pv);
+            load4<SP>(wb, g, site, d.Vhp, wv);
+            load4<SX>(xb, g, site, d.Vhp, xv);
+            load4<SX>(rb, g, site, d.Vhp, rv);
+#pragma unroll
+            for (int q = 0; q < 8; ++q) {
+                xv[q] += a * RX(pv[q]);
+                rv[q] -= a * RX(wv[q]);
+                acc += double(rv[q]) * double(rv[q]);
+            }
+            store4<SX>(xb, g, site, d.Vhp, xv);
+            store4<SX>(rb, g, site, d.Vhp, rv);
+        }
     }
     const double t = bsum(acc, red);
     if (threadIdx.x == 0) partial[(long)v * pstride + b] = t;
@@ -88,13 +114,28 @@ __global__ __launch_bounds__(BT) void bcg_p_kernel(void* p, const void* r, const
     if (sv[CG_DONE] != 0.0) return;
     using RP = typename Traits<SP>::R;
     const RP be = RP(sv[CG_BETA]);
-    for (long i = (long)b * BT + threadIdx.x; i < d.n; i += (long)d.nb * BT) {
-        const long k = d.off + i;
+    auto upd = [&](long kr, long kp) {
         typename Traits<SR>::R rr, ri;
         RP pr, pi;
-        cload<SR>(r, k, rr, ri);
-        cload<SP>(p, k, pr, pi);
-        cstore<SP>(p, k, RP(rr) + be * pr, RP(ri) + be * pi);
+        cload<SR>(r, kr, rr, ri);
+        cload<SP>(p, kp, pr, pi);
+        cstore<SP>(p, kp, RP(rr) + be * pr, RP(ri) + be * pi);
+    };
+    if constexpr (fpack<SR>() == fpack<SP>()) {
+        for (long i = (long)b * BT + threadIdx.x; i < d.n; i += (long)d.nb * BT) upd(d.off + i, d.off + i);
+    } else {
+        const char* rb = static_cast<const char*>(r) + d.off * cbytes<SR>();
+        char* pb = static_cast<char*>(p) + d.off * cbytes<SP>();
+        for (long t = (long)b * BT + threadIdx.x; t < d.n / 4; t += (long)d.nb * BT) {
+            const long g = t / d.Vhp, site = t - g * d.Vhp;
+            typename Traits<SR>::R rv[8];
+            RP pv[8];
+            load4<SR>(rb, g, site, d.Vhp, rv);
+            load4<SP>(pb, g, site, d.Vhp, pv);
+#pragma unroll
+            for (int q = 0; q < 8; ++q) pv[q] = RP(rv[q]) + be * pv[q];
+            store4<SP>(pb, g, site, d.Vhp, pv);
+        }
     }
 }
 

@@ -81,9 +81,9 @@ int cgnr(const dwf_op* op, CgWork& W, const void* b_kp, double tol_rel, int maxi
     while (k < maxiter) {
         apply_normal(op, W.kp, W.w.p, W.p.p, W.t.p, W.v.p, partial, W.nrhs, st);
         finalize(partial, hop_partials(op, W.nrhs), 1, scal, 1, st);
-        cg_update_xr(W.kx, W.kp, W.x.p, W.r.p, W.p.p, W.w.p, n, scal + CG_ALPHA, partial, st);
+        cg_update_xr(W.kx, W.kp, W.x.p, W.r.p, W.p.p, W.w.p, n, scal + CG_ALPHA, partial, st, op->lat->Vhp);
         finalize(partial, blas_grid(n), 1, scal, 2, st);
-        cg_update_p(W.kx, W.kp, W.p.p, W.r.p, n, scal + CG_BETA, st);
+        cg_update_p(W.kx, W.kp, W.p.p, W.r.p, n, scal + CG_BETA, st, op->lat->Vhp);
         ++k;
         if (on_iter) on_iter(k, W.x.p);
         if (k % check_every == 0 || k == maxiter) {
@@ -150,7 +150,7 @@ static int cgnr_reliable(const dwf_op* op, CgWork& W, void* xe, const void* bt, 
     while (k < maxiter) {
         apply_normal(op, W.kp, W.w.p, W.p.p, W.t.p, W.v.p, partial, W.nrhs, st);
         finalize(partial, hop_partials(op, W.nrhs), 1, scal, 1, st);
-        cg_update_xr(W.kx, W.kp, W.x.p, W.r.p, W.p.p, W.w.p, n, scal + CG_ALPHA, partial, st);
+        cg_update_xr(W.kx, W.kp, W.x.p, W.r.p, W.p.p, W.w.p, n, scal + CG_ALPHA, partial, st, op->lat->Vhp);
         finalize(partial, blas_grid(n), 1, scal, 2, st);
         ++k;
         if (k % check_every == 0 || k == maxiter) {
@@ -185,7 +185,7 @@ static int cgnr_reliable(const dwf_op* op, CgWork& W, void* xe, const void* bt, 
                 rmax2 = std::max(rmax2, rr);
             }
         }
-        cg_update_p(W.kx, W.kp, W.p.p, W.r.p, n, scal + CG_BETA, st);
+        cg_update_p(W.kx, W.kp, W.p.p, W.r.p, n, scal + CG_BETA, st, op->lat->Vhp);
     }
     if (*nan_seen) return k;
     *rel5_out = rel5;
