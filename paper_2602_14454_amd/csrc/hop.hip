@@ -61,6 +61,12 @@ namespace dwf {
 #ifndef DWF_HOP_NBR_PRELOAD
 #define DWF_HOP_NBR_PRELOAD 1
 #endif
+// Stage the block's links and neighbour indices in LDS once (all lanes of a
+// block need the same 16 sites' links; loaded per lane they would be fetched
+// by every slice group of every wave).
+#ifndef DWF_HOP_LDS_LINKS
+#define DWF_HOP_LDS_LINKS 1
+#endif
 typedef float v4f __attribute__((ext_vector_type(4)));
 typedef double v4d __attribute__((ext_vector_type(4)));
 
@@ -178,17 +184,24 @@ __device__ __forceinline__ void hop_direction(const HopParams& P, const HopRes& 
                                               int D, unsigned ynb, const int (&s)[G],
                                               const typename Traits<S>::R (&pd)[G][2],
                                               const typename Traits<S>::R (&pe)[G][2],
-                                              typename Traits<S>::R (&h)[G][24]) {
+                                              typename Traits<S>::R (&h)[G][24], const u32x4* lnk,
+                                              const unsigned* lnbr, int j) {
     using R = typename Traits<S>::R;
     constexpr unsigned CB = cbytes<S>();
     constexpr unsigned NG = link_ng(CB);
     const int Ls = P.Ls;
     const unsigned Vhp = (unsigned)P.Vhp;
-    const unsigned y = DWF_HOP_NBR_PRELOAD ? ynb
-                                           : __builtin_amdgcn_raw_buffer_load_b32(R_.nbr, sx * 4u, (unsigned)D * Vhp * 4u, 0);
     R U[18];
-    constexpr unsigned LGB = link_lp(CB) * CB;   // bytes of one link group per site
-    bload_link<S>(R_.links, sx * LGB, (unsigned)D * NG * Vhp * LGB, Vhp * LGB, U);
+    unsigned y;
+    if constexpr (DWF_HOP_LDS_LINKS) {
+        y = lnbr[D * 16 + j];
+#pragma unroll
+        for (unsigned g = 0; g < NG; ++g) decode_link_group<S>(lnk[(D * NG + g) * 16 + j], (int)g, U);
+    } else {
+        y = DWF_HOP_NBR_PRELOAD ? ynb : __builtin_amdgcn_raw_buffer_load_b32(R_.nbr, sx * 4u, (unsigned)D * Vhp * 4u, 0);
+        constexpr unsigned LGB = link_lp(CB) * CB;   // bytes of one link group per site
+        bload_link<S>(R_.links, sx * LGB, (unsigned)D * NG * Vhp * LGB, Vhp * LGB, U);
+    }
     constexpr int PK = fpack<S>();             // components per group
     constexpr int NGR = 12 / PK;               // groups per slice
     const unsigned yg = y * (unsigned)PK * CB; // byte offset of the neighbour in a group row
@@ -284,9 +297,12 @@ __host__ __device__ constexpr int hop_waves(int KK, bool f64) { return KK / hop_
 // hop_tile computes one such block's work: sites 16*tile .. 16*tile+15 of
 // right-hand side `rhs`; part_out (or nullptr) receives the block's partial
 // norm.  Both kernels below call it.
+template <class S> constexpr int lnk_entries() { return 8 * link_ng(cbytes<S>()) * 16; }
+
 template <class S, int KK>
 __device__ __forceinline__ void hop_tile(const HopParams& P, long tile, int rhs, double* part_out,
-                                         typename Traits<S>::R (&hs)[KK][24][64], double (&red)[4]) {
+                                         typename Traits<S>::R (&hs)[KK][24][64], double (&red)[4],
+                                         u32x4 (&lnk)[lnk_entries<S>()], unsigned (&lnbr)[128]) {
     using R = typename Traits<S>::R;
     using V = typename Vec4<R>::T;
     const int lane = threadIdx.x & 63;
@@ -311,6 +327,25 @@ __device__ __forceinline__ void hop_tile(const HopParams& P, long tile, int rhs,
     R_.links = make_rsrc(P.links, 8u * link_ng(CB) * (unsigned)P.Vhp * link_lp(CB) * CB);
     R_.nbr = make_rsrc(P.nbr, 8u * (unsigned)P.Vhp * 4u);
 
+    if constexpr (DWF_HOP_LDS_LINKS) {
+        // the tile's links (16-byte groups) and neighbour indices, once per block;
+        // every lane-dependent offset is in the vector operand
+        const unsigned Vhp = (unsigned)P.Vhp;
+        for (int e = threadIdx.x; e < lnk_entries<S>(); e += blockDim.x) {
+            const int dg = e >> 4, jj = e & 15;
+            const long se = tile * 16 + jj;
+            const unsigned sxe = (unsigned)(se < Vh ? se : Vh - 1);
+            lnk[e] = __builtin_amdgcn_raw_buffer_load_b128(R_.links, sxe * 16u + (unsigned)dg * Vhp * 16u, 0u, 0);
+        }
+        for (int e = threadIdx.x; e < 128; e += blockDim.x) {
+            const int d = e >> 4, jj = e & 15;
+            const long se = tile * 16 + jj;
+            const unsigned sxe = (unsigned)(se < Vh ? se : Vh - 1);
+            lnbr[e] = __builtin_amdgcn_raw_buffer_load_b32(R_.nbr, sxe * 4u + (unsigned)d * Vhp * 4u, 0u, 0);
+        }
+        __syncthreads();
+    }
+
     {
         constexpr int G = hop_kpw(KK, sizeof(S) == 8);
         R h[G][24];
@@ -334,11 +369,12 @@ __device__ __forceinline__ void hop_tile(const HopParams& P, long tile, int rhs,
         unsigned ynb[8];
 #pragma unroll
         for (int d = 0; d < 8; ++d)
-            ynb[d] = DWF_HOP_NBR_PRELOAD
+            ynb[d] = (DWF_HOP_NBR_PRELOAD && !DWF_HOP_LDS_LINKS)
                          ? __builtin_amdgcn_raw_buffer_load_b32(R_.nbr, (unsigned)sx * 4u, (unsigned)d * (unsigned)P.Vhp * 4u, 0)
                          : 0u;
 #pragma unroll DWF_HOP_UNROLL
-        for (int d = 0; d < 8; ++d) hop_direction<S, G>(P, R_, gb, (unsigned)sx, d, ynb[d], sg, pd, pe, h);
+        for (int d = 0; d < 8; ++d)
+            hop_direction<S, G>(P, R_, gb, (unsigned)sx, d, ynb[d], sg, pd, pe, h, lnk, lnbr, j);
 #pragma unroll
         for (int g = 0; g < G; ++g)
 #pragma unroll
@@ -453,8 +489,10 @@ __attribute__((amdgpu_waves_per_eu(sizeof(S) == 8 ? DWF_HOP_WAVES_PER_EU64 : DWF
 void hop_mfma_kernel(HopParams P) {
     __shared__ typename Traits<S>::R hs[KK][24][64];
     __shared__ double red[4];
+    __shared__ u32x4 lnk[lnk_entries<S>()];
+    __shared__ unsigned lnbr[128];
     hop_tile<S, KK>(P, xcd_block(blockIdx.x, gridDim.x), blockIdx.y,
-                    P.partial ? P.partial + (long)blockIdx.y * gridDim.x + blockIdx.x : nullptr, hs, red);
+                    P.partial ? P.partial + (long)blockIdx.y * gridDim.x + blockIdx.x : nullptr, hs, red, lnk, lnbr);
 }
 
 // Work-list form for batches: one launch covers several operators (lattices
@@ -474,6 +512,8 @@ void hop_batch_kernel(const HopParams* __restrict__ items, const int* __restrict
                       int order) {
     __shared__ typename Traits<S>::R hs[KK][24][64];
     __shared__ double red[4];
+    __shared__ u32x4 lnk[lnk_entries<S>()];
+    __shared__ unsigned lnbr[128];
     const int b = xcd_block(blockIdx.x, gridDim.x);
     int i = 0;
     while (i + 1 < nitems && b >= meta[i + 1]) ++i;
@@ -492,7 +532,7 @@ void hop_batch_kernel(const HopParams* __restrict__ items, const int* __restrict
             if (part && threadIdx.x == 0) *part = 0.0;
             continue;
         }
-        hop_tile<S, KK>(P, tile, r, part, hs, red);
+        hop_tile<S, KK>(P, tile, r, part, hs, red, lnk, lnbr);
         __syncthreads();   // hs and red are reused by the next right-hand side
     }
 }

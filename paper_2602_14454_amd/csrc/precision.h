@@ -304,6 +304,32 @@ __device__ __forceinline__ void bload_group(__amdgpu_buffer_rsrc_t r, unsigned v
     }
 }
 
+// Decode one 16-byte link group g (elements LP*g .. LP*g+LP-1) into U.
+template <class S>
+__device__ __forceinline__ void decode_link_group(u32x4 w, int g, typename Traits<S>::R (&U)[18]) {
+    constexpr int LP = link_lp(cbytes<S>());
+    static_assert(LP * cbytes<S>() == 16, "16-byte link groups expected");
+    if constexpr (sizeof(S) == 8) {
+        U[2 * g] = __hiloint2double(w.y, w.x);
+        U[2 * g + 1] = __hiloint2double(w.w, w.z);
+    } else if constexpr (sizeof(S) == 4) {
+        U[4 * g] = __uint_as_float(w.x);
+        U[4 * g + 1] = __uint_as_float(w.y);
+        if (2 * g + 1 < 9) {
+            U[4 * g + 2] = __uint_as_float(w.z);
+            U[4 * g + 3] = __uint_as_float(w.w);
+        }
+    } else {
+        const unsigned u[4] = {w.x, w.y, w.z, w.w};
+#pragma unroll
+        for (int k = 0; k < 4; ++k)
+            if (LP * g + k < 9) {
+                U[2 * (LP * g + k)] = bf16_to_f32(u[k] & 0xffffu);
+                U[2 * (LP * g + k) + 1] = bf16_to_f32(u[k] >> 16);
+            }
+    }
+}
+
 // The 3x3 link of direction d at one site: voff = site * group bytes,
 // soff = d * NG * group row bytes, gstride = group row bytes.  U = re, im of
 // elements 0..8.
