@@ -21,9 +21,10 @@
 // group of 4 slices s = 4 kk + sc (or KPW groups).  Memory access: every
 // lane-dependent offset (site, slice) is in the vector offset of a buffer
 // load and only wave-uniform offsets are scalar, so no load is serialised
-// over lanes; FP32 and BF16 fields hold spin-colour components in pairs
-// (16 / 8 bytes per site), so a wave reads 16 consecutive sites of a pair
-// with one 128-bit / 64-bit load per lane.  The hop results go to LDS as
+// over lanes; fields hold spin-colour components in 16-byte groups per site
+// (FP64 one, FP32 a pair, BF16 a quad), so a wave reads 16 consecutive sites
+// of a group with one 128-bit load per lane, and the block's links (also in
+// 16-byte groups) are staged once in LDS.  The hop results go to LDS as
 // hs[kk][real][lane], which is exactly the B operand of v_mfma_*_16x16x4
 // (B[k][n] = lane n + 16 k: k = slice within the group, n = site), so the
 // dense s-mixing C = A * h reads each operand with one LDS load per MFMA.
