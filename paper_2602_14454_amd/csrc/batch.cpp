@@ -177,6 +177,7 @@ struct NormalHops {
     int nrb = 1, order = 0, kind = ST_F32;
     size_t per_stage = 0;      // HopParams per stage
     size_t meta_per_class = 0;
+    bool stage_loc[4] = {false, false, false, false};   // stage carries a local term
 
     // fields: in/out buffers of storage `kind`; partial/pstride/done for the |q|^2 reduction
     void build(const std::vector<Item>& items, int kind_, int nrb_, int order_, void* p, void* t, void* v, void* w,
@@ -227,6 +228,10 @@ struct NormalHops {
                     P->done_stride = CG_NSLOTS;
                     P->pstride = pstride;
                 }
+                stage_loc[0] = s1.loc != nullptr;
+                stage_loc[1] = s2.loc != nullptr;
+                stage_loc[2] = s3.loc != nullptr;
+                stage_loc[3] = s4.loc != nullptr;
                 hp[0 * per_stage + pos] = s1;
                 hp[1 * per_stage + pos] = s2;
                 hp[2 * per_stage + pos] = s3;
@@ -247,7 +252,8 @@ struct NormalHops {
         for (size_t ci = 0; ci < classes.size(); ++ci) {
             const HopParams* it = items_dev.as<HopParams>() + sidx * per_stage + first;
             const int* m = meta_dev.as<int>() + ci * meta_per_class;
-            launch_hop_batch(kind, classes[ci].KK, it, m, (int)classes[ci].items.size(), blocks[ci], nrb, order, st);
+            launch_hop_batch(kind, classes[ci].KK, it, m, (int)classes[ci].items.size(), blocks[ci], nrb, order,
+                             stage_loc[sidx], st);
             first += classes[ci].items.size();
         }
     }

@@ -46,9 +46,10 @@ int hop_grid_blocks(long Vh);
 void launch_hop(int kind, const HopParams& P, int nrhs, hipStream_t st, int bench_tag = 0);
 // One work-list launch over `nitems` HopParams (device array `items`, same
 // ceil(Ls/4) = KK for all) with block prefix sums and RHS counts in `meta`
-// (device, 2 * nitems + 1 ints); `blocks` = meta[nitems].
+// (device, 2 * nitems + 1 ints); `blocks` = meta[nitems].  has_loc: the
+// items carry a local term (all or none of them).
 void launch_hop_batch(int kind, int KK, const HopParams* items, const int* meta, int nitems, int blocks, int nrb,
-                      int order, hipStream_t st);
+                      int order, bool has_loc, hipStream_t st);
 void launch_copy(void* dst, const void* src, size_t bytes, hipStream_t st);
 void launch_mix(int kind, const MixParams& P, int nrhs, hipStream_t st);
 

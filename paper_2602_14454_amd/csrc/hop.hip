@@ -68,6 +68,21 @@ namespace dwf {
 #ifndef DWF_HOP_LDS_LINKS
 #define DWF_HOP_LDS_LINKS 1
 #endif
+// FP32/BF16: stage the local-term field of the tile in LDS with 16-byte loads
+// at block start, and write the outputs through an LDS tile so that every
+// global store is a whole 16-byte group (the MFMA leaves one complex number
+// per lane, which would otherwise be written by 2-4 partial stores per group).
+#ifndef DWF_HOP_TILE_IO
+#define DWF_HOP_TILE_IO 1
+#endif
+// Local-term tile in LDS for BF16 / FP32 launches.  Off for FP32: its 24 KB
+// tile costs a block per CU, and the solve was measured faster without it.
+#ifndef DWF_HOP_LOC_LDS16
+#define DWF_HOP_LOC_LDS16 1
+#endif
+#ifndef DWF_HOP_LOC_LDS32
+#define DWF_HOP_LOC_LDS32 0
+#endif
 typedef float v4f __attribute__((ext_vector_type(4)));
 typedef double v4d __attribute__((ext_vector_type(4)));
 
@@ -288,7 +303,8 @@ __host__ __device__ constexpr int hop_waves(int KK, bool f64) { return KK / hop_
 //           that is exactly the MFMA B operand for k-step w.
 //  phase 2: wave w takes 12/KK of the 12 spin-colour components; for each it
 //           runs the dense s-mixes as KK MFMAs per real part with B read back
-//           from LDS, adds the local term and stores.
+//           from LDS, plus the local term as more MFMAs, and stores (FP32 and
+//           BF16 through LDS, as whole 16-byte groups).
 // Keeping one 4-slice group per wave (instead of all Ls slices) keeps the
 // data a wave touches, and its registers, four times smaller; that lets an
 // XCD's 4 MB L2 hold the neighbour reuse window.
@@ -300,12 +316,47 @@ __host__ __device__ constexpr int hop_waves(int KK, bool f64) { return KK / hop_
 // norm.  Both kernels below call it.
 template <class S> constexpr int lnk_entries() { return 8 * link_ng(cbytes<S>()) * 16; }
 
+// Shared memory of one block (dynamic, bytes from the host):
+//   [0, r0)       phase 1: the tile's links and neighbour indices;
+//                 then hs, the hop result (MFMA B operand), hs[kk][r][lane]
+//                 at kk * HSK + r * 64 + lane (HSK padded so that the four
+//                 slice groups of a wave fall on different banks);
+//                 FP32/BF16 then reuse the rows 2 cp, 2 cp + 1 of every kk
+//                 (read only by the wave that owns component cp) for the
+//                 output of component cp: slice 4 kk + i, site jj at
+//                 complex (i * 16 + jj) of that 128-value run
+//   [r0, r0+32)   per-wave partial norms
+//   [r0+32, ...)  local-term tile, 16-byte groups [s][group][site]
+//                 (FP32/BF16 launches with a local term only)
+template <class S, int KK> struct HopSmem {
+    using R = typename Traits<S>::R;
+    static constexpr bool TIO = DWF_HOP_TILE_IO && sizeof(S) < 8;
+    static constexpr bool LOC = TIO && (sizeof(S) == 2 ? DWF_HOP_LOC_LDS16 : DWF_HOP_LOC_LDS32);
+    static constexpr int PK = fpack<S>();
+    static constexpr int NGR = 12 / PK;
+    static constexpr int HSK = 24 * 64 + (sizeof(R) == 4 ? 16 : 8);
+    static constexpr unsigned hs_b = KK * HSK * sizeof(R);
+    static constexpr unsigned lnk_b = lnk_entries<S>() * 16 + 128 * 4;
+    static constexpr unsigned mx = hs_b > lnk_b ? hs_b : lnk_b;
+    static constexpr unsigned r0 = (mx + 15u) & ~15u;
+    static constexpr unsigned red_off = r0;
+    static constexpr unsigned loc_off = r0 + 32;
+    static constexpr unsigned loc_b = LOC ? KK * 4 * NGR * 16 * 16 : 0u;
+    static constexpr unsigned bytes(bool has_loc) { return loc_off + (has_loc ? loc_b : 0u); }
+};
+
 template <class S, int KK>
 __device__ __forceinline__ void hop_tile(const HopParams& P, long tile, int rhs, double* part_out,
-                                         typename Traits<S>::R (&hs)[KK][24][64], double (&red)[4],
-                                         u32x4 (&lnk)[lnk_entries<S>()], unsigned (&lnbr)[128]) {
+                                         unsigned char* smem) {
     using R = typename Traits<S>::R;
     using V = typename Vec4<R>::T;
+    using L = HopSmem<S, KK>;
+    R* hs = reinterpret_cast<R*>(smem);   // hs[kk][r][lane] at kk * HSK + r * 64 + lane
+    constexpr int HSK = L::HSK;
+    u32x4* lnk = reinterpret_cast<u32x4*>(smem);
+    unsigned* lnbr = reinterpret_cast<unsigned*>(smem + lnk_entries<S>() * 16);
+    double* red = reinterpret_cast<double*>(smem + L::red_off);
+    u32x4* locT = reinterpret_cast<u32x4*>(smem + L::loc_off);
     const int lane = threadIdx.x & 63;
     const int w = threadIdx.x >> 6;
     const int j = lane & 15, sc = lane >> 4;
@@ -344,8 +395,22 @@ __device__ __forceinline__ void hop_tile(const HopParams& P, long tile, int rhs,
             const unsigned sxe = (unsigned)(se < Vh ? se : Vh - 1);
             lnbr[e] = __builtin_amdgcn_raw_buffer_load_b32(R_.nbr, sxe * 4u + (unsigned)d * Vhp * 4u, 0u, 0);
         }
-        __syncthreads();
     }
+    if constexpr (L::LOC) {
+        // local-term tile: group (s, q) of site jj at locT[(s * NGR + q) * 16 + jj];
+        // slices s >= Ls are zero (they meet zero columns of the local mixes)
+        if (P.loc != nullptr) {
+            for (int e = threadIdx.x; e < KK * 4 * L::NGR * 16; e += blockDim.x) {
+                const int jj = e & 15, g = e >> 4;
+                const long se = tile * 16 + jj;
+                const unsigned sxe = (unsigned)(se < Vh ? se : Vh - 1);
+                u32x4 v = {0u, 0u, 0u, 0u};
+                if (g < Ls * L::NGR) v = __builtin_amdgcn_raw_buffer_load_b128(R_.loc, sxe * 16u + (unsigned)g * gb, 0u, 0);
+                locT[e] = v;
+            }
+        }
+    }
+    if constexpr (DWF_HOP_LDS_LINKS || L::LOC) __syncthreads();
 
     {
         constexpr int G = hop_kpw(KK, sizeof(S) == 8);
@@ -376,14 +441,18 @@ __device__ __forceinline__ void hop_tile(const HopParams& P, long tile, int rhs,
 #pragma unroll DWF_HOP_UNROLL
         for (int d = 0; d < 8; ++d)
             hop_direction<S, G>(P, R_, gb, (unsigned)sx, d, ynb[d], sg, pd, pe, h, lnk, lnbr, j);
+        __syncthreads();   // hs shares storage with the staged links
 #pragma unroll
         for (int g = 0; g < G; ++g)
 #pragma unroll
-            for (int k = 0; k < 24; ++k) hs[w * G + g][k][lane] = h[g][k];
+            for (int k = 0; k < 24; ++k) hs[(w * G + g) * HSK + k * 64 + lane] = h[g][k];
     }
     __syncthreads();
 
-    // A operands: A[m][k] = MAT[chi][row m = j][col 4*kk + sc]
+    // A operands: A[m][k] = MAT[chi][row m = j][col 4*kk + sc].  A dense
+    // local mix (LOCMIX, LOCMIX2) enters as more MFMAs with B = the local
+    // field in the hs layout; loc_scale times the identity is a plain add
+    // when the local tile is in LDS, else one more MFMA set.
     const R* post = static_cast<const R*>(P.post);
     const R* lmix = static_cast<const R*>(P.locmix);
     const R* post2 = static_cast<const R*>(P.post2);
@@ -394,7 +463,11 @@ __device__ __forceinline__ void hop_tile(const HopParams& P, long tile, int rhs,
     const R lscale = R(P.loc_scale);
     constexpr int CPW = 12 / hop_waves(KK, sizeof(S) == 8);
 
+    // FP32/BF16: the primary output (out, else out2) goes through LDS; a
+    // second output, if any, is stored directly
+    const bool tile_out = L::TIO && (P.out != nullptr || has_out2);
     double nrm = 0.0;
+#pragma unroll
     for (int q = 0; q < CPW; ++q) {
         const int cp = w * CPW + q;
         const int chi = cp >= 6 ? 1 : 0;
@@ -403,55 +476,74 @@ __device__ __forceinline__ void hop_tile(const HopParams& P, long tile, int rhs,
         for (int kk = 0; kk < KK; ++kk) {
             const int idx = (chi * 16 + j) * 16 + 4 * kk + sc;
             ap[kk] = post[idx];
-            al[kk] = dense_loc ? lmix[idx] : R(0);
+            al[kk] = dense_loc ? lmix[idx] : ((has_loc && !L::LOC && j == 4 * kk + sc) ? lscale : R(0));
             ap2[kk] = has_out2 ? post2[idx] : R(0);
             al2[kk] = (has_out2 && has_loc) ? lmix2[idx] : R(0);
         }
-        // B-layout local values (needed by dense loc mixes)
+        // local values in the B layout: slice 4 kk + sc of site j
         R lr[KK], li[KK];
 #pragma unroll
         for (int kk = 0; kk < KK; ++kk) { lr[kk] = 0; li[kk] = 0; }
-        if (dense_loc || (has_out2 && has_loc)) {
+        const bool loc_mfma = dense_loc || (has_loc && !L::LOC);
+        if (loc_mfma || (has_out2 && has_loc)) {
 #pragma unroll
             for (int kk = 0; kk < KK; ++kk) {
                 const int s = sc + 4 * kk;
-                if (s < Ls) bload<S>(R_.loc, sxb + (unsigned)s * (12u / PK) * gb, (cp / PK) * gb + (cp % PK) * CB, lr[kk], li[kk]);
+                if constexpr (L::LOC) {
+                    const int e = (s * L::NGR + cp / L::PK) * 16 + j;
+                    if constexpr (sizeof(S) == 4) {
+                        const u32x2 v = reinterpret_cast<const u32x2*>(locT)[e * 2 + cp % 2];
+                        lr[kk] = __uint_as_float(v.x);
+                        li[kk] = __uint_as_float(v.y);
+                    } else {
+                        const unsigned v = reinterpret_cast<const unsigned*>(locT)[e * 4 + cp % 4];
+                        lr[kk] = bf16_to_f32(v & 0xffffu);
+                        li[kk] = bf16_to_f32(v >> 16);
+                    }
+                } else {
+                    if (s < Ls) bload<S>(R_.loc, sxb + (unsigned)s * (12u / PK) * gb, (cp / PK) * gb + (cp % PK) * CB, lr[kk], li[kk]);
+                }
             }
         }
         V cr = {0, 0, 0, 0}, ci = {0, 0, 0, 0};
 #pragma unroll
         for (int kk = 0; kk < KK; ++kk) {
-            cr = mfma4(ap[kk], hs[kk][2 * cp][lane], cr);
-            ci = mfma4(ap[kk], hs[kk][2 * cp + 1][lane], ci);
+            cr = mfma4(ap[kk], hs[kk * HSK + (2 * cp) * 64 + lane], cr);
+            ci = mfma4(ap[kk], hs[kk * HSK + (2 * cp + 1) * 64 + lane], ci);
         }
-        if (dense_loc) {
+        if (loc_mfma) {
 #pragma unroll
             for (int kk = 0; kk < KK; ++kk) {
                 cr = mfma4(al[kk], lr[kk], cr);
                 ci = mfma4(al[kk], li[kk], ci);
             }
         }
+        if constexpr (L::LOC) {
+            if (has_loc && !dense_loc) {
 #pragma unroll
-        for (int i = 0; i < 4; ++i) {
-            const int s = out_row<R>(sc, i);
-            R orr = cr[i], oi = ci[i];
-            if (has_loc && !dense_loc && s < Ls) {
-                R xr, xi;
-                bload<S>(R_.loc, sxb + (unsigned)s * (12u / PK) * gb, (cp / PK) * gb + (cp % PK) * CB, xr, xi);
-                orr += lscale * xr;
-                oi += lscale * xi;
-            }
-            if (valid && s < Ls) {
-                if (P.out) bstore<S>(R_.out, sxb + (unsigned)s * (12u / PK) * gb, (cp / PK) * gb + (cp % PK) * CB, orr, oi);
-                if (P.reduce == 1) nrm += double(orr) * double(orr) + double(oi) * double(oi);
+                for (int i = 0; i < 4; ++i) {   // row layout: slice out_row(sc, i) of site j
+                    const int e = (out_row<R>(sc, i) * L::NGR + cp / L::PK) * 16 + j;
+                    R xr, xi;
+                    if constexpr (sizeof(S) == 4) {
+                        const u32x2 v = reinterpret_cast<const u32x2*>(locT)[e * 2 + cp % 2];
+                        xr = __uint_as_float(v.x);
+                        xi = __uint_as_float(v.y);
+                    } else {
+                        const unsigned v = reinterpret_cast<const unsigned*>(locT)[e * 4 + cp % 4];
+                        xr = bf16_to_f32(v & 0xffffu);
+                        xi = bf16_to_f32(v >> 16);
+                    }
+                    cr[i] += lscale * xr;
+                    ci[i] += lscale * xi;
+                }
             }
         }
+        V dr = {0, 0, 0, 0}, di = {0, 0, 0, 0};
         if (has_out2) {
-            V dr = {0, 0, 0, 0}, di = {0, 0, 0, 0};
 #pragma unroll
             for (int kk = 0; kk < KK; ++kk) {
-                dr = mfma4(ap2[kk], hs[kk][2 * cp][lane], dr);
-                di = mfma4(ap2[kk], hs[kk][2 * cp + 1][lane], di);
+                dr = mfma4(ap2[kk], hs[kk * HSK + (2 * cp) * 64 + lane], dr);
+                di = mfma4(ap2[kk], hs[kk * HSK + (2 * cp + 1) * 64 + lane], di);
             }
             if (has_loc) {
 #pragma unroll
@@ -460,13 +552,65 @@ __device__ __forceinline__ void hop_tile(const HopParams& P, long tile, int rhs,
                     di = mfma4(al2[kk], li[kk], di);
                 }
             }
+        }
 #pragma unroll
-            for (int i = 0; i < 4; ++i) {
-                const int s = out_row<R>(sc, i);
-                if (valid && s < Ls) {
+        for (int i = 0; i < 4; ++i) {
+            const int s = out_row<R>(sc, i);
+            if (valid && s < Ls) {
+                if (P.reduce == 1) nrm += double(cr[i]) * double(cr[i]) + double(ci[i]) * double(ci[i]);
+                if (P.reduce == 2) nrm += double(dr[i]) * double(dr[i]) + double(di[i]) * double(di[i]);
+                if (!tile_out) {
+                    if (P.out) bstore<S>(R_.out, sxb + (unsigned)s * (12u / PK) * gb, (cp / PK) * gb + (cp % PK) * CB, cr[i], ci[i]);
+                    if (has_out2) bstore<S>(R_.out2, sxb + (unsigned)s * (12u / PK) * gb, (cp / PK) * gb + (cp % PK) * CB, dr[i], di[i]);
+                } else if (P.out && has_out2) {
                     bstore<S>(R_.out2, sxb + (unsigned)s * (12u / PK) * gb, (cp / PK) * gb + (cp % PK) * CB, dr[i], di[i]);
-                    if (P.reduce == 2) nrm += double(dr[i]) * double(dr[i]) + double(di[i]) * double(di[i]);
                 }
+            }
+        }
+        if constexpr (L::TIO) {
+            if (tile_out) {
+                // this wave alone read rows 2 cp, 2 cp + 1 of hs: overwrite them
+                // with the component's output (slice 4 kk + i at i * 16 + jj)
+#pragma unroll
+                for (int i = 0; i < 4; ++i) {
+                    const int s = out_row<R>(sc, i);
+                    if (s >= Ls) continue;   // rows past Ls: zero columns, and past the hs runs when KK < 4
+                    const R orr = P.out ? cr[i] : dr[i];
+                    const R oi = P.out ? ci[i] : di[i];
+                    R* run = hs + (s >> 2) * HSK + (2 * cp) * 64;
+                    if constexpr (sizeof(S) == 4) {
+                        reinterpret_cast<float2*>(run)[(s & 3) * 16 + j] = make_float2(orr, oi);
+                    } else {
+                        reinterpret_cast<unsigned*>(run)[(s & 3) * 16 + j] = f32_to_bf16(orr) | (f32_to_bf16(oi) << 16);
+                    }
+                }
+            }
+        }
+    }
+
+    if constexpr (L::TIO) {
+        if (tile_out) {
+            // whole 16-byte groups of 16 consecutive sites
+            __syncthreads();
+            const __amdgpu_buffer_rsrc_t dst = P.out ? R_.out : R_.out2;
+            for (int e = threadIdx.x; e < Ls * L::NGR * 16; e += blockDim.x) {
+                const int jj = e & 15, g = e >> 4;
+                const int sl = g / L::NGR, q = g - sl * L::NGR;
+                const long se = tile * 16 + jj;
+                const R* run0 = hs + (sl >> 2) * HSK + (sl & 3) * 16 * (int)(CB / 4) + jj * (int)(CB / 4);
+                u32x4 v;
+                if constexpr (sizeof(S) == 4) {
+                    const u32x2 a = *reinterpret_cast<const u32x2*>(run0 + (2 * (2 * q)) * 64);
+                    const u32x2 b = *reinterpret_cast<const u32x2*>(run0 + (2 * (2 * q + 1)) * 64);
+                    v.x = a.x; v.y = a.y; v.z = b.x; v.w = b.y;
+                } else {
+                    const unsigned* r = reinterpret_cast<const unsigned*>(run0);
+                    v.x = r[(2 * (4 * q)) * 64];
+                    v.y = r[(2 * (4 * q + 1)) * 64];
+                    v.z = r[(2 * (4 * q + 2)) * 64];
+                    v.w = r[(2 * (4 * q + 3)) * 64];
+                }
+                if (se < Vh) __builtin_amdgcn_raw_buffer_store_b128(v, dst, (unsigned)se * 16u + (unsigned)g * gb, 0u, 0);
             }
         }
     }
@@ -488,12 +632,10 @@ template <class S, int KK, int TAG = 0>
 __global__ __launch_bounds__(256)
 __attribute__((amdgpu_waves_per_eu(sizeof(S) == 8 ? DWF_HOP_WAVES_PER_EU64 : DWF_HOP_WAVES_PER_EU)))
 void hop_mfma_kernel(HopParams P) {
-    __shared__ typename Traits<S>::R hs[KK][24][64];
-    __shared__ double red[4];
-    __shared__ u32x4 lnk[lnk_entries<S>()];
-    __shared__ unsigned lnbr[128];
+    extern __shared__ u32x4 hop_smem[];
     hop_tile<S, KK>(P, xcd_block(blockIdx.x, gridDim.x), blockIdx.y,
-                    P.partial ? P.partial + (long)blockIdx.y * gridDim.x + blockIdx.x : nullptr, hs, red, lnk, lnbr);
+                    P.partial ? P.partial + (long)blockIdx.y * gridDim.x + blockIdx.x : nullptr,
+                    reinterpret_cast<unsigned char*>(hop_smem));
 }
 
 // Work-list form for batches: one launch covers several operators (lattices
@@ -511,10 +653,7 @@ __global__ __launch_bounds__(256)
 __attribute__((amdgpu_waves_per_eu(sizeof(S) == 8 ? DWF_HOP_WAVES_PER_EU64 : DWF_HOP_WAVES_PER_EU)))
 void hop_batch_kernel(const HopParams* __restrict__ items, const int* __restrict__ meta, int nitems, int nrb,
                       int order) {
-    __shared__ typename Traits<S>::R hs[KK][24][64];
-    __shared__ double red[4];
-    __shared__ u32x4 lnk[lnk_entries<S>()];
-    __shared__ unsigned lnbr[128];
+    extern __shared__ u32x4 hop_smem[];
     const int b = xcd_block(blockIdx.x, gridDim.x);
     int i = 0;
     while (i + 1 < nitems && b >= meta[i + 1]) ++i;
@@ -533,8 +672,8 @@ void hop_batch_kernel(const HopParams* __restrict__ items, const int* __restrict
             if (part && threadIdx.x == 0) *part = 0.0;
             continue;
         }
-        hop_tile<S, KK>(P, tile, r, part, hs, red, lnk, lnbr);
-        __syncthreads();   // hs and red are reused by the next right-hand side
+        hop_tile<S, KK>(P, tile, r, part, reinterpret_cast<unsigned char*>(hop_smem));
+        __syncthreads();   // shared memory is reused by the next right-hand side
     }
 }
 
@@ -600,6 +739,16 @@ __global__ __launch_bounds__(256) void mix_mfma_kernel(MixParams P) {
 // ---------------------------------------------------------------------
 // launchers
 // ---------------------------------------------------------------------
+template <class S>
+static unsigned hop_smem_bytes(int KK, bool loc) {
+    switch (KK) {
+        case 1: return HopSmem<S, 1>::bytes(loc);
+        case 2: return HopSmem<S, 2>::bytes(loc);
+        case 3: return HopSmem<S, 3>::bytes(loc);
+        default: return HopSmem<S, 4>::bytes(loc);
+    }
+}
+
 int hop_grid_blocks(long Vh) { return (int)((Vh + 15) / 16); }
 static int mix_grid_blocks(long Vh) { return (int)((Vh + 63) / 64); }
 
@@ -607,11 +756,12 @@ template <class S, int TAG>
 static void launch_hop_t(const HopParams& P, int nrhs, hipStream_t st) {
     const int KK = (P.Ls + 3) / 4;
     dim3 grid(hop_grid_blocks(P.Vh), nrhs), block(64 * hop_waves(KK, sizeof(S) == 8));
+    const unsigned smem_b = hop_smem_bytes<S>(KK, P.loc != nullptr);
     switch (KK) {
-        case 1: hipLaunchKernelGGL((hop_mfma_kernel<S, 1, TAG>), grid, block, 0, st, P); break;
-        case 2: hipLaunchKernelGGL((hop_mfma_kernel<S, 2, TAG>), grid, block, 0, st, P); break;
-        case 3: hipLaunchKernelGGL((hop_mfma_kernel<S, 3, TAG>), grid, block, 0, st, P); break;
-        case 4: hipLaunchKernelGGL((hop_mfma_kernel<S, 4, TAG>), grid, block, 0, st, P); break;
+        case 1: hipLaunchKernelGGL((hop_mfma_kernel<S, 1, TAG>), grid, block, smem_b, st, P); break;
+        case 2: hipLaunchKernelGGL((hop_mfma_kernel<S, 2, TAG>), grid, block, smem_b, st, P); break;
+        case 3: hipLaunchKernelGGL((hop_mfma_kernel<S, 3, TAG>), grid, block, smem_b, st, P); break;
+        case 4: hipLaunchKernelGGL((hop_mfma_kernel<S, 4, TAG>), grid, block, smem_b, st, P); break;
         default: throw Error{DWF_EDIMS, "Ls > 16 not supported by the fused hop"};
     }
     DWF_HIP(hipGetLastError());
@@ -619,25 +769,26 @@ static void launch_hop_t(const HopParams& P, int nrhs, hipStream_t st) {
 
 template <class S>
 static void launch_hop_batch_t(int KK, const HopParams* items, const int* meta, int nitems, int blocks, int nrb,
-                               int order, hipStream_t st) {
+                               int order, bool loc, hipStream_t st) {
     dim3 grid(blocks), block(64 * hop_waves(KK, sizeof(S) == 8));
+    const unsigned smem_b = hop_smem_bytes<S>(KK, loc);
     switch (KK) {
-        case 1: hipLaunchKernelGGL((hop_batch_kernel<S, 1>), grid, block, 0, st, items, meta, nitems, nrb, order); break;
-        case 2: hipLaunchKernelGGL((hop_batch_kernel<S, 2>), grid, block, 0, st, items, meta, nitems, nrb, order); break;
-        case 3: hipLaunchKernelGGL((hop_batch_kernel<S, 3>), grid, block, 0, st, items, meta, nitems, nrb, order); break;
-        case 4: hipLaunchKernelGGL((hop_batch_kernel<S, 4>), grid, block, 0, st, items, meta, nitems, nrb, order); break;
+        case 1: hipLaunchKernelGGL((hop_batch_kernel<S, 1>), grid, block, smem_b, st, items, meta, nitems, nrb, order); break;
+        case 2: hipLaunchKernelGGL((hop_batch_kernel<S, 2>), grid, block, smem_b, st, items, meta, nitems, nrb, order); break;
+        case 3: hipLaunchKernelGGL((hop_batch_kernel<S, 3>), grid, block, smem_b, st, items, meta, nitems, nrb, order); break;
+        case 4: hipLaunchKernelGGL((hop_batch_kernel<S, 4>), grid, block, smem_b, st, items, meta, nitems, nrb, order); break;
         default: throw Error{DWF_EDIMS, "Ls > 16 not supported by the fused hop"};
     }
     DWF_HIP(hipGetLastError());
 }
 
 void launch_hop_batch(int kind, int KK, const HopParams* items, const int* meta, int nitems, int blocks, int nrb,
-                      int order, hipStream_t st) {
+                      int order, bool has_loc, hipStream_t st) {
     if (blocks <= 0) return;
     switch (kind) {
-        case ST_F64: launch_hop_batch_t<double>(KK, items, meta, nitems, blocks, nrb, order, st); break;
-        case ST_F32: launch_hop_batch_t<float>(KK, items, meta, nitems, blocks, nrb, order, st); break;
-        case ST_BF16: launch_hop_batch_t<bf16s>(KK, items, meta, nitems, blocks, nrb, order, st); break;
+        case ST_F64: launch_hop_batch_t<double>(KK, items, meta, nitems, blocks, nrb, order, has_loc, st); break;
+        case ST_F32: launch_hop_batch_t<float>(KK, items, meta, nitems, blocks, nrb, order, has_loc, st); break;
+        case ST_BF16: launch_hop_batch_t<bf16s>(KK, items, meta, nitems, blocks, nrb, order, has_loc, st); break;
         default: throw Error{DWF_EINVAL, "bad storage kind"};
     }
 }
