@@ -218,7 +218,8 @@ struct NormalHops {
                 HopParams s1 = hop_params(op, kind, 1, at(p), nullptr, at(t), PRE_K, MAT_Q, -1, 0.0, nullptr, 0, 0,
                                           nullptr, 0);
                 HopParams s2 = hop_params(op, kind, 0, at(t), at(p), nullptr, -1, MAT_MQMINV, -1, 1.0, at(v),
-                                          MAT_G5MIT_MQMINV, MAT_G5MIT, part, 1);
+                                          DWF_CHAIN2 ? MAT_G5MIT : MAT_G5MIT_MQMINV, MAT_G5MIT, part, 1);
+                s2.chain2 = DWF_CHAIN2;   // v = g5 Minv^T q from q itself
                 HopParams s3 = hop_params(op, kind, 1, at(v), nullptr, at(t), -1, MAT_QT, -1, 0.0, nullptr, 0, 0,
                                           nullptr, 0);
                 HopParams s4 = hop_params(op, kind, 0, at(t), at(v), at(w), -1, MAT_MQG5KT, MAT_G5MT, 0.0, nullptr, 0,

@@ -7,6 +7,11 @@ namespace dwf {
 
 // All matrices are compute-type (double for F64 storage, float otherwise),
 // padded to [2 chirality][16][16]; `pre` is [d chi0 | d chi1 | e chi0 | e chi1] x 16.
+// Stage 2 of D^dag D^ forms v = g5 Minv^T q from q itself (1) or as
+// POST2 . h + LOCMIX2 . p (0).
+#ifndef DWF_CHAIN2
+#define DWF_CHAIN2 1
+#endif
 struct HopParams {
     const void* in;        // input half field, parity 1-p
     const void* loc;       // local half field, parity p (nullptr: none)
@@ -25,6 +30,7 @@ struct HopParams {
     int Ls;
     int pre_mode;          // 0 identity, 1 diagonal d, 2 d + e (K sparsity)
     int reduce;            // 1: |out|^2, 2: |out2|^2
+    int chain2;            // 1: out2 = POST2 . (the first result, local term included); LOCMIX2 unused
     double loc_scale;
     // work-list (batch) launches only
     const double* done;    // per-RHS done flags, done[r * done_stride] != 0: skip (nullptr: none)

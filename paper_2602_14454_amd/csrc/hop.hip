@@ -97,6 +97,15 @@ __device__ __forceinline__ v4d mfma4(double a, double b, v4d c) {
     return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
 }
 
+// Orders LDS accesses of the lanes of one wave (data passed between lanes
+// through LDS without a block barrier): the compiler reasons per lane and
+// would otherwise move another lane's read across this lane's write.
+__device__ __forceinline__ void wave_sync() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
 // Row of the 16x16 result held in accumulator slot i of a lane with
 // sc = lane / 16 (column = lane % 16 for both).  Measured on gfx950:
 // v_mfma_f32_16x16x4f32 keeps rows 4*sc .. 4*sc+3, v_mfma_f64_16x16x4f64
@@ -460,6 +469,7 @@ __device__ __forceinline__ void hop_tile(const HopParams& P, long tile, int rhs,
     const bool has_loc = P.loc != nullptr;
     const bool dense_loc = has_loc && lmix != nullptr;
     const bool has_out2 = P.out2 != nullptr;
+    const bool chain = has_out2 && P.chain2 != 0;
     const R lscale = R(P.loc_scale);
     constexpr int CPW = 12 / hop_waves(KK, sizeof(S) == 8);
 
@@ -478,14 +488,14 @@ __device__ __forceinline__ void hop_tile(const HopParams& P, long tile, int rhs,
             ap[kk] = post[idx];
             al[kk] = dense_loc ? lmix[idx] : ((has_loc && !L::LOC && j == 4 * kk + sc) ? lscale : R(0));
             ap2[kk] = has_out2 ? post2[idx] : R(0);
-            al2[kk] = (has_out2 && has_loc) ? lmix2[idx] : R(0);
+            al2[kk] = (has_out2 && has_loc && !chain) ? lmix2[idx] : R(0);
         }
         // local values in the B layout: slice 4 kk + sc of site j
         R lr[KK], li[KK];
 #pragma unroll
         for (int kk = 0; kk < KK; ++kk) { lr[kk] = 0; li[kk] = 0; }
         const bool loc_mfma = dense_loc || (has_loc && !L::LOC);
-        if (loc_mfma || (has_out2 && has_loc)) {
+        if (loc_mfma || (has_out2 && has_loc && !chain)) {
 #pragma unroll
             for (int kk = 0; kk < KK; ++kk) {
                 const int s = sc + 4 * kk;
@@ -539,7 +549,26 @@ __device__ __forceinline__ void hop_tile(const HopParams& P, long tile, int rhs,
             }
         }
         V dr = {0, 0, 0, 0}, di = {0, 0, 0, 0};
-        if (has_out2) {
+        if (chain) {
+            // the first result back to the B layout through the rows 2 cp,
+            // 2 cp + 1 of hs, which only this wave reads (no block barrier),
+            // then out2 = POST2 . result
+            wave_sync();
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                const int s = out_row<R>(sc, i);
+                if (s < 4 * KK) {
+                    hs[(s >> 2) * HSK + (2 * cp) * 64 + 16 * (s & 3) + j] = cr[i];
+                    hs[(s >> 2) * HSK + (2 * cp + 1) * 64 + 16 * (s & 3) + j] = ci[i];
+                }
+            }
+            wave_sync();
+#pragma unroll
+            for (int kk = 0; kk < KK; ++kk) {
+                dr = mfma4(ap2[kk], hs[kk * HSK + (2 * cp) * 64 + lane], dr);
+                di = mfma4(ap2[kk], hs[kk * HSK + (2 * cp + 1) * 64 + lane], di);
+            }
+        } else if (has_out2) {
 #pragma unroll
             for (int kk = 0; kk < KK; ++kk) {
                 dr = mfma4(ap2[kk], hs[kk * HSK + (2 * cp) * 64 + lane], dr);
@@ -571,6 +600,7 @@ __device__ __forceinline__ void hop_tile(const HopParams& P, long tile, int rhs,
             if (tile_out) {
                 // this wave alone read rows 2 cp, 2 cp + 1 of hs: overwrite them
                 // with the component's output (slice 4 kk + i at i * 16 + jj)
+                wave_sync();
 #pragma unroll
                 for (int i = 0; i < 4; ++i) {
                     const int s = out_row<R>(sc, i);

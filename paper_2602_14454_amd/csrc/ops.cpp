@@ -96,8 +96,12 @@ void apply_normal(const dwf_op* op, int kind, void* out_e, const void* in_e, voi
     // t = Q H_oe K p
     hop(op, kind, 1, in_e, nullptr, tmp_o, PRE_K, MAT_Q, -1, 0.0, nullptr, 0, 0, nullptr, 0, nrhs, st);
     // q = (-1/4 Minv) H_eo t + p (not stored, |q|^2 reduced);  v = g5 Minv^T q
-    hop(op, kind, 0, tmp_o, in_e, nullptr, -1, MAT_MQMINV, -1, 1.0, tmp_v, MAT_G5MIT_MQMINV, MAT_G5MIT,
-        qq_partial, qq_partial ? 1 : 0, nrhs, st);
+    {
+        HopParams P = hop_params(op, kind, 0, tmp_o, in_e, nullptr, -1, MAT_MQMINV, -1, 1.0, tmp_v,
+                                 DWF_CHAIN2 ? MAT_G5MIT : MAT_G5MIT_MQMINV, MAT_G5MIT, qq_partial, qq_partial ? 1 : 0);
+        P.chain2 = DWF_CHAIN2;
+        launch_hop(kind, P, nrhs, st);
+    }
     // t = Q^T H_oe v
     hop(op, kind, 1, tmp_v, nullptr, tmp_o, -1, MAT_QT, -1, 0.0, nullptr, 0, 0, nullptr, 0, nrhs, st);
     // out = (-1/4 g5 K^T) H_eo t + g5 M^T v   (= D^dag q)
