@@ -35,6 +35,9 @@ void axpby(int ky, int kx, void* y, const void* x, long n, const double* sa, dou
 void cg_update_xr(int kx, int kp, void* x, void* r, const void* p, const void* w, long n, const double* alpha,
                   double* partial, hipStream_t st, long Vhp = 0);
 void cg_update_p(int kr, int kp, void* p, const void* r, long n, const double* beta, hipStream_t st, long Vhp = 0);
+// x += alpha p; p = r + beta p (x, r of kind kx; p of kind kp)
+void cg_update_px(int kx, int kp, void* x, void* p, const void* r, long n, const double* alpha, const double* beta,
+                  hipStream_t st, long Vhp = 0);
 // y += (ar + i ai) x
 void caxpy(int kind, void* y, const void* x, long n, double ar, double ai, hipStream_t st);
 // FP64 half field(s) of `rows` rows: uniform [-1,1) real and imaginary parts on valid sites

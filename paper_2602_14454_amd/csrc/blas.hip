@@ -227,6 +227,32 @@ __global__ void cg_p_remap_kernel(void* p, const void* r, long nquads, long Vhp,
     }
 }
 
+// x += alpha p; p = r + beta p (the x update of a CG step deferred to the
+// kernel that reads p anyway), operands in different layouts
+template <class SX, class SP>
+__global__ void cg_px_remap_kernel(void* x, void* p, const void* r, long nquads, long Vhp, const double* alpha,
+                                   const double* beta) {
+    using RX = typename Traits<SX>::R;
+    using RP = typename Traits<SP>::R;
+    const RX a = RX(*alpha);
+    const RP b = RP(*beta);
+    for (long t = (long)blockIdx.x * blockDim.x + threadIdx.x; t < nquads; t += (long)gridDim.x * blockDim.x) {
+        const long g = t / Vhp, site = t - g * Vhp;
+        RX xv[8], rv[8];
+        RP pv[8];
+        load4<SP>(p, g, site, Vhp, pv);
+        load4<SX>(x, g, site, Vhp, xv);
+        load4<SX>(r, g, site, Vhp, rv);
+#pragma unroll
+        for (int k = 0; k < 8; ++k) {
+            xv[k] += a * RX(pv[k]);
+            pv[k] = RP(rv[k]) + b * pv[k];
+        }
+        store4<SX>(x, g, site, Vhp, xv);
+        store4<SP>(p, g, site, Vhp, pv);
+    }
+}
+
 template <class S>
 __global__ void norm2_kernel(const void* x, long n, double* partial) {
     __shared__ double red[BLAS_THREADS / 64];
@@ -347,6 +373,24 @@ __global__ void cg_p_kernel(void* p, const void* r, long n, const double* beta) 
         RP pr, pi;
         cload<SR>(r, i, rr, ri);
         cload<SP>(p, i, pr, pi);
+        cstore<SP>(p, i, RP(rr) + b * pr, RP(ri) + b * pi);
+    }
+}
+
+// x += alpha p; p = r + beta p, operands in the same layout
+template <class SX, class SP>
+__global__ void cg_px_kernel(void* x, void* p, const void* r, long n, const double* alpha, const double* beta) {
+    using RX = typename Traits<SX>::R;
+    using RP = typename Traits<SP>::R;
+    const RX a = RX(*alpha);
+    const RP b = RP(*beta);
+    for (long i = (long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (long)gridDim.x * blockDim.x) {
+        RX xr, xi, rr, ri;
+        RP pr, pi;
+        cload<SP>(p, i, pr, pi);
+        cload<SX>(x, i, xr, xi);
+        cload<SX>(r, i, rr, ri);
+        cstore<SX>(x, i, xr + a * RX(pr), xi + a * RX(pi));
         cstore<SP>(p, i, RP(rr) + b * pr, RP(ri) + b * pi);
     }
 }
@@ -607,6 +651,34 @@ void cg_update_p(int kr, int kp, void* p, const void* r, long n, const double* b
     if (fpack_of(kr) != fpack_of(kp))
         DWF_REQUIRE(Vhp > 0 && n % (4 * Vhp) == 0, DWF_EINVAL, "layout change needs the row stride");
     DISPATCH1(kr, cg_p_t1, kp, p, r, n, Vhp, beta, st);
+    DWF_HIP(hipGetLastError());
+}
+
+template <class SX, class SP>
+static void cg_px_t2(void* x, void* p, const void* r, long n, long Vhp, const double* alpha, const double* beta,
+                     hipStream_t st) {
+    if (fpack<SX>() == fpack<SP>())
+        hipLaunchKernelGGL((cg_px_kernel<SX, SP>), dim3(blas_grid(n)), dim3(BLAS_THREADS), 0, st, x, p, r, n, alpha,
+                           beta);
+    else
+        hipLaunchKernelGGL((cg_px_remap_kernel<SX, SP>), dim3(blas_grid(n)), dim3(BLAS_THREADS), 0, st, x, p, r,
+                           n / 4, Vhp, alpha, beta);
+}
+template <class SX>
+static void cg_px_t1(int kp, void* x, void* p, const void* r, long n, long Vhp, const double* alpha,
+                     const double* beta, hipStream_t st) {
+    switch (kp) {
+        case ST_F64: cg_px_t2<SX, double>(x, p, r, n, Vhp, alpha, beta, st); break;
+        case ST_F32: cg_px_t2<SX, float>(x, p, r, n, Vhp, alpha, beta, st); break;
+        case ST_BF16: cg_px_t2<SX, bf16s>(x, p, r, n, Vhp, alpha, beta, st); break;
+        default: throw Error{DWF_EINVAL, "bad storage kind"};
+    }
+}
+void cg_update_px(int kx, int kp, void* x, void* p, const void* r, long n, const double* alpha, const double* beta,
+                  hipStream_t st, long Vhp) {
+    if (fpack_of(kx) != fpack_of(kp))
+        DWF_REQUIRE(Vhp > 0 && n % (4 * Vhp) == 0, DWF_EINVAL, "layout change needs the row stride");
+    DISPATCH1(kx, cg_px_t1, kp, x, p, r, n, Vhp, alpha, beta, st);
     DWF_HIP(hipGetLastError());
 }
 

@@ -29,9 +29,15 @@ struct HopParams {
     long Vhp;              // padded row stride of fields, links and neighbour table
     int Ls;
     int pre_mode;          // 0 identity, 1 diagonal d, 2 d + e (K sparsity)
-    int reduce;            // 1: |out|^2, 2: |out2|^2
+    int reduce;            // 1: |out|^2, 2: |out2|^2, 3: |upd|^2 after the update
     int chain2;            // 1: out2 = POST2 . (the first result, local term included); LOCMIX2 unused
     double loc_scale;
+    // fused CG update (nullptr: none; needs out == out2 == nullptr):
+    // upd -= (*upd_alpha) * (first result), the result itself is not stored.
+    // upd holds the compute type (FP64 for FP64 launches, FP32 otherwise) in
+    // that type's own field layout.
+    void* upd;
+    const double* upd_alpha;
     // work-list (batch) launches only
     const double* done;    // per-RHS done flags, done[r * done_stride] != 0: skip (nullptr: none)
     long done_stride;

@@ -201,7 +201,7 @@ __device__ __forceinline__ void hop_dir(const R* __restrict__ U, const R* __rest
 
 // Buffer descriptors of one hop launch (wave-uniform, scalar registers).
 struct HopRes {
-    __amdgpu_buffer_rsrc_t in, loc, out, out2, links, nbr;
+    __amdgpu_buffer_rsrc_t in, loc, out, out2, upd, links, nbr;
 };
 
 template <class S, int G>
@@ -385,6 +385,10 @@ __device__ __forceinline__ void hop_tile(const HopParams& P, long tile, int rhs,
     R_.loc = make_rsrc(P.loc ? static_cast<const char*>(P.loc) + rhsb : nullptr, P.loc ? fieldb : 0u);
     R_.out = make_rsrc(P.out ? static_cast<const char*>(P.out) + rhsb : nullptr, P.out ? fieldb : 0u);
     R_.out2 = make_rsrc(P.out2 ? static_cast<const char*>(P.out2) + rhsb : nullptr, P.out2 ? fieldb : 0u);
+    // fused CG update target: compute type in its own layout
+    constexpr unsigned PKU = fpack<typename std::conditional<sizeof(R) == 8, double, float>::type>();
+    const unsigned fieldu = (unsigned)Ls * 12u * (unsigned)P.Vhp * 2u * (unsigned)sizeof(R);
+    R_.upd = make_rsrc(P.upd ? static_cast<char*>(P.upd) + (size_t)rhs * fieldu : nullptr, P.upd ? fieldu : 0u);
     R_.links = make_rsrc(P.links, 8u * link_ng(CB) * (unsigned)P.Vhp * link_lp(CB) * CB);
     R_.nbr = make_rsrc(P.nbr, 8u * (unsigned)P.Vhp * 4u);
 
@@ -475,7 +479,9 @@ __device__ __forceinline__ void hop_tile(const HopParams& P, long tile, int rhs,
 
     // FP32/BF16: the primary output (out, else out2) goes through LDS; a
     // second output, if any, is stored directly
-    const bool tile_out = L::TIO && (P.out != nullptr || has_out2);
+    const bool upd = P.upd != nullptr;
+    const R ua = upd ? R(*P.upd_alpha) : R(0);
+    const bool tile_out = L::TIO && (P.out != nullptr || has_out2 || upd);
     double nrm = 0.0;
 #pragma unroll
     for (int q = 0; q < CPW; ++q) {
@@ -589,6 +595,14 @@ __device__ __forceinline__ void hop_tile(const HopParams& P, long tile, int rhs,
                 if (P.reduce == 1) nrm += double(cr[i]) * double(cr[i]) + double(ci[i]) * double(ci[i]);
                 if (P.reduce == 2) nrm += double(dr[i]) * double(dr[i]) + double(di[i]) * double(di[i]);
                 if (!tile_out) {
+                    if (upd) {   // FP64: upd has the layout of out
+                        R ur, ui;
+                        bload<S>(R_.upd, sxb + (unsigned)s * (12u / PK) * gb, (cp / PK) * gb + (cp % PK) * CB, ur, ui);
+                        ur -= ua * cr[i];
+                        ui -= ua * ci[i];
+                        bstore<S>(R_.upd, sxb + (unsigned)s * (12u / PK) * gb, (cp / PK) * gb + (cp % PK) * CB, ur, ui);
+                        if (P.reduce == 3) nrm += double(ur) * double(ur) + double(ui) * double(ui);
+                    }
                     if (P.out) bstore<S>(R_.out, sxb + (unsigned)s * (12u / PK) * gb, (cp / PK) * gb + (cp % PK) * CB, cr[i], ci[i]);
                     if (has_out2) bstore<S>(R_.out2, sxb + (unsigned)s * (12u / PK) * gb, (cp / PK) * gb + (cp % PK) * CB, dr[i], di[i]);
                 } else if (P.out && has_out2) {
@@ -605,10 +619,10 @@ __device__ __forceinline__ void hop_tile(const HopParams& P, long tile, int rhs,
                 for (int i = 0; i < 4; ++i) {
                     const int s = out_row<R>(sc, i);
                     if (s >= Ls) continue;   // rows past Ls: zero columns, and past the hs runs when KK < 4
-                    const R orr = P.out ? cr[i] : dr[i];
-                    const R oi = P.out ? ci[i] : di[i];
+                    const R orr = (P.out || upd) ? cr[i] : dr[i];
+                    const R oi = (P.out || upd) ? ci[i] : di[i];
                     R* run = hs + (s >> 2) * HSK + (2 * cp) * 64;
-                    if constexpr (sizeof(S) == 4) {
+                    if (sizeof(S) == 4 || upd) {   // FP32 values (the update needs them unrounded)
                         reinterpret_cast<float2*>(run)[(s & 3) * 16 + j] = make_float2(orr, oi);
                     } else {
                         reinterpret_cast<unsigned*>(run)[(s & 3) * 16 + j] = f32_to_bf16(orr) | (f32_to_bf16(oi) << 16);
@@ -619,7 +633,32 @@ __device__ __forceinline__ void hop_tile(const HopParams& P, long tile, int rhs,
     }
 
     if constexpr (L::TIO) {
-        if (tile_out) {
+        if (upd) {
+            // upd -= alpha * result over upd's own groups (FP32 pairs)
+            static_assert(PKU == 2, "fused update expects FP32 fields in component pairs");
+            __syncthreads();
+            const unsigned gbu = (unsigned)P.Vhp * 16u;
+            for (int e = threadIdx.x; e < Ls * 6 * 16; e += blockDim.x) {
+                const int jj = e & 15, g = e >> 4;
+                const int sl = g / 6, q2 = g - sl * 6;
+                const long se = tile * 16 + jj;
+                const float* run0 = hs + (sl >> 2) * HSK + 2 * ((sl & 3) * 16 + jj);
+                const float2 a = *reinterpret_cast<const float2*>(run0 + (2 * (2 * q2)) * 64);
+                const float2 b = *reinterpret_cast<const float2*>(run0 + (2 * (2 * q2 + 1)) * 64);
+                if (se < Vh) {
+                    const unsigned off = (unsigned)se * 16u + (unsigned)g * gbu;
+                    const u32x4 u = __builtin_amdgcn_raw_buffer_load_b128(R_.upd, off, 0u, 0);
+                    float v0 = __uint_as_float(u.x) - ua * a.x, v1 = __uint_as_float(u.y) - ua * a.y;
+                    float v2 = __uint_as_float(u.z) - ua * b.x, v3 = __uint_as_float(u.w) - ua * b.y;
+                    u32x4 o;
+                    o.x = __float_as_uint(v0); o.y = __float_as_uint(v1); o.z = __float_as_uint(v2); o.w = __float_as_uint(v3);
+                    __builtin_amdgcn_raw_buffer_store_b128(o, R_.upd, off, 0u, 0);
+                    if (P.reduce == 3)
+                        nrm += double(v0) * double(v0) + double(v1) * double(v1) + double(v2) * double(v2) +
+                               double(v3) * double(v3);
+                }
+            }
+        } else if (tile_out) {
             // whole 16-byte groups of 16 consecutive sites
             __syncthreads();
             const __amdgpu_buffer_rsrc_t dst = P.out ? R_.out : R_.out2;

@@ -79,11 +79,11 @@ int cgnr(const dwf_op* op, CgWork& W, const void* b_kp, double tol_rel, int maxi
     int k = 0;
     double rr = rr0;
     while (k < maxiter) {
-        apply_normal(op, W.kp, W.w.p, W.p.p, W.t.p, W.v.p, partial, W.nrhs, st);
-        finalize(partial, hop_partials(op, W.nrhs), 1, scal, 1, st);
-        cg_update_xr(W.kx, W.kp, W.x.p, W.r.p, W.p.p, W.w.p, n, scal + CG_ALPHA, partial, st, op->lat->Vhp);
-        finalize(partial, blas_grid(n), 1, scal, 2, st);
-        cg_update_p(W.kx, W.kp, W.p.p, W.r.p, n, scal + CG_BETA, st, op->lat->Vhp);
+        // alpha, then r -= alpha D^dag D^ p inside the last hop (|r|^2 partials);
+        // the x update rides on the p update, which reads p anyway
+        apply_normal_update_r(op, W.kp, W.r.p, W.p.p, W.t.p, W.v.p, partial, scal, W.nrhs, st);
+        finalize(partial, hop_partials(op, W.nrhs), 1, scal, 2, st);
+        cg_update_px(W.kx, W.kp, W.x.p, W.p.p, W.r.p, n, scal + CG_ALPHA, scal + CG_BETA, st, op->lat->Vhp);
         ++k;
         if (on_iter) on_iter(k, W.x.p);
         if (k % check_every == 0 || k == maxiter) {
