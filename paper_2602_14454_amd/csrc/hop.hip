@@ -134,10 +134,19 @@ __device__ __forceinline__ int xcd_block(int b, int nb) {
 //   h_up += U w,   h_lo += SG * B^dag (U w)
 // p, h: 12 complex as 24 reals, index (spin*3 + colour)*2 + reim.
 // U: 9 complex as 18 reals, index (row*3 + col)*2 + reim.
+// kr scales the lower half spinor (a diagonal pre-mix d_lo/d_up whose d_up
+// the caller applies to the sum of all directions); 1 otherwise.  The colour
+// products are explicit FMA chains: written as re += ur*xr - ui*xi the
+// compiler keeps a separate product and an add of the running sum per term.
 // ---------------------------------------------------------------------
+template <class R> __device__ __forceinline__ R fmad(R a, R b, R c);
+template <> __device__ __forceinline__ float fmad(float a, float b, float c) { return __builtin_fmaf(a, b, c); }
+template <> __device__ __forceinline__ double fmad(double a, double b, double c) { return __builtin_fma(a, b, c); }
+
 template <int MU, int SG, class R>
 __device__ __forceinline__ void hop_dir(const R* __restrict__ U, const R* __restrict__ p,
-                                        R* __restrict__ h) {
+                                        R* __restrict__ h, R kr) {
+    const R skr = R(SG) * kr;
     R w[12];
 #pragma unroll
     for (int c = 0; c < 3; ++c) {
@@ -153,23 +162,27 @@ __device__ __forceinline__ void hop_dir(const R* __restrict__ U, const R* __rest
         } else {                        // B v = v
             b0r = v0r; b0i = v0i; b1r = v1r; b1i = v1i;
         }
-        w[c * 2] = p[c * 2] + R(SG) * b0r;
-        w[c * 2 + 1] = p[c * 2 + 1] + R(SG) * b0i;
-        w[(3 + c) * 2] = p[(3 + c) * 2] + R(SG) * b1r;
-        w[(3 + c) * 2 + 1] = p[(3 + c) * 2 + 1] + R(SG) * b1i;
+        w[c * 2] = fmad(skr, b0r, p[c * 2]);
+        w[c * 2 + 1] = fmad(skr, b0i, p[c * 2 + 1]);
+        w[(3 + c) * 2] = fmad(skr, b1r, p[(3 + c) * 2]);
+        w[(3 + c) * 2 + 1] = fmad(skr, b1i, p[(3 + c) * 2 + 1]);
     }
     R u[12];
 #pragma unroll
     for (int hs = 0; hs < 2; ++hs)
 #pragma unroll
         for (int a = 0; a < 3; ++a) {
-            R re = 0, im = 0;
+            const R* Ua = U + a * 6;
+            const R* x = w + hs * 6;
+            R re = Ua[0] * x[0], im = Ua[0] * x[1];
+            re = fmad(-Ua[1], x[1], re);
+            im = fmad(Ua[1], x[0], im);
 #pragma unroll
-            for (int b = 0; b < 3; ++b) {
-                const R ur = U[(a * 3 + b) * 2], ui = U[(a * 3 + b) * 2 + 1];
-                const R xr = w[(hs * 3 + b) * 2], xi = w[(hs * 3 + b) * 2 + 1];
-                re += ur * xr - ui * xi;
-                im += ur * xi + ui * xr;
+            for (int b = 1; b < 3; ++b) {
+                re = fmad(Ua[2 * b], x[2 * b], re);
+                re = fmad(-Ua[2 * b + 1], x[2 * b + 1], re);
+                im = fmad(Ua[2 * b], x[2 * b + 1], im);
+                im = fmad(Ua[2 * b + 1], x[2 * b], im);
             }
             u[(hs * 3 + a) * 2] = re;
             u[(hs * 3 + a) * 2 + 1] = im;
@@ -209,6 +222,7 @@ __device__ __forceinline__ void hop_direction(const HopParams& P, const HopRes& 
                                               int D, unsigned ynb, const int (&s)[G],
                                               const typename Traits<S>::R (&pd)[G][2],
                                               const typename Traits<S>::R (&pe)[G][2],
+                                              const typename Traits<S>::R (&kr)[G],
                                               typename Traits<S>::R (&h)[G][24], const u32x4* lnk,
                                               const unsigned* lnbr, int j) {
     using R = typename Traits<S>::R;
@@ -232,11 +246,10 @@ __device__ __forceinline__ void hop_direction(const HopParams& P, const HopRes& 
     const unsigned yg = y * (unsigned)PK * CB; // byte offset of the neighbour in a group row
 #pragma unroll
     for (int g = 0; g < G; ++g) {
-        // Slices beyond Ls (Ls not a multiple of 4) read slice 0 and are zeroed:
-        // branch-free, so the loads of all lanes are issued together; their
-        // hop results meet zero columns of the post-mix.
-        const bool sv = s[g] < Ls;
-        const int sg_ = sv ? s[g] : 0;
+        // Slices beyond Ls (Ls not a multiple of 4) read slice 0 (finite
+        // values; branch-free, so the loads of all lanes are issued together)
+        // and their hop result is zeroed once after the last direction.
+        const int sg_ = s[g] < Ls ? s[g] : 0;
         R p[24];
         // lane-dependent offsets (site, slice) go to the vector operand, the
         // wave-uniform group offset to the scalar one
@@ -248,7 +261,7 @@ __device__ __forceinline__ void hop_direction(const HopParams& P, const HopRes& 
 #pragma unroll
             for (int k = 0; k < 2 * PK; ++k) p[2 * PK * q + k] = v[k];
         }
-        if (P.pre_mode >= 1) {
+        if (P.pre_mode == 2) {   // mode 1 (diagonal) enters through kr and a final scale
 #pragma unroll
             for (int k = 0; k < 12; ++k) p[k] *= pd[g][0];
 #pragma unroll
@@ -284,17 +297,15 @@ __device__ __forceinline__ void hop_direction(const HopParams& P, const HopRes& 
                 }
             }
         }
-#pragma unroll
-        for (int k = 0; k < 24; ++k) p[k] = sv ? p[k] : R(0);
         switch (D) {   // wave-uniform
-            case 0: hop_dir<0, -1, R>(U, p, h[g]); break;
-            case 1: hop_dir<1, -1, R>(U, p, h[g]); break;
-            case 2: hop_dir<2, -1, R>(U, p, h[g]); break;
-            case 3: hop_dir<3, -1, R>(U, p, h[g]); break;
-            case 4: hop_dir<0, +1, R>(U, p, h[g]); break;
-            case 5: hop_dir<1, +1, R>(U, p, h[g]); break;
-            case 6: hop_dir<2, +1, R>(U, p, h[g]); break;
-            default: hop_dir<3, +1, R>(U, p, h[g]); break;
+            case 0: hop_dir<0, -1, R>(U, p, h[g], kr[g]); break;
+            case 1: hop_dir<1, -1, R>(U, p, h[g], kr[g]); break;
+            case 2: hop_dir<2, -1, R>(U, p, h[g], kr[g]); break;
+            case 3: hop_dir<3, -1, R>(U, p, h[g], kr[g]); break;
+            case 4: hop_dir<0, +1, R>(U, p, h[g], kr[g]); break;
+            case 5: hop_dir<1, +1, R>(U, p, h[g], kr[g]); break;
+            case 6: hop_dir<2, +1, R>(U, p, h[g], kr[g]); break;
+            default: hop_dir<3, +1, R>(U, p, h[g], kr[g]); break;
         }
     }
 }
@@ -429,7 +440,7 @@ __device__ __forceinline__ void hop_tile(const HopParams& P, long tile, int rhs,
         constexpr int G = hop_kpw(KK, sizeof(S) == 8);
         R h[G][24];
         int sg[G];
-        R pd[G][2], pe[G][2];
+        R pd[G][2], pe[G][2], kr[G];
         const R* pre = static_cast<const R*>(P.pre);
 #pragma unroll
         for (int g = 0; g < G; ++g) {
@@ -439,6 +450,9 @@ __device__ __forceinline__ void hop_tile(const HopParams& P, long tile, int rhs,
             pd[g][1] = pre ? pre[1 * 16 + sc_] : R(1);
             pe[g][0] = pre ? pre[2 * 16 + sc_] : R(0);
             pe[g][1] = pre ? pre[3 * 16 + sc_] : R(0);
+            // diagonal pre-mix (mode 1; the host guarantees d_up != 0 on valid
+            // slices): lower/upper ratio inside the projection, d_up at the end
+            kr[g] = (P.pre_mode == 1 && pd[g][0] != R(0)) ? pd[g][1] / pd[g][0] : R(1);
 #pragma unroll
             for (int k = 0; k < 24; ++k) h[g][k] = 0;
         }
@@ -452,8 +466,23 @@ __device__ __forceinline__ void hop_tile(const HopParams& P, long tile, int rhs,
                          ? __builtin_amdgcn_raw_buffer_load_b32(R_.nbr, (unsigned)sx * 4u, (unsigned)d * (unsigned)P.Vhp * 4u, 0)
                          : 0u;
 #pragma unroll DWF_HOP_UNROLL
-        for (int d = 0; d < 8; ++d)
-            hop_direction<S, G>(P, R_, gb, (unsigned)sx, d, ynb[d], sg, pd, pe, h, lnk, lnbr, j);
+        for (int d = 0; d < 8; ++d) {
+            hop_direction<S, G>(P, R_, gb, (unsigned)sx, d, ynb[d], sg, pd, pe, kr, h, lnk, lnbr, j);
+            // unrolled: keep each direction's loads after the previous one's
+            // arithmetic (hoisting them all raises the register count past
+            // the occupancy target)
+            if constexpr (DWF_HOP_UNROLL > 1) __builtin_amdgcn_sched_barrier(0);
+        }
+#pragma unroll
+        for (int g = 0; g < G; ++g) {
+            if (P.pre_mode == 1) {
+#pragma unroll
+                for (int k = 0; k < 24; ++k) h[g][k] *= pd[g][0];
+            }
+            const bool inval = sg[g] >= Ls;
+#pragma unroll
+            for (int k = 0; k < 24; ++k) h[g][k] = inval ? R(0) : h[g][k];
+        }
         __syncthreads();   // hs shares storage with the staged links
 #pragma unroll
         for (int g = 0; g < G; ++g)

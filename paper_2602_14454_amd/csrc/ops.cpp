@@ -36,6 +36,12 @@ HopParams hop_params(const dwf_op* op, int kind, int out_parity, const void* in,
     P.nbr = L->nbr.as<int>() + (size_t)out_parity * 8 * Vhp;
     P.pre = pre_slot >= 0 ? op->pre(kind, pre_slot) : nullptr;
     P.pre_mode = pre_slot < 0 ? 0 : (pre_slot == PRE_K && op->c != 0.0 ? 2 : 1);
+    if (P.pre_mode == 1 && pre_slot == PRE_K) {
+        // the kernel factors the upper-chirality diagonal out of the hop sum;
+        // a zero entry takes the general pre-mix path instead
+        for (int s = 0; s < op->Ls; ++s)
+            if (op->fd.K[0][(size_t)s * op->Ls + s] == 0.0) P.pre_mode = 2;
+    }
     P.post = op->mat(kind, post_slot);
     P.locmix = (loc && locmix_slot >= 0) ? op->mat(kind, locmix_slot) : nullptr;
     P.post2 = out2 ? op->mat(kind, post2_slot) : nullptr;
