@@ -72,6 +72,12 @@ namespace dwf {
 // at block start, and write the outputs through an LDS tile so that every
 // global store is a whole 16-byte group (the MFMA leaves one complex number
 // per lane, which would otherwise be written by 2-4 partial stores per group).
+// Wave index marked uniform (readfirstlane).  Off: with it the FP64 CG solve
+// was measured not bit-reproducible run to run on MI355X (the generated code
+// differs in scheduling and register assignment only).
+#ifndef DWF_HOP_W_UNIFORM
+#define DWF_HOP_W_UNIFORM 0
+#endif
 #ifndef DWF_HOP_TILE_IO
 #define DWF_HOP_TILE_IO 1
 #endif
@@ -143,11 +149,14 @@ template <class R> __device__ __forceinline__ R fmad(R a, R b, R c);
 template <> __device__ __forceinline__ float fmad(float a, float b, float c) { return __builtin_fmaf(a, b, c); }
 template <> __device__ __forceinline__ double fmad(double a, double b, double c) { return __builtin_fma(a, b, c); }
 
-template <int MU, int SG, class R>
-__device__ __forceinline__ void hop_dir(const R* __restrict__ U, const R* __restrict__ p,
-                                        R* __restrict__ h, R kr) {
-    const R skr = R(SG) * kr;
-    R w[12];
+// The direction loop runs over a wave-uniform d; only the spin structure
+// depends on mu = d % 4, so the code is split into a projection and a
+// reconstruction per mu around common colour products (a switch over all
+// eight (mu, sign) variants of the whole update leaves the accumulators in
+// different registers per case and costs 24 copies per direction).
+//   w = p_up + skr * B_MU p_lo            (skr = SG * kr)
+template <int MU, class R>
+__device__ __forceinline__ void hop_project(const R* __restrict__ p, R skr, R* __restrict__ w) {
 #pragma unroll
     for (int c = 0; c < 3; ++c) {
         const R v0r = p[(6 + c) * 2], v0i = p[(6 + c) * 2 + 1];
@@ -166,6 +175,46 @@ __device__ __forceinline__ void hop_dir(const R* __restrict__ U, const R* __rest
         w[c * 2 + 1] = fmad(skr, b0i, p[c * 2 + 1]);
         w[(3 + c) * 2] = fmad(skr, b1r, p[(3 + c) * 2]);
         w[(3 + c) * 2 + 1] = fmad(skr, b1i, p[(3 + c) * 2 + 1]);
+    }
+}
+//   h_lo += sg * B_MU^dag u
+template <int MU, class R>
+__device__ __forceinline__ void hop_reconstruct(const R* __restrict__ u, R sg, R* __restrict__ h) {
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+        const R u0r = u[c * 2], u0i = u[c * 2 + 1];
+        const R u1r = u[(3 + c) * 2], u1i = u[(3 + c) * 2 + 1];
+        R* h0 = h + (6 + c) * 2;
+        R* h1 = h + (9 + c) * 2;
+        if constexpr (MU == 0) {        // (i u1, i u0)
+            h0[0] = fmad(-sg, u1i, h0[0]); h0[1] = fmad(sg, u1r, h0[1]);
+            h1[0] = fmad(-sg, u0i, h1[0]); h1[1] = fmad(sg, u0r, h1[1]);
+        } else if constexpr (MU == 1) { // (u1, -u0)
+            h0[0] = fmad(sg, u1r, h0[0]); h0[1] = fmad(sg, u1i, h0[1]);
+            h1[0] = fmad(-sg, u0r, h1[0]); h1[1] = fmad(-sg, u0i, h1[1]);
+        } else if constexpr (MU == 2) { // (i u0, -i u1)
+            h0[0] = fmad(-sg, u0i, h0[0]); h0[1] = fmad(sg, u0r, h0[1]);
+            h1[0] = fmad(sg, u1i, h1[0]); h1[1] = fmad(-sg, u1r, h1[1]);
+        } else {
+            h0[0] = fmad(sg, u0r, h0[0]); h0[1] = fmad(sg, u0i, h0[1]);
+            h1[0] = fmad(sg, u1r, h1[0]); h1[1] = fmad(sg, u1i, h1[1]);
+        }
+    }
+}
+
+// h += (1 + SG gamma_mu) U p for a wave-uniform direction d (mu = d % 4,
+// SG = -1 for d < 4, +1 otherwise), spin-projected as described above.
+template <class R>
+__device__ __forceinline__ void hop_dir(int d, const R* __restrict__ U, const R* __restrict__ p,
+                                        R* __restrict__ h, R kr) {
+    const R sg = d < 4 ? R(-1) : R(1);
+    const R skr = sg * kr;
+    R w[12];
+    switch (d & 3) {   // wave-uniform
+        case 0: hop_project<0, R>(p, skr, w); break;
+        case 1: hop_project<1, R>(p, skr, w); break;
+        case 2: hop_project<2, R>(p, skr, w); break;
+        default: hop_project<3, R>(p, skr, w); break;
     }
     R u[12];
 #pragma unroll
@@ -188,27 +237,12 @@ __device__ __forceinline__ void hop_dir(const R* __restrict__ U, const R* __rest
             u[(hs * 3 + a) * 2 + 1] = im;
         }
 #pragma unroll
-    for (int c = 0; c < 3; ++c) {
-        const R u0r = u[c * 2], u0i = u[c * 2 + 1];
-        const R u1r = u[(3 + c) * 2], u1i = u[(3 + c) * 2 + 1];
-        h[c * 2] += u0r;
-        h[c * 2 + 1] += u0i;
-        h[(3 + c) * 2] += u1r;
-        h[(3 + c) * 2 + 1] += u1i;
-        R l0r, l0i, l1r, l1i;           // B^dag u
-        if constexpr (MU == 0) {        // (i u1, i u0)
-            l0r = -u1i; l0i = u1r; l1r = -u0i; l1i = u0r;
-        } else if constexpr (MU == 1) { // (u1, -u0)
-            l0r = u1r; l0i = u1i; l1r = -u0r; l1i = -u0i;
-        } else if constexpr (MU == 2) { // (i u0, -i u1)
-            l0r = -u0i; l0i = u0r; l1r = u1i; l1i = -u1r;
-        } else {
-            l0r = u0r; l0i = u0i; l1r = u1r; l1i = u1i;
-        }
-        h[(6 + c) * 2] += R(SG) * l0r;
-        h[(6 + c) * 2 + 1] += R(SG) * l0i;
-        h[(9 + c) * 2] += R(SG) * l1r;
-        h[(9 + c) * 2 + 1] += R(SG) * l1i;
+    for (int k = 0; k < 12; ++k) h[k] += u[k];   // h_up += U w
+    switch (d & 3) {
+        case 0: hop_reconstruct<0, R>(u, sg, h); break;
+        case 1: hop_reconstruct<1, R>(u, sg, h); break;
+        case 2: hop_reconstruct<2, R>(u, sg, h); break;
+        default: hop_reconstruct<3, R>(u, sg, h); break;
     }
 }
 
@@ -297,16 +331,7 @@ __device__ __forceinline__ void hop_direction(const HopParams& P, const HopRes& 
                 }
             }
         }
-        switch (D) {   // wave-uniform
-            case 0: hop_dir<0, -1, R>(U, p, h[g], kr[g]); break;
-            case 1: hop_dir<1, -1, R>(U, p, h[g], kr[g]); break;
-            case 2: hop_dir<2, -1, R>(U, p, h[g], kr[g]); break;
-            case 3: hop_dir<3, -1, R>(U, p, h[g], kr[g]); break;
-            case 4: hop_dir<0, +1, R>(U, p, h[g], kr[g]); break;
-            case 5: hop_dir<1, +1, R>(U, p, h[g], kr[g]); break;
-            case 6: hop_dir<2, +1, R>(U, p, h[g], kr[g]); break;
-            default: hop_dir<3, +1, R>(U, p, h[g], kr[g]); break;
-        }
+        hop_dir<R>(D, U, p, h[g], kr[g]);
     }
 }
 
@@ -378,7 +403,11 @@ __device__ __forceinline__ void hop_tile(const HopParams& P, long tile, int rhs,
     double* red = reinterpret_cast<double*>(smem + L::red_off);
     u32x4* locT = reinterpret_cast<u32x4*>(smem + L::loc_off);
     const int lane = threadIdx.x & 63;
+#if DWF_HOP_W_UNIFORM
+    const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);   // wave-uniform, in a scalar register
+#else
     const int w = threadIdx.x >> 6;
+#endif
     const int j = lane & 15, sc = lane >> 4;
     const long Vh = P.Vh;
     const int Ls = P.Ls;
@@ -471,7 +500,10 @@ __device__ __forceinline__ void hop_tile(const HopParams& P, long tile, int rhs,
             // unrolled: keep each direction's loads after the previous one's
             // arithmetic (hoisting them all raises the register count past
             // the occupancy target)
-            if constexpr (DWF_HOP_UNROLL > 1) __builtin_amdgcn_sched_barrier(0);
+            if constexpr (DWF_HOP_UNROLL > 1) {
+                asm volatile("" ::: "memory");
+                __builtin_amdgcn_sched_barrier(0);
+            }
         }
 #pragma unroll
         for (int g = 0; g < G; ++g) {
@@ -511,6 +543,13 @@ __device__ __forceinline__ void hop_tile(const HopParams& P, long tile, int rhs,
     const bool upd = P.upd != nullptr;
     const R ua = upd ? R(*P.upd_alpha) : R(0);
     const bool tile_out = L::TIO && (P.out != nullptr || has_out2 || upd);
+    // byte offset of component cp of slice s of this lane's site; the whole
+    // offset goes to the vector operand (cp depends on the wave index, which
+    // the compiler does not treat as uniform: a scalar operand would be
+    // split into a loop over lanes)
+    auto coff = [&](int s, int cp) -> unsigned {
+        return sxb + (unsigned)s * (12u / PK) * gb + (unsigned)(cp / PK) * gb + (unsigned)(cp % PK) * CB;
+    };
     double nrm = 0.0;
 #pragma unroll
     for (int q = 0; q < CPW; ++q) {
@@ -546,7 +585,7 @@ __device__ __forceinline__ void hop_tile(const HopParams& P, long tile, int rhs,
                         li[kk] = bf16_to_f32(v >> 16);
                     }
                 } else {
-                    if (s < Ls) bload<S>(R_.loc, sxb + (unsigned)s * (12u / PK) * gb, (cp / PK) * gb + (cp % PK) * CB, lr[kk], li[kk]);
+                    if (s < Ls) bload<S>(R_.loc, coff(s, cp), 0u, lr[kk], li[kk]);
                 }
             }
         }
@@ -626,16 +665,16 @@ __device__ __forceinline__ void hop_tile(const HopParams& P, long tile, int rhs,
                 if (!tile_out) {
                     if (upd) {   // FP64: upd has the layout of out
                         R ur, ui;
-                        bload<S>(R_.upd, sxb + (unsigned)s * (12u / PK) * gb, (cp / PK) * gb + (cp % PK) * CB, ur, ui);
+                        bload<S>(R_.upd, coff(s, cp), 0u, ur, ui);
                         ur -= ua * cr[i];
                         ui -= ua * ci[i];
-                        bstore<S>(R_.upd, sxb + (unsigned)s * (12u / PK) * gb, (cp / PK) * gb + (cp % PK) * CB, ur, ui);
+                        bstore<S>(R_.upd, coff(s, cp), 0u, ur, ui);
                         if (P.reduce == 3) nrm += double(ur) * double(ur) + double(ui) * double(ui);
                     }
-                    if (P.out) bstore<S>(R_.out, sxb + (unsigned)s * (12u / PK) * gb, (cp / PK) * gb + (cp % PK) * CB, cr[i], ci[i]);
-                    if (has_out2) bstore<S>(R_.out2, sxb + (unsigned)s * (12u / PK) * gb, (cp / PK) * gb + (cp % PK) * CB, dr[i], di[i]);
+                    if (P.out) bstore<S>(R_.out, coff(s, cp), 0u, cr[i], ci[i]);
+                    if (has_out2) bstore<S>(R_.out2, coff(s, cp), 0u, dr[i], di[i]);
                 } else if (P.out && has_out2) {
-                    bstore<S>(R_.out2, sxb + (unsigned)s * (12u / PK) * gb, (cp / PK) * gb + (cp % PK) * CB, dr[i], di[i]);
+                    bstore<S>(R_.out2, coff(s, cp), 0u, dr[i], di[i]);
                 }
             }
         }
