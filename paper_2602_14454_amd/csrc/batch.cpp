@@ -180,7 +180,7 @@ struct NormalHops {
     bool stage_loc[4] = {false, false, false, false};   // stage carries a local term
 
     // fields: in/out buffers of storage `kind`; partial/pstride/done for the |q|^2 reduction
-    void build(const std::vector<Item>& items, int kind_, int nrb_, int order_, void* p, void* t, void* v, void* w,
+    void build(const std::vector<Item>& items, int kind_, int nrb_, int order_, void* p, void* t, void* v, void* r,
                double* partial, long pstride, const double* scal) {
         kind = kind_;
         nrb = nrb_;
@@ -222,8 +222,12 @@ struct NormalHops {
                 s2.chain2 = DWF_CHAIN2;   // v = g5 Minv^T q from q itself
                 HopParams s3 = hop_params(op, kind, 1, at(v), nullptr, at(t), -1, MAT_QT, -1, 0.0, nullptr, 0, 0,
                                           nullptr, 0);
-                HopParams s4 = hop_params(op, kind, 0, at(t), at(v), at(w), -1, MAT_MQG5KT, MAT_G5MT, 0.0, nullptr, 0,
-                                          0, nullptr, 0);
+                // stage 4 applies r -= alpha D^dag D^ p per slot and reduces |r|^2
+                HopParams s4 = hop_params(op, kind, 0, at(t), at(v), nullptr, -1, MAT_MQG5KT, MAT_G5MT, 0.0, nullptr, 0,
+                                          0, part, 3);
+                s4.upd = static_cast<char*>(r) + (size_t)it.off * complex_bytes_of(kind == ST_F64 ? ST_F64 : ST_F32);
+                s4.upd_alpha = scal + (long)it.slot0 * CG_NSLOTS + CG_ALPHA;
+                s4.upd_stride = CG_NSLOTS;
                 for (HopParams* P : {&s1, &s2, &s3, &s4}) {
                     P->done = done;
                     P->done_stride = CG_NSLOTS;
@@ -314,7 +318,7 @@ void make_batch(Batch& B, int n, const dwf_op* const* ops, const int* nrhs) {
 
 struct Inner {
     int kx, kp;
-    DevBuf x, r, p, t, v, w;
+    DevBuf x, r, p, t, v;
     NormalHops hops;
     GraphExec graph;
     int graph_k = 0;
@@ -325,7 +329,6 @@ struct Inner {
         p.alloc(bp);
         t.alloc(bp);
         v.alloc(bp);
-        w.alloc(bp);
     }
 };
 
@@ -338,10 +341,9 @@ void iteration(const Batch& B, Inner& I, hipStream_t st) {
     I.hops.stage(1, st);
     bfinalize(pp, B.pstride, sd, B.nslots, sc, 1, 1, nullptr, st);
     I.hops.stage(2, st);
-    I.hops.stage(3, st);
-    bcg_xr(I.kx, I.kp, I.x.p, I.r.p, I.p.p, I.w.p, sd, B.nslots, B.vblocks, sc, pp, B.pstride, st);
-    bfinalize(pp, B.pstride, sd, B.nslots, sc, 2, 0, nullptr, st);
-    bcg_p(I.kx, I.kp, I.p.p, I.r.p, sd, B.nslots, B.vblocks, sc, st);
+    I.hops.stage(3, st);   // r -= alpha D^dag D^ p, |r|^2 partials per hop tile
+    bfinalize(pp, B.pstride, sd, B.nslots, sc, 2, 1, nullptr, st);
+    bcg_px(I.kx, I.kp, I.x.p, I.p.p, I.r.p, sd, B.nslots, B.vblocks, sc, st);
 }
 
 void capture(const Batch& B, Inner& I, int k, hipStream_t cs) {
@@ -362,7 +364,7 @@ void capture(const Batch& B, Inner& I, int k, hipStream_t cs) {
 
 // times the four hops of D^dag D^ for one (nrb, order)
 double time_hops(const Batch& B, Inner& I, int nrb, int order, hipStream_t st) {
-    I.hops.build(B.items, I.kp, nrb, order, I.p.p, I.t.p, I.v.p, I.w.p, B.partial.as<double>(), B.pstride,
+    I.hops.build(B.items, I.kp, nrb, order, I.p.p, I.t.p, I.v.p, I.r.p, B.partial.as<double>(), B.pstride,
                  B.scal.as<double>());
     Event e0, e1;
     for (int s = 0; s < 4; ++s) I.hops.stage(s, st);
@@ -466,7 +468,7 @@ int solve_batch(int n, const dwf_op* const* ops, void* const* x5, const void* co
     double tms = 0;
     const int autotune = prm->autotune;
     choose_tiles(B, *I, autotune, cs.s, &nrb, &order, &tms);
-    I->hops.build(B.items, kp, nrb, order, I->p.p, I->t.p, I->v.p, I->w.p, B.partial.as<double>(), B.pstride,
+    I->hops.build(B.items, kp, nrb, order, I->p.p, I->t.p, I->v.p, I->r.p, B.partial.as<double>(), B.pstride,
                   B.scal.as<double>());
 
     const SlotDesc* sd = B.slots_dev.as<SlotDesc>();
@@ -596,7 +598,7 @@ int solve_batch(int n, const dwf_op* const* ops, void* const* x5, const void* co
             // step the inner storage up one precision for the rest of the batch
             const int nk = I->kp == ST_BF16 ? ST_F32 : ST_F64;
             I.reset(new Inner(B, nk == ST_F64 ? ST_F64 : ST_F32, nk));
-            I->hops.build(B.items, nk, nrb, order, I->p.p, I->t.p, I->v.p, I->w.p, pp, B.pstride, sc);
+            I->hops.build(B.items, nk, nrb, order, I->p.p, I->t.p, I->v.p, I->r.p, pp, B.pstride, sc);
             fallback = 1;
         }
     }

@@ -37,7 +37,8 @@ struct HopParams {
     // upd holds the compute type (FP64 for FP64 launches, FP32 otherwise) in
     // that type's own field layout.
     void* upd;
-    const double* upd_alpha;
+    const double* upd_alpha;   // alpha of right-hand side r at upd_alpha[r * upd_stride]
+    long upd_stride;
     // work-list (batch) launches only
     const double* done;    // per-RHS done flags, done[r * done_stride] != 0: skip (nullptr: none)
     long done_stride;

@@ -541,7 +541,7 @@ __device__ __forceinline__ void hop_tile(const HopParams& P, long tile, int rhs,
     // FP32/BF16: the primary output (out, else out2) goes through LDS; a
     // second output, if any, is stored directly
     const bool upd = P.upd != nullptr;
-    const R ua = upd ? R(*P.upd_alpha) : R(0);
+    const R ua = upd ? R(P.upd_alpha[(long)rhs * P.upd_stride]) : R(0);
     const bool tile_out = L::TIO && (P.out != nullptr || has_out2 || upd);
     // byte offset of component cp of slice s of this lane's site; the whole
     // offset goes to the vector operand (cp depends on the wave index, which
@@ -814,6 +814,30 @@ void hop_batch_kernel(const HopParams* __restrict__ items, const int* __restrict
     }
 }
 
+// The same work list with one right-hand side per block (nrb = 1): no loop
+// around the tile, so nothing is live across right-hand sides.
+template <class S, int KK>
+__global__ __launch_bounds__(256)
+__attribute__((amdgpu_waves_per_eu(sizeof(S) == 8 ? DWF_HOP_WAVES_PER_EU64 : DWF_HOP_WAVES_PER_EU)))
+void hop_batch1_kernel(const HopParams* __restrict__ items, const int* __restrict__ meta, int nitems, int order) {
+    extern __shared__ u32x4 hop_smem[];
+    const int b = xcd_block(blockIdx.x, gridDim.x);
+    int i = 0;
+    while (i + 1 < nitems && b >= meta[i + 1]) ++i;
+    const HopParams P = items[i];
+    const int nrhs = meta[nitems + 1 + i];
+    const long tiles = (P.Vh + 15) / 16;
+    const long local = b - meta[i];
+    const long tile = order == 0 ? local % tiles : local / nrhs;
+    const int r = order == 0 ? (int)(local / tiles) : (int)(local % nrhs);
+    double* part = P.partial ? P.partial + (long)r * P.pstride + tile : nullptr;
+    if (P.done && P.done[(long)r * P.done_stride] != 0.0) {
+        if (part && threadIdx.x == 0) *part = 0.0;
+        return;
+    }
+    hop_tile<S, KK>(P, tile, r, part, reinterpret_cast<unsigned char*>(hop_smem));
+}
+
 // ---------------------------------------------------------------------
 // Local dense s-mix on one half field: out = A . in (per chirality),
 // same lane layout and MFMA use as the hop epilogue.  Optional reduction.
@@ -909,6 +933,17 @@ static void launch_hop_batch_t(int KK, const HopParams* items, const int* meta, 
                                int order, bool loc, hipStream_t st) {
     dim3 grid(blocks), block(64 * hop_waves(KK, sizeof(S) == 8));
     const unsigned smem_b = hop_smem_bytes<S>(KK, loc);
+    if (nrb == 1) {
+        switch (KK) {
+            case 1: hipLaunchKernelGGL((hop_batch1_kernel<S, 1>), grid, block, smem_b, st, items, meta, nitems, order); break;
+            case 2: hipLaunchKernelGGL((hop_batch1_kernel<S, 2>), grid, block, smem_b, st, items, meta, nitems, order); break;
+            case 3: hipLaunchKernelGGL((hop_batch1_kernel<S, 3>), grid, block, smem_b, st, items, meta, nitems, order); break;
+            case 4: hipLaunchKernelGGL((hop_batch1_kernel<S, 4>), grid, block, smem_b, st, items, meta, nitems, order); break;
+            default: throw Error{DWF_EDIMS, "Ls > 16 not supported by the fused hop"};
+        }
+        DWF_HIP(hipGetLastError());
+        return;
+    }
     switch (KK) {
         case 1: hipLaunchKernelGGL((hop_batch_kernel<S, 1>), grid, block, smem_b, st, items, meta, nitems, nrb, order); break;
         case 2: hipLaunchKernelGGL((hop_batch_kernel<S, 2>), grid, block, smem_b, st, items, meta, nitems, nrb, order); break;

@@ -14,7 +14,10 @@
 namespace dwf {
 
 // extra per-slot CG scalars (after the ones in blas.h)
-enum { CG_DONE = 9, CG_STOP = 10, CG_ITERS = 11 };
+// CG_XPEND: the slot converged in this iteration and its x update is still
+// due (the fused step updates x together with p, after the finalize that
+// sets CG_DONE)
+enum { CG_DONE = 9, CG_STOP = 10, CG_ITERS = 11, CG_XPEND = 12 };
 
 struct SlotDesc {
     long off;     // complex-element offset of the slot in every batch vector
@@ -38,13 +41,17 @@ void bcg_xr(int kx, int kp, void* x, void* r, const void* p, const void* w, cons
 // p_v = r_v + beta_v p_v
 void bcg_p(int kx, int kp, void* p, const void* r, const SlotDesc* slots, int nslots, int blocks,
            const double* scal, hipStream_t st);
+// x_v += alpha_v p_v (slots not done, or done with CG_XPEND set); then
+// p_v = r_v + beta_v p_v (slots not done)
+void bcg_px(int kx, int kp, void* x, void* p, const void* r, const SlotDesc* slots, int nslots, int blocks,
+            const double* scal, hipStream_t st);
 // Per-slot reduction of the partials (count: nhop if from_hop, else nb) and
 // CG scalar update, one block per slot:
-//  mode 0: RR = RR0 = sum; STOP = tol2[v] * sum; ITERS = 0;
+//  mode 0: RR = RR0 = sum; STOP = tol2[v] * sum; ITERS = 0; XPEND = 0;
 //          DONE = (sum == 0 || tol2[v] < 0); NANFLAG = !finite(sum)
-//  mode 1: QQ = sum; ALPHA = RR / QQ
+//  mode 1: QQ = sum; ALPHA = RR / QQ (done slots: XPEND = 0)
 //  mode 2: RRNEW = sum; BETA = sum / RR; RROLD = RR; RR = sum; ITERS += 1;
-//          DONE = (sum <= STOP); non-finite: NANFLAG = DONE = 1
+//          sum <= STOP: DONE = XPEND = 1; non-finite: NANFLAG = DONE = 1
 //  mode 4: TMP = sum (any slot, done or not)
 void bfinalize(const double* partial, long pstride, const SlotDesc* slots, int nslots, double* scal, int mode,
                int from_hop, const double* tol2, hipStream_t st);

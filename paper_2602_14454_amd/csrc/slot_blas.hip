@@ -139,6 +139,56 @@ __global__ __launch_bounds__(BT) void bcg_p_kernel(void* p, const void* r, const
     }
 }
 
+template <class SX, class SP>
+__global__ __launch_bounds__(BT) void bcg_px_kernel(void* x, void* p, const void* r,
+                                                    const SlotDesc* __restrict__ slots, int nslots,
+                                                    const double* scal) {
+    const int v = find_slot(slots, nslots, blockIdx.x);
+    const SlotDesc d = slots[v];
+    const int b = blockIdx.x - d.block0;
+    const double* sv = scal + (long)v * CG_NSLOTS;
+    const bool done = sv[CG_DONE] != 0.0;
+    if (done && sv[CG_XPEND] == 0.0) return;
+    using RX = typename Traits<SX>::R;
+    using RP = typename Traits<SP>::R;
+    const RX al = RX(sv[CG_ALPHA]);
+    const RP be = RP(sv[CG_BETA]);
+    if constexpr (fpack<SX>() == fpack<SP>()) {
+        for (long i = (long)b * BT + threadIdx.x; i < d.n; i += (long)d.nb * BT) {
+            const long k = d.off + i;
+            RX xr, xi, rr, ri;
+            RP pr, pi;
+            cload<SP>(p, k, pr, pi);
+            cload<SX>(x, k, xr, xi);
+            cstore<SX>(x, k, xr + al * RX(pr), xi + al * RX(pi));
+            if (!done) {
+                cload<SX>(r, k, rr, ri);
+                cstore<SP>(p, k, RP(rr) + be * pr, RP(ri) + be * pi);
+            }
+        }
+    } else {
+        char* xb = static_cast<char*>(x) + d.off * cbytes<SX>();
+        const char* rb = static_cast<const char*>(r) + d.off * cbytes<SX>();
+        char* pb = static_cast<char*>(p) + d.off * cbytes<SP>();
+        for (long t = (long)b * BT + threadIdx.x; t < d.n / 4; t += (long)d.nb * BT) {
+            const long g = t / d.Vhp, site = t - g * d.Vhp;
+            RX xv[8], rv[8];
+            RP pv[8];
+            load4<SP>(pb, g, site, d.Vhp, pv);
+            load4<SX>(xb, g, site, d.Vhp, xv);
+#pragma unroll
+            for (int q = 0; q < 8; ++q) xv[q] += al * RX(pv[q]);
+            store4<SX>(xb, g, site, d.Vhp, xv);
+            if (!done) {
+                load4<SX>(rb, g, site, d.Vhp, rv);
+#pragma unroll
+                for (int q = 0; q < 8; ++q) pv[q] = RP(rv[q]) + be * pv[q];
+                store4<SP>(pb, g, site, d.Vhp, pv);
+            }
+        }
+    }
+}
+
 __global__ __launch_bounds__(BT) void bfinalize_kernel(const double* partial, long pstride,
                                                        const SlotDesc* __restrict__ slots, double* scal, int mode,
                                                        int from_hop, const double* tol2) {
@@ -146,7 +196,10 @@ __global__ __launch_bounds__(BT) void bfinalize_kernel(const double* partial, lo
     const int v = blockIdx.x;
     const SlotDesc d = slots[v];
     double* sv = scal + (long)v * CG_NSLOTS;
-    if ((mode == 1 || mode == 2) && sv[CG_DONE] != 0.0) return;
+    if ((mode == 1 || mode == 2) && sv[CG_DONE] != 0.0) {
+        if (mode == 1 && threadIdx.x == 0) sv[CG_XPEND] = 0.0;   // its last x update is done
+        return;
+    }
     const int np = from_hop ? d.nhop : d.nb;
     const double* pp = partial + (long)v * pstride;
     double acc = 0.0;
@@ -166,6 +219,7 @@ __global__ __launch_bounds__(BT) void bfinalize_kernel(const double* partial, lo
         const double t2 = tol2 ? tol2[v] : 0.0;
         sv[CG_STOP] = t2 * sum;
         sv[CG_ITERS] = 0.0;
+        sv[CG_XPEND] = 0.0;
         sv[CG_NANFLAG] = fin ? 0.0 : 1.0;
         sv[CG_DONE] = (!fin || sum == 0.0 || t2 < 0.0) ? 1.0 : 0.0;
     } else if (mode == 1) {
@@ -179,7 +233,7 @@ __global__ __launch_bounds__(BT) void bfinalize_kernel(const double* partial, lo
         sv[CG_RR] = sum;
         sv[CG_ITERS] += 1.0;
         if (!fin) { sv[CG_NANFLAG] = 1.0; sv[CG_DONE] = 1.0; }
-        else if (sum <= sv[CG_STOP]) sv[CG_DONE] = 1.0;
+        else if (sum <= sv[CG_STOP]) { sv[CG_DONE] = 1.0; sv[CG_XPEND] = 1.0; }
     } else {
         sv[CG_TMP] = sum;
         if (!fin) sv[CG_NANFLAG] = 1.0;
@@ -252,6 +306,27 @@ static void bcg_p_t1(int kp, void* p, const void* r, const SlotDesc* slots, int 
 void bcg_p(int kx, int kp, void* p, const void* r, const SlotDesc* slots, int nslots, int blocks,
            const double* scal, hipStream_t st) {
     BDISPATCH1(kx, bcg_p_t1, kp, p, r, slots, nslots, blocks, scal, st);
+    DWF_HIP(hipGetLastError());
+}
+
+template <class SX, class SP>
+static void bcg_px_t2(void* x, void* p, const void* r, const SlotDesc* slots, int nslots, int blocks,
+                      const double* scal, hipStream_t st) {
+    hipLaunchKernelGGL((bcg_px_kernel<SX, SP>), dim3(blocks), dim3(BT), 0, st, x, p, r, slots, nslots, scal);
+}
+template <class SX>
+static void bcg_px_t1(int kp, void* x, void* p, const void* r, const SlotDesc* slots, int nslots, int blocks,
+                      const double* scal, hipStream_t st) {
+    switch (kp) {
+        case ST_F64: bcg_px_t2<SX, double>(x, p, r, slots, nslots, blocks, scal, st); break;
+        case ST_F32: bcg_px_t2<SX, float>(x, p, r, slots, nslots, blocks, scal, st); break;
+        case ST_BF16: bcg_px_t2<SX, bf16s>(x, p, r, slots, nslots, blocks, scal, st); break;
+        default: throw Error{DWF_EINVAL, "bad storage kind"};
+    }
+}
+void bcg_px(int kx, int kp, void* x, void* p, const void* r, const SlotDesc* slots, int nslots, int blocks,
+            const double* scal, hipStream_t st) {
+    BDISPATCH1(kx, bcg_px_t1, kp, x, p, r, slots, nslots, blocks, scal, st);
     DWF_HIP(hipGetLastError());
 }
 
