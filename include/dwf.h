@@ -146,7 +146,12 @@ int dwf_source_4d(const dwf_op* op, void* b5, const void* b4, void* stream);
 int dwf_project_4d(const dwf_op* op, void* x4, const void* x5, void* stream);
 
 /* Solves D^(alpha) x5 = b5 through the even-odd Schur system (x5, b5 5D
- * canonical).  info may be NULL.  Returns DWF_OK or DWF_NOT_CONVERGED. */
+ * canonical).  info may be NULL.  Returns DWF_OK or DWF_NOT_CONVERGED.
+ * The operator keeps its solve workspace (nine FP64 half-lattice vectors
+ * plus the inner-precision CG vectors) from the first solve until
+ * dwf_op_destroy, so later solves allocate nothing; solves on one operator
+ * from several threads run one at a time.  A solve that returns an error
+ * drops the workspace. */
 int dwf_solve(const dwf_op* op, void* x5, const void* b5, const dwf_solve_params* prm,
               dwf_solve_info* info, void* stream);
 

@@ -22,6 +22,8 @@
 #include <hip/hip_bf16.h>
 
 #include <cstdint>
+#include <memory>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -138,6 +140,10 @@ struct dwf_op {
     dwf::DevBuf mats[2];   // compute kind 0: double, 1: float; NMAT * MAT_ELEMS
     dwf::DevBuf pres[2];   // NPRE * PRE_ELEMS
     std::vector<double> mats_host;   // NMAT * MAT_ELEMS, FP64
+    // solve workspace kept between solves on this operator (solver.cpp owns
+    // the type); solves on one operator run one at a time
+    mutable std::shared_ptr<void> solve_ws;
+    mutable std::mutex solve_mu;
     const void* mat(int store_kind, int slot) const {
         const int ck = store_kind == dwf::ST_F64 ? 0 : 1;
         const size_t esz = ck == 0 ? 8 : 4;

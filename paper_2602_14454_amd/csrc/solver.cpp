@@ -22,24 +22,21 @@
 
 namespace dwf {
 
-struct Pinned {
-    double* h = nullptr;
-    explicit Pinned(size_t n) {
-        if (hipHostMalloc(reinterpret_cast<void**>(&h), n * sizeof(double), hipHostMallocDefault) != hipSuccess)
-            throw Error{DWF_ENOMEM, "hipHostMalloc failed"};
-        std::memset(h, 0, n * sizeof(double));
-    }
-    ~Pinned() {
-        if (h) (void)hipHostFree(h);
-    }
-};
+Pinned::Pinned(size_t n) {
+    if (hipHostMalloc(reinterpret_cast<void**>(&h), n * sizeof(double), hipHostMallocDefault) != hipSuccess)
+        throw Error{DWF_ENOMEM, "hipHostMalloc failed"};
+    std::memset(h, 0, n * sizeof(double));
+}
+Pinned::~Pinned() {
+    if (h) (void)hipHostFree(h);
+}
 
 static void read_scalars(const double* dev, Pinned& host, hipStream_t st) {
     DWF_HIP(hipMemcpyAsync(host.h, dev, CG_NSLOTS * sizeof(double), hipMemcpyDeviceToHost, st));
     DWF_HIP(hipStreamSynchronize(st));
 }
 
-CgWork::CgWork(const dwf_op* op, int kx_, int kp_, int nrhs_) : kx(kx_), kp(kp_), nrhs(nrhs_) {
+CgWork::CgWork(const dwf_op* op, int kx_, int kp_, int nrhs_) : kx(kx_), kp(kp_), nrhs(nrhs_), hs(CG_NSLOTS) {
     n = (long)op->Ls * 12 * op->lat->Vhp * nrhs;
     const size_t bx = complex_bytes_of(kx) * n, bp = complex_bytes_of(kp) * n;
     x.alloc(bx);
@@ -58,7 +55,7 @@ int cgnr(const dwf_op* op, CgWork& W, const void* b_kp, double tol_rel, int maxi
     const long n = W.n;
     double* partial = W.partial.as<double>();
     double* scal = W.scal.as<double>();
-    Pinned hs(CG_NSLOTS);
+    Pinned& hs = W.hs;
     if (check_every < 1) check_every = 1;
     DWF_HIP(hipMemsetAsync(W.scal.p, 0, CG_NSLOTS * sizeof(double), st));
     // r = D^dag b, p = r, x = 0
@@ -216,6 +213,48 @@ double dc_ratio(double achieved, double requested) {
     return std::min(1e4, std::max(1e-2, achieved / requested));
 }
 
+namespace {
+// Workspace of dwf_solve, kept by the operator between solves: allocation and
+// release of ~10 full-size vectors per solve cost milliseconds of host time.
+// Every buffer keeps one role and layout, so its zero padding (never written
+// by a kernel) stays valid; a solve that ends in an error drops the workspace.
+struct SolveWs {
+    long n = 0;
+    DevBuf be, bo, bt, xe, xo, rh, te, to, rin, partial, scal;
+    Pinned hs{CG_NSLOTS};
+    std::unique_ptr<CgWork> cg[3];   // by inner storage kind
+};
+
+SolveWs& solve_ws(const dwf_op* op, long n) {
+    auto ws = std::static_pointer_cast<SolveWs>(op->solve_ws);
+    if (!ws || ws->n != n) {
+        op->solve_ws.reset();   // release the old workspace first
+        ws = std::make_shared<SolveWs>();
+        const size_t b64 = 16 * (size_t)n;
+        for (DevBuf* b : {&ws->be, &ws->bo, &ws->bt, &ws->xe, &ws->xo, &ws->rh, &ws->te, &ws->to, &ws->rin})
+            b->alloc(b64);
+        ws->partial.alloc((std::max<long>(hop_partials(op, 1), blas_grid(n)) * 2 + 16) * sizeof(double));
+        ws->scal.alloc(CG_NSLOTS * sizeof(double));
+        ws->n = n;
+        op->solve_ws = ws;
+    }
+    return *ws;
+}
+
+CgWork& solve_cg(SolveWs& ws, const dwf_op* op, int kp) {
+    if (!ws.cg[kp]) ws.cg[kp].reset(new CgWork(op, kp == ST_F64 ? ST_F64 : ST_F32, kp, 1));
+    return *ws.cg[kp];
+}
+
+struct DropOnError {
+    const dwf_op* op;
+    bool ok = false;
+    ~DropOnError() {
+        if (!ok) op->solve_ws.reset();
+    }
+};
+}  // namespace
+
 int solve(const dwf_op* op, void* x5, const void* b5, const dwf_solve_params* prm, dwf_solve_info* info,
           hipStream_t st) {
     const dwf_lattice* L = op->lat;
@@ -224,20 +263,23 @@ int solve(const dwf_op* op, void* x5, const void* b5, const dwf_solve_params* pr
     const int Ls = op->Ls;
     const long n = (long)Ls * 12 * Vhp;
     const size_t b64 = 16 * n;
-    DevBuf be(b64), bo(b64), bt(b64), xe(b64), xo(b64), rh(b64), te(b64), to(b64);
-    DevBuf partial((std::max<long>(hop_partials(op, 1), blas_grid(n)) * 2 + 16) * sizeof(double));
-    DevBuf scal(CG_NSLOTS * sizeof(double));
-    Pinned hs(CG_NSLOTS);
-    double* pp = partial.as<double>();
-    double* sc = scal.as<double>();
 
     int kp = ST_F64;
     if (prm->algo == DWF_ALGO_DC || prm->algo == DWF_ALGO_MIXED || prm->paper_mode) kp = prm->inner_prec;
     if (prm->algo == DWF_ALGO_FGCR_LEARNED) kp = ST_F32;   // FGCR and the network run in FP32
     DWF_REQUIRE(kp == ST_F64 || kp == ST_F32 || kp == ST_BF16, DWF_EINVAL, "bad inner precision");
-    // all workspace is allocated before the timed region starts
-    std::unique_ptr<CgWork> W(new CgWork(op, kp == ST_F64 ? ST_F64 : ST_F32, kp, 1));
-    DevBuf rin(16 * n);
+
+    // all workspace exists before the timed region starts
+    std::lock_guard<std::mutex> lock(op->solve_mu);
+    DropOnError guard{op};
+    SolveWs& ws = solve_ws(op, n);
+    DevBuf &be = ws.be, &bo = ws.bo, &bt = ws.bt, &xe = ws.xe, &xo = ws.xo, &rh = ws.rh, &te = ws.te, &to = ws.to;
+    DevBuf& rin = ws.rin;
+    Pinned& hs = ws.hs;
+    double* pp = ws.partial.as<double>();
+    double* sc = ws.scal.as<double>();
+    DevBuf& scal = ws.scal;
+    CgWork* W = &solve_cg(ws, op, kp);
 
     hipEvent_t e0, e1;
     DWF_HIP(hipEventCreate(&e0));
@@ -285,7 +327,7 @@ int solve(const dwf_op* op, void* x5, const void* b5, const dwf_solve_params* pr
     if (use_fgcr) FW.reset(new FgcrWork(op, prm->restart > 0 ? prm->restart : 16));
     while (prm->algo != DWF_ALGO_MIXED && !converged && total < maxiter && outer < 100) {
         const int kx = kp == ST_F64 ? ST_F64 : ST_F32;
-        if (W->kp != kp) W.reset(new CgWork(op, kx, kp, 1));
+        if (W->kp != kp) W = &solve_cg(ws, op, kp);
         convert(kp, ST_F64, rin.p, rh.p, n, st, Vhp);
         // FP64: the first step is the textbook CGNR stop; restarts are calibrated
         const bool plain = prm->paper_mode || (kp == ST_F64 && outer == 0);
@@ -361,6 +403,7 @@ int solve(const dwf_op* op, void* x5, const void* b5, const dwf_solve_params* pr
         info->final_rel_res_even = last_inner_rel;
     }
     if (nan_seen) throw Error{DWF_ENAN, "NaN/Inf in a CG reduction"};
+    guard.ok = true;
     if (prm->paper_mode) return DWF_OK;
     return (converged || true_res <= tol) ? DWF_OK : DWF_NOT_CONVERGED;
 }

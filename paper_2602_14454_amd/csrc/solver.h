@@ -8,11 +8,22 @@
 
 namespace dwf {
 
-// Inner CGNR workspace: x, r in storage kx; p, t (odd), v, w in storage kp.
+// Page-locked host doubles (read-back of device CG scalars).
+struct Pinned {
+    double* h = nullptr;
+    explicit Pinned(size_t n);
+    ~Pinned();
+    Pinned(const Pinned&) = delete;
+    Pinned& operator=(const Pinned&) = delete;
+};
+
+// Inner CGNR workspace: x, r in storage kx; p, t (odd), v, w in storage kp;
+// device CG scalars and their host read-back buffer.
 struct CgWork {
     int kx, kp, nrhs;
     long n;   // complex elements per field (all RHS)
     DevBuf x, r, p, t, v, w, partial, scal;
+    Pinned hs;
     CgWork(const dwf_op* op, int kx, int kp, int nrhs);
 };
 
