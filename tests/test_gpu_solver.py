@@ -160,3 +160,34 @@ def test_mixed_reliable_update_cg(inner):
     st, info64 = op.solve(x5d, b5, dwf.default_params(tol=1e-10))
     assert info.iters <= (1.35 if inner == "f32" else 2.0) * info64.iters
     assert (x5 - x5d).abs().max().item() / x5d.abs().max().item() < 1e-7
+
+
+def test_workspace_reuse_across_solves_and_after_an_error():
+    """The operator keeps its solve workspace: a NaN solve (error, workspace
+    dropped), then solves with alternating inner precisions on the same
+    operator all meet the oracle's true residual, and a repeated solve is
+    bit-identical to the first one."""
+    import torch
+    import paper_2602_14454_amd as dwf
+    dims = (4, 4, 4, 8)
+    Ls = 8
+    lat, op, p, U = _setup(dims, Ls, 1.6, 0.05, 1.0, 0.0, 0.5, eps=0.5, seed=21)
+    b5 = dwfgen.gaussian_source_5d(dims, Ls, 22)
+    bad = b5.copy()
+    bad[2, 5, 1, 2] = np.nan
+    x5 = torch.zeros((Ls, p.V, 4, 3), dtype=torch.complex128, device="cuda")
+    with pytest.raises(dwf.DwfError):
+        op.solve(x5, _dev(bad), dwf.default_params(algo=dwf.ALGO_DC, inner_prec=dwf.F32))
+    first = None
+    for algo, prec in ((dwf.ALGO_DC, dwf.BF16), (dwf.ALGO_CGNR, dwf.F64), (dwf.ALGO_DC, dwf.F32),
+                       (dwf.ALGO_DC, dwf.BF16)):
+        x5 = torch.zeros((Ls, p.V, 4, 3), dtype=torch.complex128, device="cuda")
+        st, info = op.solve(x5, _dev(b5), dwf.default_params(tol=1e-10, algo=algo, inner_prec=prec))
+        assert st == 0 and info.converged
+        xg = x5.cpu().numpy()
+        assert oracle.true_residual(p, U, xg, b5) <= 1.2e-10
+        if prec == dwf.BF16:
+            if first is None:
+                first = xg
+            else:
+                assert np.array_equal(first, xg)
