@@ -794,7 +794,7 @@ void hop_batch_kernel(const HopParams* __restrict__ items, const int* __restrict
     const int b = xcd_block(blockIdx.x, gridDim.x);
     int i = 0;
     while (i + 1 < nitems && b >= meta[i + 1]) ++i;
-    const HopParams P = items[i];
+    const HopParams& P = items[i];   // read in place (wave-uniform address: scalar loads)
     const int nrhs = meta[nitems + 1 + i];
     const long tiles = (P.Vh + 15) / 16;
     const int chunks = (nrhs + nrb - 1) / nrb;
@@ -816,20 +816,30 @@ void hop_batch_kernel(const HopParams* __restrict__ items, const int* __restrict
 
 // The same work list with one right-hand side per block (nrb = 1): no loop
 // around the tile, so nothing is live across right-hand sides.
+#ifndef DWF_HOP_BATCH1_WPE
+#define DWF_HOP_BATCH1_WPE 5
+#endif
 template <class S, int KK>
 __global__ __launch_bounds__(256)
-__attribute__((amdgpu_waves_per_eu(sizeof(S) == 8 ? DWF_HOP_WAVES_PER_EU64 : DWF_HOP_WAVES_PER_EU)))
+__attribute__((amdgpu_waves_per_eu(sizeof(S) == 8 ? DWF_HOP_WAVES_PER_EU64 : DWF_HOP_BATCH1_WPE)))
 void hop_batch1_kernel(const HopParams* __restrict__ items, const int* __restrict__ meta, int nitems, int order) {
     extern __shared__ u32x4 hop_smem[];
     const int b = xcd_block(blockIdx.x, gridDim.x);
     int i = 0;
     while (i + 1 < nitems && b >= meta[i + 1]) ++i;
-    const HopParams P = items[i];
+    const HopParams& P = items[i];   // read in place (wave-uniform address: scalar loads)
     const int nrhs = meta[nitems + 1 + i];
-    const long tiles = (P.Vh + 15) / 16;
-    const long local = b - meta[i];
-    const long tile = order == 0 ? local % tiles : local / nrhs;
-    const int r = order == 0 ? (int)(local / tiles) : (int)(local % nrhs);
+    const int tiles = (int)((P.Vh + 15) / 16);
+    int tile = b - meta[i], r = 0;
+    if (order == 0) {
+        // tiles fastest: a uniform subtraction loop (nrhs steps at most)
+        // keeps tile and r in scalar registers, where a division would be
+        // expanded on the vector unit
+        while (tile >= tiles) { tile -= tiles; ++r; }
+    } else {
+        r = tile % nrhs;
+        tile /= nrhs;
+    }
     double* part = P.partial ? P.partial + (long)r * P.pstride + tile : nullptr;
     if (P.done && P.done[(long)r * P.done_stride] != 0.0) {
         if (part && threadIdx.x == 0) *part = 0.0;

@@ -21,19 +21,23 @@ static uint16_t host_f32_to_bf16(float f) {
 
 // Internal site order: the spatial volume is cut into bricks and every
 // brick is swept in t (brick index slowest, then t, z, y, x).  With bricks of
-// the whole spatial volume (the default) this is the lexicographic order.
-// Smaller bricks shorten the reuse distance of t neighbours (a t slice of
-// 24^3 sites is ~10 MB of FP32 input at Ls = 16, beyond an XCD's 4 MB L2).
-// Measured on MI355X: bricks of <= 4096 sites per slice gain 7-8 % on the
-// 24^3x48 hop (FP32, FP64) and are neutral on 16^3x32.
-#ifndef DWF_BRICK_SITES
-#define DWF_BRICK_SITES 4096L
-#endif
+// the whole spatial volume this is the lexicographic order.  Smaller bricks
+// keep the t neighbours of the sites a GPU die has in flight inside its L2
+// (a t slice of 24^3 sites is ~10 MB of FP32 input at Ls = 16, beyond an
+// XCD's 4 MB L2) at the cost of re-reading brick faces.  Measured on MI355X
+// (fused hop, Ls = 16): on 16^3x32 bricks of 1024 sites per slice beat whole
+// slices (FP64 193 -> 185 us, FP32 84 -> 78 us); on 24^3x48 bricks of 4096
+// sites are best (FP32 479 us vs 519 us at 2048 and 546 us at 1024).  Default:
+// 1024 up to 16^3 spatial sites, 4096 above; DWF_BRICK_SITES overrides.
 static void choose_brick(const int dims[4], int b[3]) {
     b[0] = dims[0];
     b[1] = dims[1];
     b[2] = dims[2];
+#ifdef DWF_BRICK_SITES
     const long fmax = DWF_BRICK_SITES;   // sites (both parities) per brick slice
+#else
+    const long fmax = (long)dims[0] * dims[1] * dims[2] <= 4096 ? 1024L : 4096L;
+#endif
     while ((long)b[0] * b[1] * b[2] > fmax) {
         int best = -1;
         for (int mu = 2; mu >= 0; --mu)   // prefer z, then y, then x on ties
