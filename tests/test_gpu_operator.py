@@ -56,7 +56,10 @@ def test_geometry_bit_exact():
     """Device site tables: a parity-preserving bijection onto the lattice, and
     neighbour tables equal to the oracle's, bit for bit."""
     import paper_2602_14454_amd as dwf
-    for dims in [(6, 6, 4, 4), (4, 2, 2, 6), (2, 2, 2, 2), (8, 4, 6, 2), (16, 16, 8, 4), (24, 12, 12, 2)]:
+    # (16,16,8,4) and (24,12,12,2) are cut into bricks of 1024 sites per t
+    # slice, (20,20,12,2) (spatial volume above 16^3) into bricks of <= 4096
+    for dims in [(6, 6, 4, 4), (4, 2, 2, 6), (2, 2, 2, 2), (8, 4, 6, 2), (16, 16, 8, 4), (24, 12, 12, 2),
+                 (20, 20, 12, 2)]:
         lat = dwf.Lattice(dims)
         lex, nbr = lat.maps()
         par, eo, le, lo = oracle.site_maps(dims)
