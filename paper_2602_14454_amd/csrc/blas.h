@@ -35,6 +35,13 @@ void axpby(int ky, int kx, void* y, const void* x, long n, const double* sa, dou
 void cg_update_xr(int kx, int kp, void* x, void* r, const void* p, const void* w, long n, const double* alpha,
                   double* partial, hipStream_t st, long Vhp = 0);
 void cg_update_p(int kr, int kp, void* p, const void* r, long n, const double* beta, hipStream_t st, long Vhp = 0);
+// p_dst = r + beta p_src (r of kind kr; p_src, p_dst of kind kp, distinct buffers)
+void cg_update_p2(int kr, int kp, void* p_dst, const void* p_src, const void* r, long n, const double* beta,
+                  hipStream_t st, long Vhp = 0);
+// x += sum_{i < cnt} alpha[i] p_i, p_i = p_ring + i * n elements of kind kp, added in order i = 0, 1, ...
+// with x (kind kx) rounded after each term, as cnt successive x += alpha p updates
+void cg_accumulate_x(int kx, int kp, void* x, const void* p_ring, const double* alpha, int cnt, long n,
+                     hipStream_t st, long Vhp = 0);
 // x += alpha p; p = r + beta p (x, r of kind kx; p of kind kp)
 void cg_update_px(int kx, int kp, void* x, void* p, const void* r, long n, const double* alpha, const double* beta,
                   hipStream_t st, long Vhp = 0);
@@ -44,6 +51,7 @@ void caxpy(int kind, void* y, const void* x, long n, double ar, double ai, hipSt
 void random_fill_f64(void* v, long rows, long Vh, long Vhp, unsigned long long seed, hipStream_t st);
 // mode 0: out[0] = sum; 1: alpha step; 2: beta step; 3: beta after a residual
 // replacement (RR = sum, BETA = sum / RROLD) (see CG slots)
-void finalize(const double* partial, int nparts, int stride, double* out, int mode, hipStream_t st);
+void finalize(const double* partial, int nparts, int stride, double* out, int mode, hipStream_t st,
+              double* alpha_copy = nullptr);
 
 }  // namespace dwf

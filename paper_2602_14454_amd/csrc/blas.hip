@@ -227,6 +227,73 @@ __global__ void cg_p_remap_kernel(void* p, const void* r, long nquads, long Vhp,
     }
 }
 
+// p_dst = r + beta p_src
+template <class SR, class SP>
+__global__ void cg_p2_kernel(void* pd, const void* ps, const void* r, long n, const double* beta) {
+    using RP = typename Traits<SP>::R;
+    const RP b = RP(*beta);
+    for (long i = (long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (long)gridDim.x * blockDim.x) {
+        typename Traits<SR>::R rr, ri;
+        RP pr, pi;
+        cload<SR>(r, i, rr, ri);
+        cload<SP>(ps, i, pr, pi);
+        cstore<SP>(pd, i, RP(rr) + b * pr, RP(ri) + b * pi);
+    }
+}
+template <class SR, class SP>
+__global__ void cg_p2_remap_kernel(void* pd, const void* ps, const void* r, long nquads, long Vhp,
+                                   const double* beta) {
+    using RP = typename Traits<SP>::R;
+    const RP b = RP(*beta);
+    for (long t = (long)blockIdx.x * blockDim.x + threadIdx.x; t < nquads; t += (long)gridDim.x * blockDim.x) {
+        const long g = t / Vhp, site = t - g * Vhp;
+        typename Traits<SR>::R rv[8];
+        RP pv[8];
+        load4<SR>(r, g, site, Vhp, rv);
+        load4<SP>(ps, g, site, Vhp, pv);
+#pragma unroll
+        for (int k = 0; k < 8; ++k) pv[k] = RP(rv[k]) + b * pv[k];
+        store4<SP>(pd, g, site, Vhp, pv);
+    }
+}
+
+// x += sum_i alpha_i p_i in order, x rounded to its storage after every term
+// (x is FP32 or FP64, whose compute type is the storage type)
+template <class SX, class SP>
+__global__ void cg_accx_kernel(void* x, const void* ring, const double* alpha, int cnt, long n) {
+    using RX = typename Traits<SX>::R;
+    for (long i = (long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (long)gridDim.x * blockDim.x) {
+        RX xr, xi;
+        cload<SX>(x, i, xr, xi);
+        for (int q = 0; q < cnt; ++q) {
+            typename Traits<SP>::R pr, pi;
+            cload<SP>(static_cast<const char*>(ring) + (size_t)q * n * cbytes<SP>(), i, pr, pi);
+            const RX a = RX(alpha[q]);
+            xr = xr + a * RX(pr);   // x is FP32 or FP64: stored in its compute type
+            xi = xi + a * RX(pi);
+        }
+        cstore<SX>(x, i, xr, xi);
+    }
+}
+template <class SX, class SP>
+__global__ void cg_accx_remap_kernel(void* x, const void* ring, const double* alpha, int cnt, long n, long nquads,
+                                     long Vhp) {
+    using RX = typename Traits<SX>::R;
+    for (long t = (long)blockIdx.x * blockDim.x + threadIdx.x; t < nquads; t += (long)gridDim.x * blockDim.x) {
+        const long g = t / Vhp, site = t - g * Vhp;
+        RX xv[8];
+        load4<SX>(x, g, site, Vhp, xv);
+        for (int q = 0; q < cnt; ++q) {
+            typename Traits<SP>::R pv[8];
+            load4<SP>(static_cast<const char*>(ring) + (size_t)q * n * cbytes<SP>(), g, site, Vhp, pv);
+            const RX a = RX(alpha[q]);
+#pragma unroll
+            for (int k = 0; k < 8; ++k) xv[k] = xv[k] + a * RX(pv[k]);
+        }
+        store4<SX>(x, g, site, Vhp, xv);
+    }
+}
+
 // x += alpha p; p = r + beta p (the x update of a CG step deferred to the
 // kernel that reads p anyway), operands in different layouts
 template <class SX, class SP>
@@ -401,7 +468,9 @@ __global__ void cg_px_kernel(void* x, void* p, const void* r, long n, const doub
 //  mode 2 (beta):  s[RRNEW] = sum; s[BETA] = sum / s[RR]; s[RROLD] = s[RR]; s[RR] = sum
 //  mode 3 (beta after replacing r): s[RRNEW] = s[RR] = sum; s[BETA] = sum / s[RROLD]
 // In modes 1-3 a non-finite sum sets s[NANFLAG] = 1.
-__global__ void finalize_kernel(const double* partial, int nparts, int stride, double* out, int mode) {
+// alpha_copy (mode 1, or nullptr): also receives the new alpha.
+__global__ void finalize_kernel(const double* partial, int nparts, int stride, double* out, int mode,
+                                double* alpha_copy) {
     __shared__ double red[BLAS_THREADS];
     double acc = 0.0;
     for (int i = threadIdx.x; i < nparts; i += blockDim.x) acc += partial[(long)i * stride];
@@ -421,6 +490,7 @@ __global__ void finalize_kernel(const double* partial, int nparts, int stride, d
         } else if (mode == 1) {
             out[CG_QQ] = sum;
             out[CG_ALPHA] = (sum > 0.0 && isfinite(sum)) ? out[CG_RR] / sum : 0.0;
+            if (alpha_copy) *alpha_copy = out[CG_ALPHA];
         } else if (mode == 2) {
             out[CG_RRNEW] = sum;
             out[CG_BETA] = out[CG_RR] > 0.0 ? sum / out[CG_RR] : 0.0;
@@ -682,6 +752,60 @@ void cg_update_px(int kx, int kp, void* x, void* p, const void* r, long n, const
     DWF_HIP(hipGetLastError());
 }
 
+template <class SR, class SP>
+static void cg_p2_t2(void* pd, const void* ps, const void* r, long n, long Vhp, const double* beta, hipStream_t st) {
+    if (fpack<SR>() == fpack<SP>())
+        hipLaunchKernelGGL((cg_p2_kernel<SR, SP>), dim3(blas_grid(n)), dim3(BLAS_THREADS), 0, st, pd, ps, r, n, beta);
+    else
+        hipLaunchKernelGGL((cg_p2_remap_kernel<SR, SP>), dim3(blas_grid(n)), dim3(BLAS_THREADS), 0, st, pd, ps, r,
+                           n / 4, Vhp, beta);
+}
+template <class SR>
+static void cg_p2_t1(int kp, void* pd, const void* ps, const void* r, long n, long Vhp, const double* beta,
+                     hipStream_t st) {
+    switch (kp) {
+        case ST_F64: cg_p2_t2<SR, double>(pd, ps, r, n, Vhp, beta, st); break;
+        case ST_F32: cg_p2_t2<SR, float>(pd, ps, r, n, Vhp, beta, st); break;
+        case ST_BF16: cg_p2_t2<SR, bf16s>(pd, ps, r, n, Vhp, beta, st); break;
+        default: throw Error{DWF_EINVAL, "bad storage kind"};
+    }
+}
+void cg_update_p2(int kr, int kp, void* p_dst, const void* p_src, const void* r, long n, const double* beta,
+                  hipStream_t st, long Vhp) {
+    if (fpack_of(kr) != fpack_of(kp))
+        DWF_REQUIRE(Vhp > 0 && n % (4 * Vhp) == 0, DWF_EINVAL, "layout change needs the row stride");
+    DISPATCH1(kr, cg_p2_t1, kp, p_dst, p_src, r, n, Vhp, beta, st);
+    DWF_HIP(hipGetLastError());
+}
+
+template <class SX, class SP>
+static void cg_accx_t2(void* x, const void* ring, const double* alpha, int cnt, long n, long Vhp, hipStream_t st) {
+    if (fpack<SX>() == fpack<SP>())
+        hipLaunchKernelGGL((cg_accx_kernel<SX, SP>), dim3(blas_grid(n)), dim3(BLAS_THREADS), 0, st, x, ring, alpha,
+                           cnt, n);
+    else
+        hipLaunchKernelGGL((cg_accx_remap_kernel<SX, SP>), dim3(blas_grid(n)), dim3(BLAS_THREADS), 0, st, x, ring,
+                           alpha, cnt, n, n / 4, Vhp);
+}
+template <class SX>
+static void cg_accx_t1(int kp, void* x, const void* ring, const double* alpha, int cnt, long n, long Vhp,
+                       hipStream_t st) {
+    switch (kp) {
+        case ST_F64: cg_accx_t2<SX, double>(x, ring, alpha, cnt, n, Vhp, st); break;
+        case ST_F32: cg_accx_t2<SX, float>(x, ring, alpha, cnt, n, Vhp, st); break;
+        case ST_BF16: cg_accx_t2<SX, bf16s>(x, ring, alpha, cnt, n, Vhp, st); break;
+        default: throw Error{DWF_EINVAL, "bad storage kind"};
+    }
+}
+void cg_accumulate_x(int kx, int kp, void* x, const void* p_ring, const double* alpha, int cnt, long n,
+                     hipStream_t st, long Vhp) {
+    if (cnt <= 0) return;
+    if (fpack_of(kx) != fpack_of(kp))
+        DWF_REQUIRE(Vhp > 0 && n % (4 * Vhp) == 0, DWF_EINVAL, "layout change needs the row stride");
+    DISPATCH1(kx, cg_accx_t1, kp, x, p_ring, alpha, cnt, n, Vhp, st);
+    DWF_HIP(hipGetLastError());
+}
+
 template <class S>
 static void caxpy_t(void* y, const void* x, long n, double ar, double ai, hipStream_t st) {
     hipLaunchKernelGGL(caxpy_kernel<S>, dim3(blas_grid(n)), dim3(BLAS_THREADS), 0, st, y, x, n, ar, ai);
@@ -697,8 +821,10 @@ void random_fill_f64(void* v, long rows, long Vh, long Vhp, unsigned long long s
     DWF_HIP(hipGetLastError());
 }
 
-void finalize(const double* partial, int nparts, int stride, double* out, int mode, hipStream_t st) {
-    hipLaunchKernelGGL(finalize_kernel, dim3(1), dim3(BLAS_THREADS), 0, st, partial, nparts, stride, out, mode);
+void finalize(const double* partial, int nparts, int stride, double* out, int mode, hipStream_t st,
+              double* alpha_copy) {
+    hipLaunchKernelGGL(finalize_kernel, dim3(1), dim3(BLAS_THREADS), 0, st, partial, nparts, stride, out, mode,
+                       alpha_copy);
     DWF_HIP(hipGetLastError());
 }
 

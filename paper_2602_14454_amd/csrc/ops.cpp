@@ -115,7 +115,7 @@ void apply_normal(const dwf_op* op, int kind, void* out_e, const void* in_e, voi
 }
 
 void apply_normal_update_r(const dwf_op* op, int kind, void* r, const void* p, void* tmp_o, void* tmp_v,
-                           double* partial, double* scal, int nrhs, hipStream_t st) {
+                           double* partial, double* scal, int nrhs, hipStream_t st, double* alpha_copy) {
     hop(op, kind, 1, p, nullptr, tmp_o, PRE_K, MAT_Q, -1, 0.0, nullptr, 0, 0, nullptr, 0, nrhs, st);
     {
         HopParams P = hop_params(op, kind, 0, tmp_o, p, nullptr, -1, MAT_MQMINV, -1, 1.0, tmp_v,
@@ -123,7 +123,7 @@ void apply_normal_update_r(const dwf_op* op, int kind, void* r, const void* p, v
         P.chain2 = DWF_CHAIN2;
         launch_hop(kind, P, nrhs, st);
     }
-    finalize(partial, hop_partials(op, nrhs), 1, scal, 1, st);   // alpha
+    finalize(partial, hop_partials(op, nrhs), 1, scal, 1, st, alpha_copy);   // alpha
     hop(op, kind, 1, tmp_v, nullptr, tmp_o, -1, MAT_QT, -1, 0.0, nullptr, 0, 0, nullptr, 0, nrhs, st);
     HopParams P = hop_params(op, kind, 0, tmp_o, tmp_v, nullptr, -1, MAT_MQG5KT, MAT_G5MT, 0.0, nullptr, 0, 0,
                              partial, 3);

@@ -34,8 +34,9 @@ void apply_normal(const dwf_op* op, int kind, void* out_e, const void* in_e, voi
 // r -= alpha D^dag D^ p with partial |r|^2 per hop block in `partial`
 // (hop_partials(op, nrhs) of them).  r holds the compute type (FP64 for
 // kind FP64, FP32 otherwise); D^dag D^ p itself is not stored.
+// alpha_copy (or nullptr) also receives alpha.
 void apply_normal_update_r(const dwf_op* op, int kind, void* r, const void* p, void* tmp_o, void* tmp_v,
-                           double* partial, double* scal, int nrhs, hipStream_t st);
+                           double* partial, double* scal, int nrhs, hipStream_t st, double* alpha_copy = nullptr);
 void apply_full(const dwf_op* op, int kind, int dagger, void* out_e, void* out_o, const void* in_e,
                 const void* in_o, int nrhs, hipStream_t st);
 void schur_rhs(const dwf_op* op, int kind, void* bt_e, const void* b_e, const void* b_o, void* tmp_o,

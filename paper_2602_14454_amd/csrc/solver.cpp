@@ -58,10 +58,20 @@ int cgnr(const dwf_op* op, CgWork& W, const void* b_kp, double tol_rel, int maxi
     Pinned& hs = W.hs;
     if (check_every < 1) check_every = 1;
     DWF_HIP(hipMemsetAsync(W.scal.p, 0, CG_NSLOTS * sizeof(double), st));
+    // p lives in a ring of kRing slots unless the caller wants x after every
+    // iteration (on_iter)
+    const bool ring = !on_iter;
+    const long Vhp = op->lat->Vhp;
+    const size_t pbytes = complex_bytes_of(W.kp) * (size_t)n;
+    if (ring && !W.ring.p) {
+        W.ring.alloc(pbytes * CgWork::kRing);
+        W.alphas.alloc(sizeof(double) * CgWork::kRing);
+    }
+    auto slot = [&](int i) -> void* { return static_cast<char*>(W.ring.p) + (size_t)i * pbytes; };
     // r = D^dag b, p = r, x = 0
     apply_dhat(op, W.kp, 1, W.w.p, b_kp, W.t.p, W.v.p, W.nrhs, st);
-    convert(W.kx, W.kp, W.r.p, W.w.p, n, st, op->lat->Vhp);
-    convert(W.kp, W.kx, W.p.p, W.r.p, n, st, op->lat->Vhp);
+    convert(W.kx, W.kp, W.r.p, W.w.p, n, st, Vhp);
+    convert(W.kp, W.kx, ring ? slot(0) : W.p.p, W.r.p, n, st, Vhp);
     DWF_HIP(hipMemsetAsync(W.x.p, 0, complex_bytes_of(W.kx) * n, st));
     norm2_partial(W.kx, W.r.p, n, partial, st);
     finalize(partial, blas_grid(n), 1, scal + CG_RR, 0, st);
@@ -75,12 +85,30 @@ int cgnr(const dwf_op* op, CgWork& W, const void* b_kp, double tol_rel, int maxi
     const double stop = tol_rel * tol_rel * rr0;
     int k = 0;
     double rr = rr0;
+    int cur = 0, pend = 0;   // ring slot of p_k; slots [0, pend) hold directions not yet in x
+    double* alphas = W.alphas.as<double>();
     while (k < maxiter) {
-        // alpha, then r -= alpha D^dag D^ p inside the last hop (|r|^2 partials);
-        // the x update rides on the p update, which reads p anyway
-        apply_normal_update_r(op, W.kp, W.r.p, W.p.p, W.t.p, W.v.p, partial, scal, W.nrhs, st);
+        // alpha, then r -= alpha D^dag D^ p inside the last hop (|r|^2 partials)
+        void* pk = ring ? slot(cur) : W.p.p;
+        apply_normal_update_r(op, W.kp, W.r.p, pk, W.t.p, W.v.p, partial, scal, W.nrhs, st,
+                              ring ? alphas + cur : nullptr);
         finalize(partial, hop_partials(op, W.nrhs), 1, scal, 2, st);
-        cg_update_px(W.kx, W.kp, W.x.p, W.p.p, W.r.p, n, scal + CG_ALPHA, scal + CG_BETA, st, op->lat->Vhp);
+        if (ring) {
+            // p_{k+1} = r + beta p_k into the next slot; a full ring is folded
+            // into x first (x += alpha_i p_i in order, as the per-iteration update)
+            ++pend;
+            int nxt = cur + 1;
+            if (nxt == CgWork::kRing) {
+                cg_accumulate_x(W.kx, W.kp, W.x.p, W.ring.p, alphas, pend, n, st, Vhp);
+                pend = 0;
+                nxt = 0;
+            }
+            cg_update_p2(W.kx, W.kp, slot(nxt), pk, W.r.p, n, scal + CG_BETA, st, Vhp);
+            cur = nxt;
+        } else {
+            // the x update rides on the p update, which reads p anyway
+            cg_update_px(W.kx, W.kp, W.x.p, W.p.p, W.r.p, n, scal + CG_ALPHA, scal + CG_BETA, st, Vhp);
+        }
         ++k;
         if (on_iter) on_iter(k, W.x.p);
         if (k % check_every == 0 || k == maxiter) {
@@ -93,6 +121,7 @@ int cgnr(const dwf_op* op, CgWork& W, const void* b_kp, double tol_rel, int maxi
             if (rr <= stop) break;
         }
     }
+    if (ring) cg_accumulate_x(W.kx, W.kp, W.x.p, W.ring.p, alphas, pend, n, st, Vhp);
     if (final_rel) *final_rel = std::sqrt(rr / rr0);
     return k;
 }

@@ -24,6 +24,11 @@ struct CgWork {
     long n;   // complex elements per field (all RHS)
     DevBuf x, r, p, t, v, w, partial, scal;
     Pinned hs;
+    // search directions of the last iterations and their alphas: x is formed
+    // from them every kRing iterations and at the end of a solve instead of
+    // being read and written by every iteration
+    static constexpr int kRing = 16;
+    DevBuf ring, alphas;
     CgWork(const dwf_op* op, int kx, int kp, int nrhs);
 };
 
