@@ -14,7 +14,9 @@
 // iteration count and done flag on the device.  A slot that has converged
 // is skipped by every kernel.  The iteration body (k iterations) is
 // captured once into a HIP graph and replayed; the host reads the done
-// flags after each replay.  The FP64 outer steps use the per-operator
+// flags after each replay.  Within a replay the search directions go to a
+// ring of batch vectors and x is formed from them at the end of the ring
+// and of the replay, so x is not read or written in every iteration.  The FP64 outer steps use the per-operator
 // kernels with all right-hand sides of an operator in one launch.
 #include <algorithm>
 #include <cmath>
@@ -170,21 +172,28 @@ std::string tune_key(const std::vector<Item>& items, int kp) {
 }
 
 // The four hops of D^dag D^ (ops.cpp apply_normal) as work-list launches.
+// The first two read the search direction, which lives in one of `ring`
+// batch vectors: they have one table per ring slot.
 struct NormalHops {
     std::vector<HopClass> classes;
     DevBuf items_dev, meta_dev;
     std::vector<int> blocks;   // per class
-    int nrb = 1, order = 0, kind = ST_F32;
+    int nrb = 1, order = 0, kind = ST_F32, ring = 1;
     size_t per_stage = 0;      // HopParams per stage
     size_t meta_per_class = 0;
     bool stage_loc[4] = {false, false, false, false};   // stage carries a local term
 
-    // fields: in/out buffers of storage `kind`; partial/pstride/done for the |q|^2 reduction
-    void build(const std::vector<Item>& items, int kind_, int nrb_, int order_, void* p, void* t, void* v, void* r,
-               double* partial, long pstride, const double* scal) {
+    // table of stage sidx with the direction in ring slot q
+    size_t table(int sidx, int q) const { return sidx < 2 ? (size_t)(2 * q + sidx) : (size_t)(2 * ring + sidx - 2); }
+
+    // fields: in/out buffers of storage `kind` (ring slot q of the direction at
+    // p_ring + q * ring_bytes); partial/pstride/done for the reductions
+    void build(const std::vector<Item>& items, int kind_, int nrb_, int order_, void* p_ring, size_t ring_bytes,
+               int ring_, void* t, void* v, void* r, double* partial, long pstride, const double* scal) {
         kind = kind_;
         nrb = nrb_;
         order = order_;
+        ring = ring_;
         classes.clear();
         for (int i = 0; i < (int)items.size(); ++i) {
             const int KK = (items[i].op->Ls + 3) / 4;
@@ -199,7 +208,7 @@ struct NormalHops {
         per_stage = items.size();
         meta_per_class = 0;
         for (auto& c : classes) meta_per_class = std::max(meta_per_class, 2 * c.items.size() + 1);
-        hp.resize(4 * per_stage);
+        hp.resize((2 * (size_t)ring + 2) * per_stage);
         meta.assign(classes.size() * meta_per_class, 0);
         int pos = 0;
         for (size_t ci = 0; ci < classes.size(); ++ci) {
@@ -215,9 +224,9 @@ struct NormalHops {
                 const dwf_op* op = it.op;
                 double* part = partial + (long)it.slot0 * pstride;
                 const double* done = scal + (long)it.slot0 * CG_NSLOTS + CG_DONE;
-                HopParams s1 = hop_params(op, kind, 1, at(p), nullptr, at(t), PRE_K, MAT_Q, -1, 0.0, nullptr, 0, 0,
-                                          nullptr, 0);
-                HopParams s2 = hop_params(op, kind, 0, at(t), at(p), nullptr, -1, MAT_MQMINV, -1, 1.0, at(v),
+                HopParams s1 = hop_params(op, kind, 1, at(p_ring), nullptr, at(t), PRE_K, MAT_Q, -1, 0.0, nullptr, 0,
+                                          0, nullptr, 0);
+                HopParams s2 = hop_params(op, kind, 0, at(t), at(p_ring), nullptr, -1, MAT_MQMINV, -1, 1.0, at(v),
                                           DWF_CHAIN2 ? MAT_G5MIT : MAT_G5MIT_MQMINV, MAT_G5MIT, part, 1);
                 s2.chain2 = DWF_CHAIN2;   // v = g5 Minv^T q from q itself
                 HopParams s3 = hop_params(op, kind, 1, at(v), nullptr, at(t), -1, MAT_QT, -1, 0.0, nullptr, 0, 0,
@@ -237,10 +246,16 @@ struct NormalHops {
                 stage_loc[1] = s2.loc != nullptr;
                 stage_loc[2] = s3.loc != nullptr;
                 stage_loc[3] = s4.loc != nullptr;
-                hp[0 * per_stage + pos] = s1;
-                hp[1 * per_stage + pos] = s2;
-                hp[2 * per_stage + pos] = s3;
-                hp[3 * per_stage + pos] = s4;
+                for (int q = 0; q < ring; ++q) {
+                    const size_t shift = (size_t)q * ring_bytes;
+                    HopParams a = s1, b = s2;
+                    a.in = static_cast<const char*>(s1.in) + shift;
+                    b.loc = static_cast<const char*>(s2.loc) + shift;
+                    hp[table(0, q) * per_stage + pos] = a;
+                    hp[table(1, q) * per_stage + pos] = b;
+                }
+                hp[table(2, 0) * per_stage + pos] = s3;
+                hp[table(3, 0) * per_stage + pos] = s4;
                 ++pos;
             }
             m[c.items.size()] = acc;
@@ -252,10 +267,10 @@ struct NormalHops {
         DWF_HIP(hipMemcpy(meta_dev.p, meta.data(), meta.size() * sizeof(int), hipMemcpyHostToDevice));
     }
 
-    void stage(int sidx, hipStream_t st) const {
+    void stage(int sidx, int q, hipStream_t st) const {
         size_t first = 0;
         for (size_t ci = 0; ci < classes.size(); ++ci) {
-            const HopParams* it = items_dev.as<HopParams>() + sidx * per_stage + first;
+            const HopParams* it = items_dev.as<HopParams>() + table(sidx, q) * per_stage + first;
             const int* m = meta_dev.as<int>() + ci * meta_per_class;
             launch_hop_batch(kind, classes[ci].KK, it, m, (int)classes[ci].items.size(), blocks[ci], nrb, order,
                              stage_loc[sidx], st);
@@ -316,41 +331,62 @@ void make_batch(Batch& B, int n, const dwf_op* const* ops, const int* nrhs) {
     B.inner_tol2.alloc((size_t)B.nslots * sizeof(double));
 }
 
+// Inner CG state.  The search directions of a check period go to a ring of
+// `ring` batch vectors with their alphas (one per slot and ring slot); x is
+// formed from them when the ring fills and at the end of the period, in the
+// order of the iterations, so it matches x += alpha p per iteration bit for bit.
 struct Inner {
-    int kx, kp;
-    DevBuf x, r, p, t, v;
+    int kx, kp, ring;
+    size_t bp;   // bytes of one ring slot (one batch vector of storage kp)
+    DevBuf x, r, p, t, v, alph;
     NormalHops hops;
     GraphExec graph;
     int graph_k = 0;
-    Inner(const Batch& B, int kx_, int kp_) : kx(kx_), kp(kp_) {
-        const size_t bx = complex_bytes_of(kx) * B.N, bp = complex_bytes_of(kp) * B.N;
+    Inner(const Batch& B, int kx_, int kp_, int ring_) : kx(kx_), kp(kp_), ring(ring_) {
+        const size_t bx = complex_bytes_of(kx) * B.N;
+        bp = complex_bytes_of(kp) * B.N;
         x.alloc(bx);
         r.alloc(bx);
-        p.alloc(bp);
+        p.alloc(bp * ring);
         t.alloc(bp);
         v.alloc(bp);
+        alph.alloc(sizeof(double) * B.nslots * ring);
+    }
+    void* pslot(int q) const { return static_cast<char*>(p.p) + (size_t)q * bp; }
+    void build_hops(const Batch& B, int nrb, int order) {
+        hops.build(B.items, kp, nrb, order, p.p, bp, ring, t.p, v.p, r.p, B.partial.as<double>(), B.pstride,
+                   B.scal.as<double>());
     }
 };
 
-// one inner CG iteration over every slot
-void iteration(const Batch& B, Inner& I, hipStream_t st) {
+// ring length for a check period of k iterations
+int ring_length(int k) { return std::min(k, 16); }
+
+// iteration q (0-based) of a check period of k iterations, over every slot
+void iteration(const Batch& B, Inner& I, int q, int k, hipStream_t st) {
     const SlotDesc* sd = B.slots_dev.as<SlotDesc>();
     double* pp = B.partial.as<double>();
     double* sc = B.scal.as<double>();
-    I.hops.stage(0, st);
-    I.hops.stage(1, st);
-    bfinalize(pp, B.pstride, sd, B.nslots, sc, 1, 1, nullptr, st);
-    I.hops.stage(2, st);
-    I.hops.stage(3, st);   // r -= alpha D^dag D^ p, |r|^2 partials per hop tile
+    const int pos = q % I.ring;
+    I.hops.stage(0, pos, st);
+    I.hops.stage(1, pos, st);
+    bfinalize(pp, B.pstride, sd, B.nslots, sc, 1, 1, nullptr, st, I.alph.as<double>() + pos, I.ring);
+    I.hops.stage(2, pos, st);
+    I.hops.stage(3, pos, st);   // r -= alpha D^dag D^ p, |r|^2 partials per hop tile
     bfinalize(pp, B.pstride, sd, B.nslots, sc, 2, 1, nullptr, st);
-    bcg_px(I.kx, I.kp, I.x.p, I.p.p, I.r.p, sd, B.nslots, B.vblocks, sc, st);
+    // the next direction starts a new ring when this one fills it or the period ends:
+    // x takes the ring's directions first
+    const int next = q + 1 == k ? 0 : (pos + 1) % I.ring;
+    if (next == 0)
+        bcg_accx(I.kx, I.kp, I.x.p, I.p.p, B.N, I.alph.as<double>(), I.ring, pos + 1, sd, B.nslots, B.vblocks, st);
+    bcg_p2(I.kx, I.kp, I.pslot(next), I.pslot(pos), I.r.p, sd, B.nslots, B.vblocks, sc, st);
 }
 
 void capture(const Batch& B, Inner& I, int k, hipStream_t cs) {
     I.graph.reset();
     DWF_HIP(hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal));
     try {
-        for (int q = 0; q < k; ++q) iteration(B, I, cs);
+        for (int q = 0; q < k; ++q) iteration(B, I, q, k, cs);
     } catch (...) {
         hipGraph_t g = nullptr;
         (void)hipStreamEndCapture(cs, &g);
@@ -364,14 +400,13 @@ void capture(const Batch& B, Inner& I, int k, hipStream_t cs) {
 
 // times the four hops of D^dag D^ for one (nrb, order)
 double time_hops(const Batch& B, Inner& I, int nrb, int order, hipStream_t st) {
-    I.hops.build(B.items, I.kp, nrb, order, I.p.p, I.t.p, I.v.p, I.r.p, B.partial.as<double>(), B.pstride,
-                 B.scal.as<double>());
+    I.build_hops(B, nrb, order);
     Event e0, e1;
-    for (int s = 0; s < 4; ++s) I.hops.stage(s, st);
+    for (int s = 0; s < 4; ++s) I.hops.stage(s, 0, st);
     DWF_HIP(hipEventRecord(e0.e, st));
     const int reps = 5;
     for (int q = 0; q < reps; ++q)
-        for (int s = 0; s < 4; ++s) I.hops.stage(s, st);
+        for (int s = 0; s < 4; ++s) I.hops.stage(s, 0, st);
     DWF_HIP(hipEventRecord(e1.e, st));
     DWF_HIP(hipEventSynchronize(e1.e));
     float ms = 0;
@@ -428,7 +463,7 @@ void autotune_batch(int n, const dwf_op* const* ops, const int* nrhs, int kp, in
     DWF_REQUIRE(kp == ST_F64 || kp == ST_F32 || kp == ST_BF16, DWF_EINVAL, "bad precision");
     Batch B;
     make_batch(B, n, ops, nrhs);
-    Inner I(B, kp == ST_F64 ? ST_F64 : ST_F32, kp);
+    Inner I(B, kp == ST_F64 ? ST_F64 : ST_F32, kp, 1);
     choose_tiles(B, I, force ? 2 : 1, st, nrb, order, ms);
     DWF_HIP(hipStreamSynchronize(st));
 }
@@ -454,7 +489,8 @@ int solve_batch(int n, const dwf_op* const* ops, void* const* x5, const void* co
         if (prm->inner_tol > 0 && k == kp) return prm->inner_tol;
         return k == ST_F64 ? tol : (k == ST_F32 ? 1e-5 : 3e-2);
     };
-    std::unique_ptr<Inner> I(new Inner(B, kp == ST_F64 ? ST_F64 : ST_F32, kp));
+    const int ring = ring_length(check_every);
+    std::unique_ptr<Inner> I(new Inner(B, kp == ST_F64 ? ST_F64 : ST_F32, kp, ring));
     const int ns = B.nslots;
     PinnedD hs((size_t)ns * CG_NSLOTS);
     std::vector<int> odone(ns, 0);
@@ -468,8 +504,7 @@ int solve_batch(int n, const dwf_op* const* ops, void* const* x5, const void* co
     double tms = 0;
     const int autotune = prm->autotune;
     choose_tiles(B, *I, autotune, cs.s, &nrb, &order, &tms);
-    I->hops.build(B.items, kp, nrb, order, I->p.p, I->t.p, I->v.p, I->r.p, B.partial.as<double>(), B.pstride,
-                  B.scal.as<double>());
+    I->build_hops(B, nrb, order);
 
     const SlotDesc* sd = B.slots_dev.as<SlotDesc>();
     double* pp = B.partial.as<double>();
@@ -529,7 +564,7 @@ int solve_batch(int n, const dwf_op* const* ops, void* const* x5, const void* co
             convert(I->kx, ST_F64, static_cast<char*>(I->r.p) + complex_bytes_of(I->kx) * it.off, at(te.p, it.off),
                     it.n1 * it.nrhs, cs.s, it.op->lat->Vhp);
         for (const Item& it : B.items)
-            convert(I->kp, I->kx, static_cast<char*>(I->p.p) + complex_bytes_of(I->kp) * it.off,
+            convert(I->kp, I->kx, static_cast<char*>(I->pslot(0)) + complex_bytes_of(I->kp) * it.off,
                     static_cast<char*>(I->r.p) + complex_bytes_of(I->kx) * it.off, it.n1 * it.nrhs, cs.s,
                     it.op->lat->Vhp);
         DWF_HIP(hipMemsetAsync(I->x.p, 0, complex_bytes_of(I->kx) * N, cs.s));
@@ -550,7 +585,7 @@ int solve_batch(int n, const dwf_op* const* ops, void* const* x5, const void* co
         while (done_iters < budget) {
             if (use_graph) DWF_HIP(hipGraphLaunch(I->graph.x, cs.s));
             else
-                for (int q = 0; q < check_every; ++q) iteration(B, *I, cs.s);
+                for (int q = 0; q < check_every; ++q) iteration(B, *I, q, check_every, cs.s);
             done_iters += check_every;
             read_scal();
             bool all = true;
@@ -597,8 +632,8 @@ int solve_batch(int n, const dwf_op* const* ops, void* const* x5, const void* co
         if (stagnated) {
             // step the inner storage up one precision for the rest of the batch
             const int nk = I->kp == ST_BF16 ? ST_F32 : ST_F64;
-            I.reset(new Inner(B, nk == ST_F64 ? ST_F64 : ST_F32, nk));
-            I->hops.build(B.items, nk, nrb, order, I->p.p, I->t.p, I->v.p, I->r.p, pp, B.pstride, sc);
+            I.reset(new Inner(B, nk == ST_F64 ? ST_F64 : ST_F32, nk, ring));
+            I->build_hops(B, nrb, order);
             fallback = 1;
         }
     }

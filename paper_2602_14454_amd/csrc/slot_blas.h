@@ -14,10 +14,7 @@
 namespace dwf {
 
 // extra per-slot CG scalars (after the ones in blas.h)
-// CG_XPEND: the slot converged in this iteration and its x update is still
-// due (the fused step updates x together with p, after the finalize that
-// sets CG_DONE)
-enum { CG_DONE = 9, CG_STOP = 10, CG_ITERS = 11, CG_XPEND = 12 };
+enum { CG_DONE = 9, CG_STOP = 10, CG_ITERS = 11 };
 
 struct SlotDesc {
     long off;     // complex-element offset of the slot in every batch vector
@@ -35,25 +32,26 @@ int slot_blocks(long n);
 // partial[v * pstride + b] = |x_v|^2 over block b of slot v
 void bnorm2(int kind, const void* x, const SlotDesc* slots, int nslots, int blocks, double* partial, long pstride,
             const double* scal, hipStream_t st);
-// x_v += alpha_v p_v; r_v -= alpha_v w_v; partial |r_v|^2   (alpha_v = scal[v][CG_ALPHA])
-void bcg_xr(int kx, int kp, void* x, void* r, const void* p, const void* w, const SlotDesc* slots, int nslots,
-            int blocks, const double* scal, double* partial, long pstride, hipStream_t st);
-// p_v = r_v + beta_v p_v
-void bcg_p(int kx, int kp, void* p, const void* r, const SlotDesc* slots, int nslots, int blocks,
-           const double* scal, hipStream_t st);
-// x_v += alpha_v p_v (slots not done, or done with CG_XPEND set); then
-// p_v = r_v + beta_v p_v (slots not done)
-void bcg_px(int kx, int kp, void* x, void* p, const void* r, const SlotDesc* slots, int nslots, int blocks,
-            const double* scal, hipStream_t st);
+// Direction ring of the batched CG: every batch vector of the ring holds one
+// search direction of every slot (ring slot q at ring + q * N complex
+// elements, N = elements of one batch vector).
+// p_dst_v = r_v + beta_v p_src_v (slots not done)
+void bcg_p2(int kx, int kp, void* p_dst, const void* p_src, const void* r, const SlotDesc* slots, int nslots,
+            int blocks, const double* scal, hipStream_t st);
+// x_v += alpha[v * astride + q] p_q for q = 0 .. cnt-1 in this order, with
+// p_q ring slot q; a zero alpha (a slot already done) adds nothing
+void bcg_accx(int kx, int kp, void* x, const void* ring, long N, const double* alpha, int astride, int cnt,
+              const SlotDesc* slots, int nslots, int blocks, hipStream_t st);
 // Per-slot reduction of the partials (count: nhop if from_hop, else nb) and
 // CG scalar update, one block per slot:
-//  mode 0: RR = RR0 = sum; STOP = tol2[v] * sum; ITERS = 0; XPEND = 0;
+//  mode 0: RR = RR0 = sum; STOP = tol2[v] * sum; ITERS = 0;
 //          DONE = (sum == 0 || tol2[v] < 0); NANFLAG = !finite(sum)
-//  mode 1: QQ = sum; ALPHA = RR / QQ (done slots: XPEND = 0)
+//  mode 1: QQ = sum; ALPHA = RR / QQ; alpha_out[v * astride] = ALPHA
+//          (done slots: alpha_out[v * astride] = 0 and nothing else)
 //  mode 2: RRNEW = sum; BETA = sum / RR; RROLD = RR; RR = sum; ITERS += 1;
-//          sum <= STOP: DONE = XPEND = 1; non-finite: NANFLAG = DONE = 1
+//          sum <= STOP: DONE = 1; non-finite: NANFLAG = DONE = 1
 //  mode 4: TMP = sum (any slot, done or not)
 void bfinalize(const double* partial, long pstride, const SlotDesc* slots, int nslots, double* scal, int mode,
-               int from_hop, const double* tol2, hipStream_t st);
+               int from_hop, const double* tol2, hipStream_t st, double* alpha_out = nullptr, int astride = 0);
 
 }  // namespace dwf

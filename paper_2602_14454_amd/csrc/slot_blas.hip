@@ -47,157 +47,104 @@ __global__ __launch_bounds__(BT) void bnorm2_kernel(const void* x, const SlotDes
     if (threadIdx.x == 0) partial[(long)v * pstride + b] = t;
 }
 
-template <class SX, class SP>
-__global__ __launch_bounds__(BT) void bcg_xr_kernel(void* x, void* r, const void* p, const void* w,
-                                                    const SlotDesc* __restrict__ slots, int nslots,
-                                                    const double* scal, double* partial, long pstride) {
-    __shared__ double red[BT / 64];
-    const int v = find_slot(slots, nslots, blockIdx.x);
-    const SlotDesc d = slots[v];
-    const int b = blockIdx.x - d.block0;
-    const double* sv = scal + (long)v * CG_NSLOTS;
-    if (sv[CG_DONE] != 0.0) return;   // block-uniform
-    using RX = typename Traits<SX>::R;
-    const RX a = RX(sv[CG_ALPHA]);
-    double acc = 0.0;
-    auto upd = [&](long kx, long kp) {
-        typename Traits<SP>::R pr, pi, wr, wi;
-        RX xr, xi, rr, ri;
-        cload<SP>(p, kp, pr, pi);
-        cload<SP>(w, kp, wr, wi);
-        cload<SX>(x, kx, xr, xi);
-        cload<SX>(r, kx, rr, ri);
-        xr += a * RX(pr); xi += a * RX(pi);
-        rr -= a * RX(wr); ri -= a * RX(wi);
-        cstore<SX>(x, kx, xr, xi);
-        cstore<SX>(r, kx, rr, ri);
-        acc += double(rr) * double(rr) + double(ri) * double(ri);
-    };
-    if constexpr (fpack<SX>() == fpack<SP>()) {
-        for (long i = (long)b * BT + threadIdx.x; i < d.n; i += (long)d.nb * BT) upd(d.off + i, d.off + i);
-    } else {
-        // operands in different layouts: four components of one site per step
-        // (slot offsets are multiples of 4 * Vhp complex, whole groups)
-        const char* pb = static_cast<const char*>(p) + d.off * cbytes<SP>();
-        const char* wb = static_cast<const char*>(w) + d.off * cbytes<SP>();
-        char* xb = static_cast<char*>(x) + d.off * cbytes<SX>();
-        char* rb = static_cast<char*>(r) + d.off * cbytes<SX>();
-        for (long t = (long)b * BT + threadIdx.x; t < d.n / 4; t += (long)d.nb * BT) {
-            const long g = t / d.Vhp, site = t - g * d.Vhp;
-            typename Traits<SP>::R pv[8], wv[8];
-            RX xv[8], rv[8];
-            load4<SP>(pb, g, site, d.Vhp, pv);
-            load4<SP>(wb, g, site, d.Vhp, wv);
-            load4<SX>(xb, g, site, d.Vhp, xv);
-            load4<SX>(rb, g, site, d.Vhp, rv);
-#pragma unroll
-            for (int q = 0; q < 8; ++q) {
-                xv[q] += a * RX(pv[q]);
-                rv[q] -= a * RX(wv[q]);
-                acc += double(rv[q]) * double(rv[q]);
-            }
-            store4<SX>(xb, g, site, d.Vhp, xv);
-            store4<SX>(rb, g, site, d.Vhp, rv);
-        }
-    }
-    const double t = bsum(acc, red);
-    if (threadIdx.x == 0) partial[(long)v * pstride + b] = t;
-}
-
 template <class SR, class SP>
-__global__ __launch_bounds__(BT) void bcg_p_kernel(void* p, const void* r, const SlotDesc* __restrict__ slots,
-                                                   int nslots, const double* scal) {
-    const int v = find_slot(slots, nslots, blockIdx.x);
-    const SlotDesc d = slots[v];
-    const int b = blockIdx.x - d.block0;
-    const double* sv = scal + (long)v * CG_NSLOTS;
-    if (sv[CG_DONE] != 0.0) return;
-    using RP = typename Traits<SP>::R;
-    const RP be = RP(sv[CG_BETA]);
-    auto upd = [&](long kr, long kp) {
-        typename Traits<SR>::R rr, ri;
-        RP pr, pi;
-        cload<SR>(r, kr, rr, ri);
-        cload<SP>(p, kp, pr, pi);
-        cstore<SP>(p, kp, RP(rr) + be * pr, RP(ri) + be * pi);
-    };
-    if constexpr (fpack<SR>() == fpack<SP>()) {
-        for (long i = (long)b * BT + threadIdx.x; i < d.n; i += (long)d.nb * BT) upd(d.off + i, d.off + i);
-    } else {
-        const char* rb = static_cast<const char*>(r) + d.off * cbytes<SR>();
-        char* pb = static_cast<char*>(p) + d.off * cbytes<SP>();
-        for (long t = (long)b * BT + threadIdx.x; t < d.n / 4; t += (long)d.nb * BT) {
-            const long g = t / d.Vhp, site = t - g * d.Vhp;
-            typename Traits<SR>::R rv[8];
-            RP pv[8];
-            load4<SR>(rb, g, site, d.Vhp, rv);
-            load4<SP>(pb, g, site, d.Vhp, pv);
-#pragma unroll
-            for (int q = 0; q < 8; ++q) pv[q] = RP(rv[q]) + be * pv[q];
-            store4<SP>(pb, g, site, d.Vhp, pv);
-        }
-    }
-}
-
-template <class SX, class SP>
-__global__ __launch_bounds__(BT) void bcg_px_kernel(void* x, void* p, const void* r,
+__global__ __launch_bounds__(BT) void bcg_p2_kernel(void* pd, const void* ps, const void* r,
                                                     const SlotDesc* __restrict__ slots, int nslots,
                                                     const double* scal) {
     const int v = find_slot(slots, nslots, blockIdx.x);
     const SlotDesc d = slots[v];
     const int b = blockIdx.x - d.block0;
     const double* sv = scal + (long)v * CG_NSLOTS;
-    const bool done = sv[CG_DONE] != 0.0;
-    if (done && sv[CG_XPEND] == 0.0) return;
+    if (sv[CG_DONE] != 0.0) return;   // block-uniform
+    using RP = typename Traits<SP>::R;
+    const RP be = RP(sv[CG_BETA]);
+    if constexpr (fpack<SR>() == fpack<SP>()) {
+        for (long i = (long)b * BT + threadIdx.x; i < d.n; i += (long)d.nb * BT) {
+            const long k = d.off + i;
+            typename Traits<SR>::R rr, ri;
+            RP pr, pi;
+            cload<SR>(r, k, rr, ri);
+            cload<SP>(ps, k, pr, pi);
+            cstore<SP>(pd, k, RP(rr) + be * pr, RP(ri) + be * pi);
+        }
+    } else {
+        // operands in different layouts: four components of one site per step
+        // (slot offsets are multiples of 4 * Vhp complex, whole groups)
+        const char* rb = static_cast<const char*>(r) + d.off * cbytes<SR>();
+        const char* sb = static_cast<const char*>(ps) + d.off * cbytes<SP>();
+        char* db = static_cast<char*>(pd) + d.off * cbytes<SP>();
+        for (long t = (long)b * BT + threadIdx.x; t < d.n / 4; t += (long)d.nb * BT) {
+            const long g = t / d.Vhp, site = t - g * d.Vhp;
+            typename Traits<SR>::R rv[8];
+            RP pv[8];
+            load4<SR>(rb, g, site, d.Vhp, rv);
+            load4<SP>(sb, g, site, d.Vhp, pv);
+#pragma unroll
+            for (int q = 0; q < 8; ++q) pv[q] = RP(rv[q]) + be * pv[q];
+            store4<SP>(db, g, site, d.Vhp, pv);
+        }
+    }
+}
+
+template <class SX, class SP>
+__global__ __launch_bounds__(BT) void bcg_accx_kernel(void* x, const void* ring, long N, const double* alpha,
+                                                      int astride, int cnt, const SlotDesc* __restrict__ slots,
+                                                      int nslots) {
+    const int v = find_slot(slots, nslots, blockIdx.x);
+    const SlotDesc d = slots[v];
+    const int b = blockIdx.x - d.block0;
+    const double* al = alpha + (long)v * astride;
+    bool any = false;
+    for (int q = 0; q < cnt; ++q) any = any || al[q] != 0.0;
+    if (!any) return;   // block-uniform: the slot was done for the whole ring
     using RX = typename Traits<SX>::R;
     using RP = typename Traits<SP>::R;
-    const RX al = RX(sv[CG_ALPHA]);
-    const RP be = RP(sv[CG_BETA]);
+    const size_t qb = (size_t)N * cbytes<SP>();   // bytes of one ring slot
     if constexpr (fpack<SX>() == fpack<SP>()) {
         for (long i = (long)b * BT + threadIdx.x; i < d.n; i += (long)d.nb * BT) {
             const long k = d.off + i;
-            RX xr, xi, rr, ri;
-            RP pr, pi;
-            cload<SP>(p, k, pr, pi);
+            RX xr, xi;
             cload<SX>(x, k, xr, xi);
-            cstore<SX>(x, k, xr + al * RX(pr), xi + al * RX(pi));
-            if (!done) {
-                cload<SX>(r, k, rr, ri);
-                cstore<SP>(p, k, RP(rr) + be * pr, RP(ri) + be * pi);
+            for (int q = 0; q < cnt; ++q) {
+                if (al[q] == 0.0) continue;
+                RP pr, pi;
+                cload<SP>(static_cast<const char*>(ring) + q * qb, k, pr, pi);
+                const RX a = RX(al[q]);
+                xr = xr + a * RX(pr);
+                xi = xi + a * RX(pi);
             }
+            cstore<SX>(x, k, xr, xi);
         }
     } else {
         char* xb = static_cast<char*>(x) + d.off * cbytes<SX>();
-        const char* rb = static_cast<const char*>(r) + d.off * cbytes<SX>();
-        char* pb = static_cast<char*>(p) + d.off * cbytes<SP>();
+        const char* pb = static_cast<const char*>(ring) + d.off * cbytes<SP>();
         for (long t = (long)b * BT + threadIdx.x; t < d.n / 4; t += (long)d.nb * BT) {
             const long g = t / d.Vhp, site = t - g * d.Vhp;
-            RX xv[8], rv[8];
-            RP pv[8];
-            load4<SP>(pb, g, site, d.Vhp, pv);
+            RX xv[8];
             load4<SX>(xb, g, site, d.Vhp, xv);
+            for (int q = 0; q < cnt; ++q) {
+                if (al[q] == 0.0) continue;
+                RP pv[8];
+                load4<SP>(pb + q * qb, g, site, d.Vhp, pv);
+                const RX a = RX(al[q]);
 #pragma unroll
-            for (int q = 0; q < 8; ++q) xv[q] += al * RX(pv[q]);
-            store4<SX>(xb, g, site, d.Vhp, xv);
-            if (!done) {
-                load4<SX>(rb, g, site, d.Vhp, rv);
-#pragma unroll
-                for (int q = 0; q < 8; ++q) pv[q] = RP(rv[q]) + be * pv[q];
-                store4<SP>(pb, g, site, d.Vhp, pv);
+                for (int k = 0; k < 8; ++k) xv[k] = xv[k] + a * RX(pv[k]);
             }
+            store4<SX>(xb, g, site, d.Vhp, xv);
         }
     }
 }
 
 __global__ __launch_bounds__(BT) void bfinalize_kernel(const double* partial, long pstride,
                                                        const SlotDesc* __restrict__ slots, double* scal, int mode,
-                                                       int from_hop, const double* tol2) {
+                                                       int from_hop, const double* tol2, double* alpha_out,
+                                                       int astride) {
     __shared__ double red[BT];
     const int v = blockIdx.x;
     const SlotDesc d = slots[v];
     double* sv = scal + (long)v * CG_NSLOTS;
     if ((mode == 1 || mode == 2) && sv[CG_DONE] != 0.0) {
-        if (mode == 1 && threadIdx.x == 0) sv[CG_XPEND] = 0.0;   // its last x update is done
+        if (mode == 1 && alpha_out && threadIdx.x == 0) alpha_out[(long)v * astride] = 0.0;
         return;
     }
     const int np = from_hop ? d.nhop : d.nb;
@@ -219,12 +166,13 @@ __global__ __launch_bounds__(BT) void bfinalize_kernel(const double* partial, lo
         const double t2 = tol2 ? tol2[v] : 0.0;
         sv[CG_STOP] = t2 * sum;
         sv[CG_ITERS] = 0.0;
-        sv[CG_XPEND] = 0.0;
         sv[CG_NANFLAG] = fin ? 0.0 : 1.0;
         sv[CG_DONE] = (!fin || sum == 0.0 || t2 < 0.0) ? 1.0 : 0.0;
     } else if (mode == 1) {
         sv[CG_QQ] = sum;
-        sv[CG_ALPHA] = (sum > 0.0 && fin) ? sv[CG_RR] / sum : 0.0;
+        const double a = (sum > 0.0 && fin) ? sv[CG_RR] / sum : 0.0;
+        sv[CG_ALPHA] = a;
+        if (alpha_out) alpha_out[(long)v * astride] = a;
         if (!fin) { sv[CG_NANFLAG] = 1.0; sv[CG_DONE] = 1.0; }
     } else if (mode == 2) {
         sv[CG_RRNEW] = sum;
@@ -233,7 +181,7 @@ __global__ __launch_bounds__(BT) void bfinalize_kernel(const double* partial, lo
         sv[CG_RR] = sum;
         sv[CG_ITERS] += 1.0;
         if (!fin) { sv[CG_NANFLAG] = 1.0; sv[CG_DONE] = 1.0; }
-        else if (sum <= sv[CG_STOP]) { sv[CG_DONE] = 1.0; sv[CG_XPEND] = 1.0; }
+        else if (sum <= sv[CG_STOP]) sv[CG_DONE] = 1.0;
     } else {
         sv[CG_TMP] = sum;
         if (!fin) sv[CG_NANFLAG] = 1.0;
@@ -266,74 +214,54 @@ void bnorm2(int kind, const void* x, const SlotDesc* slots, int nslots, int bloc
     DWF_HIP(hipGetLastError());
 }
 
-template <class SX, class SP>
-static void bcg_xr_t2(void* x, void* r, const void* p, const void* w, const SlotDesc* slots, int nslots, int blocks,
-                      const double* scal, double* partial, long pstride, hipStream_t st) {
-    hipLaunchKernelGGL((bcg_xr_kernel<SX, SP>), dim3(blocks), dim3(BT), 0, st, x, r, p, w, slots, nslots, scal,
-                       partial, pstride);
-}
-template <class SX>
-static void bcg_xr_t1(int kp, void* x, void* r, const void* p, const void* w, const SlotDesc* slots, int nslots,
-                      int blocks, const double* scal, double* partial, long pstride, hipStream_t st) {
-    switch (kp) {
-        case ST_F64: bcg_xr_t2<SX, double>(x, r, p, w, slots, nslots, blocks, scal, partial, pstride, st); break;
-        case ST_F32: bcg_xr_t2<SX, float>(x, r, p, w, slots, nslots, blocks, scal, partial, pstride, st); break;
-        case ST_BF16: bcg_xr_t2<SX, bf16s>(x, r, p, w, slots, nslots, blocks, scal, partial, pstride, st); break;
-        default: throw Error{DWF_EINVAL, "bad storage kind"};
-    }
-}
-void bcg_xr(int kx, int kp, void* x, void* r, const void* p, const void* w, const SlotDesc* slots, int nslots,
-            int blocks, const double* scal, double* partial, long pstride, hipStream_t st) {
-    BDISPATCH1(kx, bcg_xr_t1, kp, x, r, p, w, slots, nslots, blocks, scal, partial, pstride, st);
-    DWF_HIP(hipGetLastError());
-}
-
 template <class SR, class SP>
-static void bcg_p_t2(void* p, const void* r, const SlotDesc* slots, int nslots, int blocks, const double* scal,
-                     hipStream_t st) {
-    hipLaunchKernelGGL((bcg_p_kernel<SR, SP>), dim3(blocks), dim3(BT), 0, st, p, r, slots, nslots, scal);
+static void bcg_p2_t2(void* pd, const void* ps, const void* r, const SlotDesc* slots, int nslots, int blocks,
+                      const double* scal, hipStream_t st) {
+    hipLaunchKernelGGL((bcg_p2_kernel<SR, SP>), dim3(blocks), dim3(BT), 0, st, pd, ps, r, slots, nslots, scal);
 }
 template <class SR>
-static void bcg_p_t1(int kp, void* p, const void* r, const SlotDesc* slots, int nslots, int blocks,
-                     const double* scal, hipStream_t st) {
+static void bcg_p2_t1(int kp, void* pd, const void* ps, const void* r, const SlotDesc* slots, int nslots, int blocks,
+                      const double* scal, hipStream_t st) {
     switch (kp) {
-        case ST_F64: bcg_p_t2<SR, double>(p, r, slots, nslots, blocks, scal, st); break;
-        case ST_F32: bcg_p_t2<SR, float>(p, r, slots, nslots, blocks, scal, st); break;
-        case ST_BF16: bcg_p_t2<SR, bf16s>(p, r, slots, nslots, blocks, scal, st); break;
+        case ST_F64: bcg_p2_t2<SR, double>(pd, ps, r, slots, nslots, blocks, scal, st); break;
+        case ST_F32: bcg_p2_t2<SR, float>(pd, ps, r, slots, nslots, blocks, scal, st); break;
+        case ST_BF16: bcg_p2_t2<SR, bf16s>(pd, ps, r, slots, nslots, blocks, scal, st); break;
         default: throw Error{DWF_EINVAL, "bad storage kind"};
     }
 }
-void bcg_p(int kx, int kp, void* p, const void* r, const SlotDesc* slots, int nslots, int blocks,
-           const double* scal, hipStream_t st) {
-    BDISPATCH1(kx, bcg_p_t1, kp, p, r, slots, nslots, blocks, scal, st);
+void bcg_p2(int kx, int kp, void* p_dst, const void* p_src, const void* r, const SlotDesc* slots, int nslots,
+            int blocks, const double* scal, hipStream_t st) {
+    BDISPATCH1(kx, bcg_p2_t1, kp, p_dst, p_src, r, slots, nslots, blocks, scal, st);
     DWF_HIP(hipGetLastError());
 }
 
 template <class SX, class SP>
-static void bcg_px_t2(void* x, void* p, const void* r, const SlotDesc* slots, int nslots, int blocks,
-                      const double* scal, hipStream_t st) {
-    hipLaunchKernelGGL((bcg_px_kernel<SX, SP>), dim3(blocks), dim3(BT), 0, st, x, p, r, slots, nslots, scal);
+static void bcg_accx_t2(void* x, const void* ring, long N, const double* alpha, int astride, int cnt,
+                        const SlotDesc* slots, int nslots, int blocks, hipStream_t st) {
+    hipLaunchKernelGGL((bcg_accx_kernel<SX, SP>), dim3(blocks), dim3(BT), 0, st, x, ring, N, alpha, astride, cnt,
+                       slots, nslots);
 }
 template <class SX>
-static void bcg_px_t1(int kp, void* x, void* p, const void* r, const SlotDesc* slots, int nslots, int blocks,
-                      const double* scal, hipStream_t st) {
+static void bcg_accx_t1(int kp, void* x, const void* ring, long N, const double* alpha, int astride, int cnt,
+                        const SlotDesc* slots, int nslots, int blocks, hipStream_t st) {
     switch (kp) {
-        case ST_F64: bcg_px_t2<SX, double>(x, p, r, slots, nslots, blocks, scal, st); break;
-        case ST_F32: bcg_px_t2<SX, float>(x, p, r, slots, nslots, blocks, scal, st); break;
-        case ST_BF16: bcg_px_t2<SX, bf16s>(x, p, r, slots, nslots, blocks, scal, st); break;
+        case ST_F64: bcg_accx_t2<SX, double>(x, ring, N, alpha, astride, cnt, slots, nslots, blocks, st); break;
+        case ST_F32: bcg_accx_t2<SX, float>(x, ring, N, alpha, astride, cnt, slots, nslots, blocks, st); break;
+        case ST_BF16: bcg_accx_t2<SX, bf16s>(x, ring, N, alpha, astride, cnt, slots, nslots, blocks, st); break;
         default: throw Error{DWF_EINVAL, "bad storage kind"};
     }
 }
-void bcg_px(int kx, int kp, void* x, void* p, const void* r, const SlotDesc* slots, int nslots, int blocks,
-            const double* scal, hipStream_t st) {
-    BDISPATCH1(kx, bcg_px_t1, kp, x, p, r, slots, nslots, blocks, scal, st);
+void bcg_accx(int kx, int kp, void* x, const void* ring, long N, const double* alpha, int astride, int cnt,
+              const SlotDesc* slots, int nslots, int blocks, hipStream_t st) {
+    DWF_REQUIRE(cnt >= 1 && cnt <= astride, DWF_EINVAL, "ring count out of range");
+    BDISPATCH1(kx, bcg_accx_t1, kp, x, ring, N, alpha, astride, cnt, slots, nslots, blocks, st);
     DWF_HIP(hipGetLastError());
 }
 
 void bfinalize(const double* partial, long pstride, const SlotDesc* slots, int nslots, double* scal, int mode,
-               int from_hop, const double* tol2, hipStream_t st) {
+               int from_hop, const double* tol2, hipStream_t st, double* alpha_out, int astride) {
     hipLaunchKernelGGL(bfinalize_kernel, dim3(nslots), dim3(BT), 0, st, partial, pstride, slots, scal, mode,
-                       from_hop, tol2);
+                       from_hop, tol2, alpha_out, astride);
     DWF_HIP(hipGetLastError());
 }
 
