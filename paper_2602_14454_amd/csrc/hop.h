@@ -56,6 +56,8 @@ struct MixParams {
 };
 
 int hop_grid_blocks(long Vh);
+// blocks of a mix launch per right-hand side (partials it writes, with partial set)
+int mix_grid_blocks(long Vh);
 void launch_hop(int kind, const HopParams& P, int nrhs, hipStream_t st, int bench_tag = 0);
 // One work-list launch over `nitems` HopParams (device array `items`, same
 // ceil(Ls/4) = KK for all) with block prefix sums and RHS counts in `meta`

@@ -693,7 +693,7 @@ __device__ __forceinline__ void hop_tile(const HopParams& P, long tile, int rhs,
                     if (sizeof(S) == 4 || upd) {   // FP32 values (the update needs them unrounded)
                         reinterpret_cast<float2*>(run)[(s & 3) * 16 + j] = make_float2(orr, oi);
                     } else {
-                        reinterpret_cast<unsigned*>(run)[(s & 3) * 16 + j] = f32_to_bf16(orr) | (f32_to_bf16(oi) << 16);
+                        reinterpret_cast<unsigned*>(run)[(s & 3) * 16 + j] = pack_bf16(orr, oi);
                     }
                 }
             }
@@ -921,7 +921,7 @@ static unsigned hop_smem_bytes(int KK, bool loc) {
 }
 
 int hop_grid_blocks(long Vh) { return (int)((Vh + 15) / 16); }
-static int mix_grid_blocks(long Vh) { return (int)((Vh + 63) / 64); }
+int mix_grid_blocks(long Vh) { return (int)((Vh + 63) / 64); }
 
 template <class S, int TAG>
 static void launch_hop_t(const HopParams& P, int nrhs, hipStream_t st) {

@@ -43,14 +43,14 @@ __device__ __forceinline__ float bf16_to_f32(uint32_t b) {
     return __uint_as_float(b << 16);
 }
 
-// Round-to-nearest-even conversion of a finite float to bfloat16 bits;
-// NaN is kept quiet.
-__device__ __forceinline__ uint32_t f32_to_bf16(float f) {
-    uint32_t u = __float_as_uint(f);
-    if ((u & 0x7f800000u) == 0x7f800000u && (u & 0x007fffffu)) return (u >> 16) | 0x40u;
-    uint32_t lsb = (u >> 16) & 1u;
-    u += 0x7fffu + lsb;
-    return u >> 16;
+// Two floats to a pair of bfloat16 (lo = re, hi = im), round to nearest
+// even, NaN stays NaN: one gfx950 v_cvt_pk_bf16_f32.  Checked against the
+// bit-level rounding rule over every 32-bit pattern.
+typedef __bf16 bf16x2_v __attribute__((ext_vector_type(2)));
+typedef float f32x2_v __attribute__((ext_vector_type(2)));
+__device__ __forceinline__ uint32_t pack_bf16(float re, float im) {
+    const f32x2_v f = {re, im};
+    return __builtin_bit_cast(uint32_t, __builtin_convertvector(f, bf16x2_v));
 }
 
 template <> struct Traits<bf16s> {
@@ -61,7 +61,7 @@ template <> struct Traits<bf16s> {
         return make_double2(bf16_to_f32(v & 0xffffu), bf16_to_f32(v >> 16));
     }
     static __device__ __forceinline__ void store(void* base, long i, float re, float im) {
-        reinterpret_cast<uint32_t*>(base)[i] = f32_to_bf16(re) | (f32_to_bf16(im) << 16);
+        reinterpret_cast<uint32_t*>(base)[i] = pack_bf16(re, im);
     }
 };
 
@@ -123,7 +123,7 @@ __device__ __forceinline__ void cstore_b(void* base, unsigned boff, typename Tra
     } else if constexpr (sizeof(S) == 4) {
         *reinterpret_cast<float2*>(p) = make_float2(re, im);
     } else {
-        *reinterpret_cast<uint32_t*>(p) = f32_to_bf16(re) | (f32_to_bf16(im) << 16);
+        *reinterpret_cast<uint32_t*>(p) = pack_bf16(re, im);
     }
 }
 
@@ -173,7 +173,7 @@ __device__ __forceinline__ void bstore(__amdgpu_buffer_rsrc_t r, unsigned voff, 
         v.y = __float_as_uint(im);
         __builtin_amdgcn_raw_buffer_store_b64(v, r, voff, soff, 0);
     } else {
-        __builtin_amdgcn_raw_buffer_store_b32(f32_to_bf16(re) | (f32_to_bf16(im) << 16), r, voff, soff, 0);
+        __builtin_amdgcn_raw_buffer_store_b32(pack_bf16(re, im), r, voff, soff, 0);
     }
 }
 
@@ -258,10 +258,10 @@ __device__ __forceinline__ void store4(void* base, long g, long site, long Vhp,
     constexpr int P = fpack<S>();
     if constexpr (P == 4) {
         uint4 w;
-        w.x = f32_to_bf16(v[0]) | (f32_to_bf16(v[1]) << 16);
-        w.y = f32_to_bf16(v[2]) | (f32_to_bf16(v[3]) << 16);
-        w.z = f32_to_bf16(v[4]) | (f32_to_bf16(v[5]) << 16);
-        w.w = f32_to_bf16(v[6]) | (f32_to_bf16(v[7]) << 16);
+        w.x = pack_bf16(v[0], v[1]);
+        w.y = pack_bf16(v[2], v[3]);
+        w.z = pack_bf16(v[4], v[5]);
+        w.w = pack_bf16(v[6], v[7]);
         reinterpret_cast<uint4*>(base)[g * Vhp + site] = w;
     } else if constexpr (P == 2 && sizeof(S) == 4) {
 #pragma unroll
