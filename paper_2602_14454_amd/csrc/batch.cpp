@@ -29,6 +29,7 @@
 #include <mutex>
 #include <sstream>
 #include <string>
+#include <utility>
 #include <vector>
 
 #include "slot_blas.h"
@@ -608,11 +609,12 @@ int solve_batch(int n, const dwf_op* const* ops, void* const* x5, const void* co
         for (const Item& it : B.items)
             axpby(ST_F64, I->kx, at(xe.p, it.off), static_cast<char*>(I->x.p) + complex_bytes_of(I->kx) * it.off,
                   it.n1 * it.nrhs, nullptr, 1.0, nullptr, 1.0, nullptr, cs.s, it.op->lat->Vhp);
-        // r^ = b~ - D^ x^, 5D residual |M r^| / |b5|
+        // r^ = b~ - D^ x^ formed where D^ x^ was written (the buffers then
+        // trade names), 5D residual |M r^| / |b5|
         for (const Item& it : B.items)
             apply_dhat(it.op, ST_F64, 0, at(te.p, it.off), at(xe.p, it.off), at(to.p, it.off), nullptr, it.nrhs, cs.s);
-        convert(ST_F64, ST_F64, rh.p, bt.p, N, cs.s);
-        axpby(ST_F64, ST_F64, rh.p, te.p, N, nullptr, -1.0, nullptr, 1.0, nullptr, cs.s);
+        axpby(ST_F64, ST_F64, te.p, bt.p, N, nullptr, 1.0, nullptr, -1.0, nullptr, cs.s);
+        std::swap(rh, te);
         for (const Item& it : B.items)
             mix(it.op, ST_F64, at(rh.p, it.off), at(te.p, it.off), MAT_M, nullptr, it.nrhs, cs.s);
         slot_norms(ST_F64, te.p, t2);

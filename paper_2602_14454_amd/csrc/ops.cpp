@@ -84,6 +84,7 @@ void mix(const dwf_op* op, int kind, const void* in, void* out, int slot, double
 }
 
 int hop_partials(const dwf_op* op, int nrhs) { return hop_grid_blocks(op->lat->Vh) * nrhs; }
+int mix_partials(const dwf_op* op, int nrhs) { return mix_grid_blocks(op->lat->Vh) * nrhs; }
 
 void apply_dhat(const dwf_op* op, int kind, int dagger, void* out_e, const void* in_e, void* tmp_o,
                 void* tmp_e, int nrhs, hipStream_t st) {

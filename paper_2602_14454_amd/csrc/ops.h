@@ -24,6 +24,7 @@ void hop(const dwf_op* op, int kind, int out_parity, const void* in, const void*
 void mix(const dwf_op* op, int kind, const void* in, void* out, int slot, double* partial, int nrhs,
          hipStream_t st);
 int hop_partials(const dwf_op* op, int nrhs);
+int mix_partials(const dwf_op* op, int nrhs);
 
 void apply_dhat(const dwf_op* op, int kind, int dagger, void* out_e, const void* in_e, void* tmp_o,
                 void* tmp_e, int nrhs, hipStream_t st);

@@ -14,6 +14,7 @@
 #include <cmath>
 #include <cstring>
 #include <memory>
+#include <utility>
 
 #include "blas.h"
 #include "fgcr.h"
@@ -384,13 +385,17 @@ int solve(const dwf_op* op, void* x5, const void* b5, const dwf_solve_params* pr
         ++outer;
         if (nan_seen) break;
         axpby(ST_F64, kx, xe.p, xin, n, nullptr, 1.0, nullptr, 1.0, nullptr, st, Vhp);
-        // rh = b~ - D^ xe (FP64); r5_e = -M rh, r5_o = 0 exactly after reconstruction
-        apply_dhat(op, ST_F64, 0, te.p, xe.p, to.p, rh.p, 1, st);
-        convert(ST_F64, ST_F64, rh.p, bt.p, n, st);
-        axpby(ST_F64, ST_F64, rh.p, te.p, n, nullptr, -1.0, nullptr, 1.0, nullptr, st);
-        mix(op, ST_F64, rh.p, te.p, MAT_M, nullptr, 1, st);
+        // r^ = b~ - D^ xe (FP64), formed where D^ xe was written; the buffers
+        // then trade names so that rh holds r^.  r5_e = -M r^ with |M r^|^2
+        // reduced by the mix itself; r5_o = 0 exactly after reconstruction.
+        apply_dhat(op, ST_F64, 0, te.p, xe.p, to.p, nullptr, 1, st);
+        axpby(ST_F64, ST_F64, te.p, bt.p, n, nullptr, 1.0, nullptr, -1.0, nullptr, st);
+        std::swap(rh, te);
+        mix(op, ST_F64, rh.p, te.p, MAT_M, pp, 1, st);
+        finalize(pp, mix_partials(op, 1), 1, sc + CG_TMP, 0, st);
+        read_scalars(sc, hs, st);
         const double rel5_old = rel5;
-        rel5 = std::sqrt(norm2_host(ST_F64, te.p, n, pp, sc, hs, st) / b2);
+        rel5 = std::sqrt(hs.h[CG_TMP] / b2);
         f_ratio = dc_ratio(rel5 / rel5_old, itol);
         if (trace_on())
             std::fprintf(stderr, "dwf trace: solve step %d prec %d requested %.3e iters %d rel5 %.3e\n", outer, kp,
