@@ -15,9 +15,10 @@
 // is skipped by every kernel.  The iteration body (k iterations) is
 // captured once into a HIP graph and replayed; the host reads the done
 // flags after each replay.  Within a replay the search directions go to a
-// ring of batch vectors and x is formed from them at the end of the ring
-// and of the replay, so x is not read or written in every iteration.  The FP64 outer steps use the per-operator
-// kernels with all right-hand sides of an operator in one launch.
+// ring of batch vectors (at most 16, and at most 8 GiB) and x is formed from
+// them at the end of the ring and of the replay, so x is not read or written
+// in every iteration.  The FP64 outer steps use the per-operator kernels with
+// all right-hand sides of an operator in one launch.
 #include <algorithm>
 #include <cmath>
 #include <cstdio>
@@ -360,8 +361,8 @@ struct Inner {
     }
 };
 
-// ring length for a check period of k iterations
-int ring_length(int k) { return std::min(k, 16); }
+// ring length for a check period of k iterations and ring slots of bp bytes
+int ring_length(int k, size_t bp) { return std::min(k, ring_slots(bp)); }
 
 // iteration q (0-based) of a check period of k iterations, over every slot
 void iteration(const Batch& B, Inner& I, int q, int k, hipStream_t st) {
@@ -490,7 +491,7 @@ int solve_batch(int n, const dwf_op* const* ops, void* const* x5, const void* co
         if (prm->inner_tol > 0 && k == kp) return prm->inner_tol;
         return k == ST_F64 ? tol : (k == ST_F32 ? 1e-5 : 3e-2);
     };
-    const int ring = ring_length(check_every);
+    const int ring = ring_length(check_every, complex_bytes_of(kp) * (size_t)B.N);
     std::unique_ptr<Inner> I(new Inner(B, kp == ST_F64 ? ST_F64 : ST_F32, kp, ring));
     const int ns = B.nslots;
     PinnedD hs((size_t)ns * CG_NSLOTS);

@@ -8,6 +8,7 @@
 // iterations to test convergence.
 #include "solver.h"
 
+#include <algorithm>
 #include <chrono>
 #include <cstdio>
 #include <cstdlib>
@@ -30,6 +31,12 @@ Pinned::Pinned(size_t n) {
 }
 Pinned::~Pinned() {
     if (h) (void)hipHostFree(h);
+}
+
+int ring_slots(size_t slot_bytes) {
+    const size_t cap = size_t(8) << 30;
+    const size_t fit = slot_bytes > 0 ? cap / slot_bytes : 16;
+    return (int)std::max<size_t>(2, std::min<size_t>(16, fit));
 }
 
 static void read_scalars(const double* dev, Pinned& host, hipStream_t st) {
@@ -59,14 +66,15 @@ int cgnr(const dwf_op* op, CgWork& W, const void* b_kp, double tol_rel, int maxi
     Pinned& hs = W.hs;
     if (check_every < 1) check_every = 1;
     DWF_HIP(hipMemsetAsync(W.scal.p, 0, CG_NSLOTS * sizeof(double), st));
-    // p lives in a ring of kRing slots unless the caller wants x after every
-    // iteration (on_iter)
+    // p lives in a ring of W.ring_len slots unless the caller wants x after
+    // every iteration (on_iter)
     const bool ring = !on_iter;
     const long Vhp = op->lat->Vhp;
     const size_t pbytes = complex_bytes_of(W.kp) * (size_t)n;
     if (ring && !W.ring.p) {
-        W.ring.alloc(pbytes * CgWork::kRing);
-        W.alphas.alloc(sizeof(double) * CgWork::kRing);
+        W.ring_len = ring_slots(pbytes);
+        W.ring.alloc(pbytes * W.ring_len);
+        W.alphas.alloc(sizeof(double) * W.ring_len);
     }
     auto slot = [&](int i) -> void* { return static_cast<char*>(W.ring.p) + (size_t)i * pbytes; };
     // r = D^dag b, p = r, x = 0
@@ -99,7 +107,7 @@ int cgnr(const dwf_op* op, CgWork& W, const void* b_kp, double tol_rel, int maxi
             // into x first (x += alpha_i p_i in order, as the per-iteration update)
             ++pend;
             int nxt = cur + 1;
-            if (nxt == CgWork::kRing) {
+            if (nxt == W.ring_len) {
                 cg_accumulate_x(W.kx, W.kp, W.x.p, W.ring.p, alphas, pend, n, st, Vhp);
                 pend = 0;
                 nxt = 0;

@@ -25,12 +25,16 @@ struct CgWork {
     DevBuf x, r, p, t, v, w, partial, scal;
     Pinned hs;
     // search directions of the last iterations and their alphas: x is formed
-    // from them every kRing iterations and at the end of a solve instead of
+    // from them every ring_len iterations and at the end of a solve instead of
     // being read and written by every iteration
-    static constexpr int kRing = 16;
+    int ring_len = 0;
     DevBuf ring, alphas;
     CgWork(const dwf_op* op, int kx, int kp, int nrhs);
 };
+
+// Slots of a direction ring whose slots hold slot_bytes each: up to 16, as
+// many as fit in 8 GiB, at least 2 (a shorter ring only folds into x more often).
+int ring_slots(size_t slot_bytes);
 
 // CG on D^dag D^ e = D^dag b from e = 0; b in storage kp.  Stops when the
 // recursive residual |r| <= tol_rel |r0| or after maxiter iterations.
