@@ -49,8 +49,7 @@ CgWork::CgWork(const dwf_op* op, int kx_, int kp_, int nrhs_) : kx(kx_), kp(kp_)
     const size_t bx = complex_bytes_of(kx) * n, bp = complex_bytes_of(kp) * n;
     x.alloc(bx);
     r.alloc(bx);
-    p.alloc(bp);
-    t.alloc(bp);
+    t.alloc(bp);   // p: on first use by a solve without the direction ring
     v.alloc(bp);
     w.alloc(bp);
     const long np = std::max<long>(hop_partials(op, nrhs), blas_grid(n)) * 2 + 16;
@@ -76,6 +75,7 @@ int cgnr(const dwf_op* op, CgWork& W, const void* b_kp, double tol_rel, int maxi
         W.ring.alloc(pbytes * W.ring_len);
         W.alphas.alloc(sizeof(double) * W.ring_len);
     }
+    if (!ring && !W.p.p) W.p.alloc(pbytes);
     auto slot = [&](int i) -> void* { return static_cast<char*>(W.ring.p) + (size_t)i * pbytes; };
     // r = D^dag b, p = r, x = 0
     apply_dhat(op, W.kp, 1, W.w.p, b_kp, W.t.p, W.v.p, W.nrhs, st);
@@ -165,6 +165,7 @@ static int cgnr_reliable(const dwf_op* op, CgWork& W, void* xe, const void* bt, 
     if (check_every < 1) check_every = 1;
     *nupdates = 0;
     *nan_seen = false;
+    if (!W.p.p) W.p.alloc(complex_bytes_of(W.kp) * (size_t)n);
     DWF_HIP(hipMemsetAsync(W.scal.p, 0, CG_NSLOTS * sizeof(double), st));
     // r^ = b~ (x_hi = 0), r = D^dag r^
     convert(ST_F64, ST_F64, rh, bt, n, st);
