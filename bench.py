@@ -346,6 +346,68 @@ def run_learned(args):
     print(json.dumps(out))
 
 
+def run_alpha_scan(args):
+    """Paper-mode FP32 CGNR iteration counts (the paper's single-precision
+    stopping rule) and FP64 CGNR iterations and times to a 1e-10 true 5D
+    residual against alpha, for the Shamir kernel and two Mobius (b, c)
+    choices, on the 16^3x32, Ls = 16 lattice (Sec. 3, the iteration-count
+    study against alpha).  x4 must not depend on alpha (Sec. 2.3): its
+    deviation from the alpha = 1 solution of the same (b, c) is recorded."""
+    import numpy as np
+    import torch
+
+    import dwfgen
+    import paper_2602_14454_amd as dwf
+
+    dev = "cuda:0"
+    cfg = dict(CONFIGS[args.config])
+    dims, Ls = cfg["dims"], cfg["Ls"]
+    V = int(np.prod(dims))
+    U = dwfgen.make_links(dims, cfg["eps"], cfg["seed"], rho=cfg["rho"], nsmear=cfg["nsmear"])
+    plaq = dwfgen.plaquette(U, dims)
+    b4 = torch.from_numpy(dwfgen.gaussian_source_4d(dims, cfg["src_seed"])).to(dev)
+    lat = dwf.Lattice(dims)
+    lat.set_gauge(U)
+    b5 = torch.empty((Ls, V, 4, 3), dtype=torch.complex128, device=dev)
+    x5 = torch.zeros_like(b5)
+    x4 = torch.empty((V, 4, 3), dtype=torch.complex128, device=dev)
+    pp = dwf.default_params(check_every=8, paper_mode=1, inner_prec=dwf.F32)
+    p64 = dwf.default_params(tol=1e-10, check_every=8)
+    alphas = (1.0, 0.9, 0.8, 0.7, 0.6, 0.5, 0.4, 0.3)
+    rows = []
+    for b, c in ((1.0, 0.0), (1.5, 0.5), (1.0, 1.0)):
+        x4_ref = None
+        for al in alphas:
+            op = dwf.Op(lat, Ls, cfg["M0"], cfg["m"], b, c, al)
+            op.source_4d(b5, b4)
+            x5.zero_()
+            st_p, info_p = op.solve(x5, b5, pp)
+            op.source_4d(b5, b4)
+            x5.zero_()
+            torch.cuda.synchronize()
+            t = time.perf_counter()
+            st, info = op.solve(x5, b5, p64)
+            op.project_4d(x4, x5)
+            torch.cuda.synchronize()
+            dt = time.perf_counter() - t
+            if x4_ref is None:
+                x4_ref = x4.clone()
+            dx4 = (torch.linalg.vector_norm(x4 - x4_ref) / torch.linalg.vector_norm(x4_ref)).item()
+            row = {"b": b, "c": c, "alpha": al, "paper_mode_f32_iters": info_p.iters,
+                   "fp64_cgnr_iters": info.iters, "fp64_cgnr_seconds": dt, "true_res5": info.true_res5,
+                   "res4": op.residual_4d(x4, b4), "x4_rel_dev_vs_alpha1": dx4, "status": st}
+            rows.append(row)
+            log(f"(b,c)=({b},{c}) alpha {al}: paper-mode FP32 {info_p.iters} iters, FP64 {info.iters} iters "
+                f"{dt:.3f}s, |dx4|/|x4| {dx4:.1e}")
+            del op
+    out = {"metric": "CGNR iterations against alpha (paper-mode FP32 and FP64 to 1e-10 true 5D residual)",
+           "data": "synthetic", "n_gpus": 1,
+           "config": {"workload": workload_name(cfg), "lattice": list(dims), "Ls": Ls, "M0": cfg["M0"],
+                      "m": cfg["m"], "plaquette": plaq},
+           "rows": rows}
+    print(json.dumps(out))
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -365,6 +427,8 @@ def main():
                     help="run the learned-preconditioner workload instead: train on 32 fields, FGCR on held-out ones")
     ap.add_argument("--train-fields", type=int, default=32)
     ap.add_argument("--train-steps", type=int, default=1500)
+    ap.add_argument("--alpha-scan", action="store_true",
+                    help="run the alpha scan instead: iteration counts against alpha for three (b, c) choices")
     ap.add_argument("--spectrum", action="store_true",
                     help="also measure lambda_min, lambda_max and kappa of D^dag D^ (Lanczos) for alpha and 1")
     args = ap.parse_args()
@@ -385,6 +449,9 @@ def main():
         return
     if args.learned:
         run_learned(args)
+        return
+    if args.alpha_scan:
+        run_alpha_scan(args)
         return
     dev = "cuda:0"
     cfg = dict(CONFIGS[args.config])
