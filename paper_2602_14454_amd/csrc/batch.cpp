@@ -11,8 +11,9 @@
 // launch.  The four fused hops of D^dag D^ run as work-list launches (one per
 // class of ceil(Ls/4)), the CG vector updates and reductions as slot-table
 // launches, and each slot carries its own alpha, beta, stopping threshold,
-// iteration count and done flag on the device.  A slot that has converged
-// is skipped by every kernel.  The iteration body (k iterations) is
+// iteration count and done flag on the device; like the single solve, a slot
+// tests its residual at multiples of the check period.  A slot that has
+// converged is skipped by every kernel.  The iteration body (k iterations) is
 // captured once into a HIP graph and replayed; the host reads the done
 // flags after each replay.  Within a replay the search directions go to a
 // ring of batch vectors (at most 16, and at most 8 GiB) and x is formed from
@@ -375,7 +376,7 @@ void iteration(const Batch& B, Inner& I, int q, int k, hipStream_t st) {
     bfinalize(pp, B.pstride, sd, B.nslots, sc, 1, 1, nullptr, st, I.alph.as<double>() + pos, I.ring);
     I.hops.stage(2, pos, st);
     I.hops.stage(3, pos, st);   // r -= alpha D^dag D^ p, |r|^2 partials per hop tile
-    bfinalize(pp, B.pstride, sd, B.nslots, sc, 2, 1, nullptr, st);
+    bfinalize(pp, B.pstride, sd, B.nslots, sc, 2, 1, nullptr, st, nullptr, 0, k);
     // the next direction starts a new ring when this one fills it or the period ends:
     // x takes the ring's directions first
     const int next = q + 1 == k ? 0 : (pos + 1) % I.ring;

@@ -49,9 +49,12 @@ void bcg_accx(int kx, int kp, void* x, const void* ring, long N, const double* a
 //  mode 1: QQ = sum; ALPHA = RR / QQ; alpha_out[v * astride] = ALPHA
 //          (done slots: alpha_out[v * astride] = 0 and nothing else)
 //  mode 2: RRNEW = sum; BETA = sum / RR; RROLD = RR; RR = sum; ITERS += 1;
-//          sum <= STOP: DONE = 1; non-finite: NANFLAG = DONE = 1
+//          sum <= STOP with ITERS a multiple of check_every: DONE = 1 (the
+//          single solve's rule, which tests every check_every iterations);
+//          non-finite: NANFLAG = DONE = 1
 //  mode 4: TMP = sum (any slot, done or not)
 void bfinalize(const double* partial, long pstride, const SlotDesc* slots, int nslots, double* scal, int mode,
-               int from_hop, const double* tol2, hipStream_t st, double* alpha_out = nullptr, int astride = 0);
+               int from_hop, const double* tol2, hipStream_t st, double* alpha_out = nullptr, int astride = 0,
+               int check_every = 1);
 
 }  // namespace dwf

@@ -138,7 +138,7 @@ __global__ __launch_bounds__(BT) void bcg_accx_kernel(void* x, const void* ring,
 __global__ __launch_bounds__(BT) void bfinalize_kernel(const double* partial, long pstride,
                                                        const SlotDesc* __restrict__ slots, double* scal, int mode,
                                                        int from_hop, const double* tol2, double* alpha_out,
-                                                       int astride) {
+                                                       int astride, int check_every) {
     __shared__ double red[BT];
     const int v = blockIdx.x;
     const SlotDesc d = slots[v];
@@ -180,8 +180,9 @@ __global__ __launch_bounds__(BT) void bfinalize_kernel(const double* partial, lo
         sv[CG_RROLD] = sv[CG_RR];
         sv[CG_RR] = sum;
         sv[CG_ITERS] += 1.0;
+        const long it = (long)sv[CG_ITERS];
         if (!fin) { sv[CG_NANFLAG] = 1.0; sv[CG_DONE] = 1.0; }
-        else if (sum <= sv[CG_STOP]) sv[CG_DONE] = 1.0;
+        else if (sum <= sv[CG_STOP] && it % check_every == 0) sv[CG_DONE] = 1.0;
     } else {
         sv[CG_TMP] = sum;
         if (!fin) sv[CG_NANFLAG] = 1.0;
@@ -259,9 +260,11 @@ void bcg_accx(int kx, int kp, void* x, const void* ring, long N, const double* a
 }
 
 void bfinalize(const double* partial, long pstride, const SlotDesc* slots, int nslots, double* scal, int mode,
-               int from_hop, const double* tol2, hipStream_t st, double* alpha_out, int astride) {
+               int from_hop, const double* tol2, hipStream_t st, double* alpha_out, int astride,
+               int check_every) {
+    DWF_REQUIRE(check_every >= 1, DWF_EINVAL, "check period must be >= 1");
     hipLaunchKernelGGL(bfinalize_kernel, dim3(nslots), dim3(BT), 0, st, partial, pstride, slots, scal, mode,
-                       from_hop, tol2, alpha_out, astride);
+                       from_hop, tol2, alpha_out, astride, check_every);
     DWF_HIP(hipGetLastError());
 }
 
