@@ -255,8 +255,9 @@ double dc_ratio(double achieved, double requested) {
 namespace {
 // Workspace of dwf_solve, kept by the operator between solves: allocation and
 // release of ~10 full-size vectors per solve cost milliseconds of host time.
-// Every buffer keeps one role and layout, so its zero padding (never written
-// by a kernel) stays valid; a solve that ends in an error drops the workspace.
+// Every buffer keeps one layout (rh and te, both FP64 half fields, trade
+// roles between outer steps), so its zero padding (never written by a
+// kernel) stays valid; a solve that ends in an error drops the workspace.
 struct SolveWs {
     long n = 0;
     DevBuf be, bo, bt, xe, xo, rh, te, to, rin, partial, scal;
