@@ -78,6 +78,15 @@ def test_twelve_point_sources(prec):
     op.solve(xs, b5[5], dwf.default_params(tol=1e-12, check_every=4))
     rel = (torch.linalg.vector_norm(x5[5] - xs) / torch.linalg.vector_norm(xs)).item()
     assert rel < 1e-7
+    # and a batched slot takes no more inner iterations than the single-solve
+    # defect correction with the same parameters (both test convergence at
+    # multiples of the check period; rounding may move a test by one period
+    # per outer step)
+    xs.zero_()
+    st1, f1 = op.solve(xs, b5[5], prm)
+    assert st1 == 0
+    slack = 4 * max(f1.outer_iters, infos[5].outer_iters)
+    assert infos[5].iters <= f1.iters + slack, (infos[5].iters, f1.iters)
 
 
 UNEVEN = [
