@@ -551,95 +551,140 @@ int solve_batch(int n, const dwf_op* const* ops, void* const* x5, const void* co
 
     std::vector<int> iters(ns, 0), outer(ns, 0);
     std::vector<double> inner_rel(ns, 0.0);
-    int fallback = 0, total_rounds = 0;
+    int fallback = 0;
     bool nan_seen = false;
-    while (total_rounds < 100) {
-        if (std::all_of(odone.begin(), odone.end(), [](int d) { return d != 0; })) break;
-        int max_it = 0;
-        for (int v = 0; v < ns; ++v) if (!odone[v]) max_it = std::max(max_it, iters[v]);
-        if (max_it >= maxiter) break;
-        ++total_rounds;
-        // inner start: r = D^dag r^ (FP64, then stored in kx), p = r, x = 0
-        for (const Item& it : B.items)
+    // Items run their defect-correction steps independently: after each
+    // replay, an item whose slots are all done takes its FP64 outer step at
+    // once and restarts its inner solve, while the others keep iterating.
+    // Item state: 0 idle (inner start due), 1 inner solve running, 2 finished.
+    const int nitems = (int)B.items.size();
+    std::vector<int> state(nitems, 0), finished0;
+    for (int i = 0; i < nitems; ++i) {
+        bool all = true;
+        for (int v = B.items[i].slot0; v < B.items[i].slot0 + B.items[i].nrhs; ++v) all = all && odone[v] != 0;
+        if (all) {
+            state[i] = 2;
+            finished0.push_back(i);
+        }
+    }
+    // te is reduced per slot after every outer step, also where no item
+    // has written it yet: it starts at zero
+    DWF_HIP(hipMemsetAsync(te.p, 0, b64, cs.s));
+    auto xat = [&](const Item& it) { return static_cast<char*>(I->x.p) + complex_bytes_of(I->kx) * it.off; };
+    auto rat = [&](const Item& it) { return static_cast<char*>(I->r.p) + complex_bytes_of(I->kx) * it.off; };
+    // inner starts of the items in `start` (r = D^dag r^ in FP64, then stored
+    // in kx; p = r; x = 0) and retirement of the items in `retire`; every
+    // other slot keeps its state (target 0 to the mode-0 finalize)
+    auto restart = [&](const std::vector<int>& start, const std::vector<int>& retire) {
+        for (int v = 0; v < ns; ++v) itol2_h.h[v] = 0.0;
+        const double itol = inner_tol_of(I->kp);
+        for (int i : start) {
+            const Item& it = B.items[i];
             apply_dhat(it.op, ST_F64, 1, at(te.p, it.off), at(rh.p, it.off), at(to.p, it.off), at(tmp.p, it.off),
                        it.nrhs, cs.s);
-        for (const Item& it : B.items)   // per operator: the layout change needs its row stride
-            convert(I->kx, ST_F64, static_cast<char*>(I->r.p) + complex_bytes_of(I->kx) * it.off, at(te.p, it.off),
+            convert(I->kx, ST_F64, rat(it), at(te.p, it.off), it.n1 * it.nrhs, cs.s, it.op->lat->Vhp);
+            convert(I->kp, I->kx, static_cast<char*>(I->pslot(0)) + complex_bytes_of(I->kp) * it.off, rat(it),
                     it.n1 * it.nrhs, cs.s, it.op->lat->Vhp);
-        for (const Item& it : B.items)
-            convert(I->kp, I->kx, static_cast<char*>(I->pslot(0)) + complex_bytes_of(I->kp) * it.off,
-                    static_cast<char*>(I->r.p) + complex_bytes_of(I->kx) * it.off, it.n1 * it.nrhs, cs.s,
-                    it.op->lat->Vhp);
-        DWF_HIP(hipMemsetAsync(I->x.p, 0, complex_bytes_of(I->kx) * N, cs.s));
-        const double itol = inner_tol_of(I->kp);
-        for (int v = 0; v < ns; ++v) {
-            const bool plain = I->kp == ST_F64 && outer[v] == 0;
-            req[v] = plain ? itol : dc_target(tol, rel5[v], I->kp, itol, fr[v]);
-            itol2_h.h[v] = odone[v] ? -1.0 : req[v] * req[v];
+            DWF_HIP(hipMemsetAsync(xat(it), 0, complex_bytes_of(I->kx) * it.n1 * it.nrhs, cs.s));
+            for (int v = it.slot0; v < it.slot0 + it.nrhs; ++v) {
+                const bool plain = I->kp == ST_F64 && outer[v] == 0;
+                req[v] = plain ? itol : dc_target(tol, rel5[v], I->kp, itol, fr[v]);
+                itol2_h.h[v] = odone[v] ? -1.0 : req[v] * req[v];
+            }
+            state[i] = 1;
         }
+        for (int i : retire)
+            for (int v = B.items[i].slot0; v < B.items[i].slot0 + B.items[i].nrhs; ++v) itol2_h.h[v] = -1.0;
         DWF_HIP(hipMemcpyAsync(B.inner_tol2.p, itol2_h.h, sizeof(double) * ns, hipMemcpyHostToDevice, cs.s));
         bnorm2(I->kx, I->r.p, sd, ns, B.vblocks, pp, B.pstride, sc, cs.s);
         bfinalize(pp, B.pstride, sd, ns, sc, 0, 0, B.inner_tol2.as<double>(), cs.s);
-        // inner iterations: graph replays of check_every iterations
-        const bool use_graph = prm->use_graph != 0;
+    };
+    auto idle_items = [&]() {
+        std::vector<int> v;
+        for (int i = 0; i < nitems; ++i) if (state[i] == 0) v.push_back(i);
+        return v;
+    };
+    const bool use_graph = prm->use_graph != 0;
+    restart(idle_items(), finished0);
+    bool want_fallback = false;
+    for (;;) {
+        if (std::none_of(state.begin(), state.end(), [](int q) { return q == 1; })) break;
         if (use_graph && I->graph_k != check_every) capture(B, *I, check_every, cs.s);
-        int done_iters = 0;
-        const int budget = maxiter - max_it;
-        while (done_iters < budget) {
-            if (use_graph) DWF_HIP(hipGraphLaunch(I->graph.x, cs.s));
-            else
-                for (int q = 0; q < check_every; ++q) iteration(B, *I, q, check_every, cs.s);
-            done_iters += check_every;
-            read_scal();
-            bool all = true;
-            for (int v = 0; v < ns; ++v) {
+        if (use_graph) DWF_HIP(hipGraphLaunch(I->graph.x, cs.s));
+        else
+            for (int q = 0; q < check_every; ++q) iteration(B, *I, q, check_every, cs.s);
+        read_scal();
+        std::vector<int> ready;
+        for (int i = 0; i < nitems; ++i) {
+            if (state[i] != 1) continue;
+            bool all = true, over = false;
+            for (int v = B.items[i].slot0; v < B.items[i].slot0 + B.items[i].nrhs; ++v) {
                 const double* s = hs.h + (size_t)v * CG_NSLOTS;
                 if (s[CG_NANFLAG] != 0.0) nan_seen = true;
                 if (s[CG_DONE] == 0.0) all = false;
+                if (!odone[v] && iters[v] + (int)s[CG_ITERS] >= maxiter) over = true;
             }
-            if (all || nan_seen) break;
-        }
-        for (int v = 0; v < ns; ++v) {
-            const double* s = hs.h + (size_t)v * CG_NSLOTS;
-            if (odone[v]) continue;
-            iters[v] += (int)s[CG_ITERS];
-            outer[v] += 1;
-            inner_rel[v] = s[CG_RR0] > 0 ? std::sqrt(s[CG_RR] / s[CG_RR0]) : 0.0;
+            // x is whole after every replay, so an item over its iteration
+            // budget takes its outer step too
+            if (all || over) ready.push_back(i);
         }
         if (nan_seen) break;
-        // x^ += x (slots that were already done add their zero correction)
-        for (const Item& it : B.items)
-            axpby(ST_F64, I->kx, at(xe.p, it.off), static_cast<char*>(I->x.p) + complex_bytes_of(I->kx) * it.off,
-                  it.n1 * it.nrhs, nullptr, 1.0, nullptr, 1.0, nullptr, cs.s, it.op->lat->Vhp);
-        // r^ = b~ - D^ x^ formed where D^ x^ was written (the buffers then
-        // trade names), 5D residual |M r^| / |b5|
-        for (const Item& it : B.items)
-            apply_dhat(it.op, ST_F64, 0, at(te.p, it.off), at(xe.p, it.off), at(to.p, it.off), nullptr, it.nrhs, cs.s);
-        axpby(ST_F64, ST_F64, te.p, bt.p, N, nullptr, 1.0, nullptr, -1.0, nullptr, cs.s);
-        std::swap(rh, te);
-        for (const Item& it : B.items)
+        if (ready.empty()) continue;
+        for (int i : ready) {
+            const Item& it = B.items[i];
+            for (int v = it.slot0; v < it.slot0 + it.nrhs; ++v) {
+                const double* s = hs.h + (size_t)v * CG_NSLOTS;
+                if (odone[v]) continue;
+                iters[v] += (int)s[CG_ITERS];
+                outer[v] += 1;
+                inner_rel[v] = s[CG_RR0] > 0 ? std::sqrt(s[CG_RR] / s[CG_RR0]) : 0.0;
+            }
+            // x^ += x; r^ = b~ - D^ x^; 5D residual |M r^| / |b5|
+            axpby(ST_F64, I->kx, at(xe.p, it.off), xat(it), it.n1 * it.nrhs, nullptr, 1.0, nullptr, 1.0, nullptr,
+                  cs.s, it.op->lat->Vhp);
+            apply_dhat(it.op, ST_F64, 0, at(te.p, it.off), at(xe.p, it.off), at(to.p, it.off), nullptr, it.nrhs,
+                       cs.s);
+            convert(ST_F64, ST_F64, at(rh.p, it.off), at(bt.p, it.off), it.n1 * it.nrhs, cs.s);
+            axpby(ST_F64, ST_F64, at(rh.p, it.off), at(te.p, it.off), it.n1 * it.nrhs, nullptr, -1.0, nullptr, 1.0,
+                  nullptr, cs.s);
             mix(it.op, ST_F64, at(rh.p, it.off), at(te.p, it.off), MAT_M, nullptr, it.nrhs, cs.s);
-        slot_norms(ST_F64, te.p, t2);
-        bool stagnated = false;
-        for (int v = 0; v < ns; ++v) {
-            if (odone[v]) continue;
-            const double old5 = rel5[v];
-            rel5[v] = std::sqrt(t2[v] / b2[v]);
-            fr[v] = dc_ratio(rel5[v] / old5, req[v]);
-            if (trace_on())
-                std::fprintf(stderr, "dwf trace: batch step %d slot %d prec %d requested %.3e iters %d rel5 %.3e\n",
-                             total_rounds, v, I->kp, req[v], iters[v], rel5[v]);
-            if (rel5[v] <= tol) odone[v] = 1;
-            else if (rel5[v] > 0.5 * prev[v] && I->kp != ST_F64) stagnated = true;
-            prev[v] = rel5[v];
         }
-        if (stagnated) {
-            // step the inner storage up one precision for the rest of the batch
+        slot_norms(ST_F64, te.p, t2);   // all slots; only the ready items' are used
+        std::vector<int> retire;
+        for (int i : ready) {
+            const Item& it = B.items[i];
+            bool all_done = true, spent = false;
+            for (int v = it.slot0; v < it.slot0 + it.nrhs; ++v) {
+                if (odone[v]) continue;
+                const double old5 = rel5[v];
+                rel5[v] = std::sqrt(t2[v] / b2[v]);
+                fr[v] = dc_ratio(rel5[v] / old5, req[v]);
+                if (trace_on())
+                    std::fprintf(stderr,
+                                 "dwf trace: batch step %d slot %d prec %d requested %.3e iters %d rel5 %.3e\n",
+                                 outer[v], v, I->kp, req[v], iters[v], rel5[v]);
+                if (rel5[v] <= tol) odone[v] = 1;
+                else if (rel5[v] > 0.5 * prev[v] && I->kp != ST_F64) want_fallback = true;
+                prev[v] = rel5[v];
+                if (!odone[v]) all_done = false;
+                if (iters[v] >= maxiter || outer[v] >= 100) spent = true;
+            }
+            state[i] = (all_done || spent) ? 2 : 0;
+            if (state[i] == 2) retire.push_back(i);
+        }
+        std::vector<int> start;
+        if (!want_fallback) {
+            start = idle_items();
+        } else if (std::none_of(state.begin(), state.end(), [](int q) { return q == 1; })) {
+            // step the inner storage up one precision once no item is running
             const int nk = I->kp == ST_BF16 ? ST_F32 : ST_F64;
             I.reset(new Inner(B, nk == ST_F64 ? ST_F64 : ST_F32, nk, ring));
             I->build_hops(B, nrb, order);
             fallback = 1;
+            want_fallback = false;
+            start = idle_items();
         }
+        if (!start.empty() || !retire.empty()) restart(start, retire);
     }
     for (const Item& it : B.items) {
         const dwf_lattice* L = it.op->lat;

@@ -45,7 +45,9 @@ void bcg_accx(int kx, int kp, void* x, const void* ring, long N, const double* a
 // Per-slot reduction of the partials (count: nhop if from_hop, else nb) and
 // CG scalar update, one block per slot:
 //  mode 0: RR = RR0 = sum; STOP = tol2[v] * sum; ITERS = 0;
-//          DONE = (sum == 0 || tol2[v] < 0); NANFLAG = !finite(sum)
+//          DONE = (sum == 0); NANFLAG = !finite(sum); a slot with
+//          tol2[v] < 0 is retired (DONE = 1, RR = RR0 = STOP = ITERS =
+//          NANFLAG = 0, partials not read); one with tol2[v] == 0 is left as it is
 //  mode 1: QQ = sum; ALPHA = RR / QQ; alpha_out[v * astride] = ALPHA
 //          (done slots: alpha_out[v * astride] = 0 and nothing else)
 //  mode 2: RRNEW = sum; BETA = sum / RR; RROLD = RR; RR = sum; ITERS += 1;

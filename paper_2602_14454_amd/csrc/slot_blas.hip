@@ -147,6 +147,17 @@ __global__ __launch_bounds__(BT) void bfinalize_kernel(const double* partial, lo
         if (mode == 1 && alpha_out && threadIdx.x == 0) alpha_out[(long)v * astride] = 0.0;
         return;
     }
+    if (mode == 0 && tol2 && tol2[v] == 0.0) return;   // block-uniform: the slot keeps its state
+    if (mode == 0 && tol2 && tol2[v] < 0.0) {
+        // retired: done without reading its partials (its r may never have been written)
+        if (threadIdx.x == 0) {
+            sv[CG_RR] = sv[CG_RR0] = sv[CG_STOP] = 0.0;
+            sv[CG_ITERS] = 0.0;
+            sv[CG_NANFLAG] = 0.0;
+            sv[CG_DONE] = 1.0;
+        }
+        return;
+    }
     const int np = from_hop ? d.nhop : d.nb;
     const double* pp = partial + (long)v * pstride;
     double acc = 0.0;
