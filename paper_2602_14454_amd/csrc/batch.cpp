@@ -19,7 +19,9 @@
 // ring of batch vectors (at most 16, and at most 8 GiB) and x is formed from
 // them at the end of the ring and of the replay, so x is not read or written
 // in every iteration.  The FP64 outer steps use the per-operator kernels with
-// all right-hand sides of an operator in one launch.
+// all right-hand sides of an operator in one launch; each operator takes its
+// outer step as soon as all its right-hand sides are done, while the others
+// keep iterating.
 #include <algorithm>
 #include <cmath>
 #include <cstdio>
