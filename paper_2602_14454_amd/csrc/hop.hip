@@ -41,11 +41,16 @@ namespace dwf {
 // groups), unrolling of the direction loop, and whether the 8 neighbour
 // indices are loaded up front.  Defaults are the best of sweeps on MI355X
 // (16^3x32, Ls = 16): with one slice group per wave and no unrolling of the
-// direction loop the FP32/BF16 kernels need ~122 VGPRs (4 waves per SIMD, no
-// spills); unrolling lets the compiler hoist the loads of several directions
-// and spill.
+// direction loop the FP32/BF16 kernels fit in 96 / 88 VGPRs at 5 waves per
+// SIMD without spills (FP32 hop 75 -> 73 us against 4 waves, BF16 unchanged);
+// unrolling lets the compiler hoist the loads of several directions and
+// spill.  The work-list kernel that loops over several right-hand sides
+// keeps 4 waves (it spills already there).
 #ifndef DWF_HOP_WAVES_PER_EU
-#define DWF_HOP_WAVES_PER_EU 4
+#define DWF_HOP_WAVES_PER_EU 5
+#endif
+#ifndef DWF_HOP_BATCHN_WPE
+#define DWF_HOP_BATCHN_WPE 4
 #endif
 #ifndef DWF_HOP_WAVES_PER_EU64
 #define DWF_HOP_WAVES_PER_EU64 2
@@ -787,7 +792,7 @@ void hop_mfma_kernel(HopParams P) {
 // (its partial is written as 0).
 template <class S, int KK>
 __global__ __launch_bounds__(256)
-__attribute__((amdgpu_waves_per_eu(sizeof(S) == 8 ? DWF_HOP_WAVES_PER_EU64 : DWF_HOP_WAVES_PER_EU)))
+__attribute__((amdgpu_waves_per_eu(sizeof(S) == 8 ? DWF_HOP_WAVES_PER_EU64 : DWF_HOP_BATCHN_WPE)))
 void hop_batch_kernel(const HopParams* __restrict__ items, const int* __restrict__ meta, int nitems, int nrb,
                       int order) {
     extern __shared__ u32x4 hop_smem[];
