@@ -194,3 +194,29 @@ def test_batch_rejects_bad_arguments():
         dwf.solve_batch([op], [x], [x], [0])
     with pytest.raises(dwf.DwfError):
         dwf.solve_batch([op], [x], [x], [1], dwf.default_params(algo=dwf.ALGO_MIXED))
+
+
+def test_batch_nan_source_reports_enan():
+    """A NaN in one right-hand side of a batch stops the batch with DWF_ENAN
+    (the other operator of the batch is still iterating when it is seen),
+    and a later batch on the same operators solves normally."""
+    import torch
+    import paper_2602_14454_amd as dwf
+    objs = _ops(UNEVEN[:2], seed0=700)
+    bs, xs = [], []
+    for k, (case, U, lat, op) in enumerate(objs):
+        dims, Ls = case[0], case[1]
+        b = np.stack([dwfgen.gaussian_source_5d(dims, Ls, 40 + k)])
+        if k == 1:
+            b[0, 2, 1, 0, 0] = np.nan
+        bs.append(_dev(b))
+        xs.append(torch.zeros_like(bs[-1]))
+    ops = [o[3] for o in objs]
+    prm = dwf.default_params(algo=dwf.ALGO_DC, inner_prec=dwf.F32, check_every=4, tol=1e-10)
+    with pytest.raises(dwf.DwfError) as e:
+        dwf.solve_batch(ops, xs, bs, [1, 1], prm)
+    assert e.value.status == -6
+    bs[1] = _dev(np.stack([dwfgen.gaussian_source_5d(objs[1][0][0], objs[1][0][1], 41)]))
+    xs = [torch.zeros_like(b) for b in bs]
+    st, infos = dwf.solve_batch(ops, xs, bs, [1, 1], prm)
+    assert st == 0 and all(f.converged for f in infos)
