@@ -220,3 +220,23 @@ def test_batch_nan_source_reports_enan():
     xs = [torch.zeros_like(b) for b in bs]
     st, infos = dwf.solve_batch(ops, xs, bs, [1, 1], prm)
     assert st == 0 and all(f.converged for f in infos)
+
+
+def test_batch_iteration_budget():
+    """With an iteration budget far below what the solves need, every slot
+    stops within one check period of the budget and the batch reports
+    DWF_NOT_CONVERGED (1) with finite, improved iterates."""
+    import torch
+    import paper_2602_14454_amd as dwf
+    objs = _ops(UNEVEN[:3], seed0=800)
+    bs = []
+    for k, (case, U, lat, op) in enumerate(objs):
+        dims, Ls = case[0], case[1]
+        bs.append(_dev(np.stack([dwfgen.gaussian_source_5d(dims, Ls, 60 + k)])))
+    xs = [torch.zeros_like(b) for b in bs]
+    prm = dwf.default_params(algo=dwf.ALGO_DC, inner_prec=dwf.F32, check_every=4, tol=1e-10, maxiter=12)
+    st, infos = dwf.solve_batch([o[3] for o in objs], xs, bs, [1, 1, 1], prm)
+    assert st == 1
+    for f, x in zip(infos, xs):
+        assert f.converged == 0 and 0 < f.iters <= 12 + 4
+        assert 0 < f.true_res5 < 1.0 and torch.isfinite(x).all()
