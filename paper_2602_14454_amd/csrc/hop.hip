@@ -67,6 +67,11 @@ namespace dwf {
 #ifndef DWF_HOP_NBR_PRELOAD
 #define DWF_HOP_NBR_PRELOAD 1
 #endif
+// Load the phase-2 MFMA A operands once per wave when all its components
+// share a chirality (see hop_tile).
+#ifndef DWF_HOP_COEF_HOIST
+#define DWF_HOP_COEF_HOIST 1
+#endif
 // Stage the block's links and neighbour indices in LDS once (all lanes of a
 // block need the same 16 sites' links; loaded per lane they would be fetched
 // by every slice group of every wave).
@@ -556,11 +561,12 @@ __device__ __forceinline__ void hop_tile(const HopParams& P, long tile, int rhs,
         return sxb + (unsigned)s * (12u / PK) * gb + (unsigned)(cp / PK) * gb + (unsigned)(cp % PK) * CB;
     };
     double nrm = 0.0;
-#pragma unroll
-    for (int q = 0; q < CPW; ++q) {
-        const int cp = w * CPW + q;
-        const int chi = cp >= 6 ? 1 : 0;
-        R ap[KK], al[KK], ap2[KK], al2[KK];
+    // A operands of one chirality.  When the components of a wave all have
+    // the same chirality (6 divisible by CPW) they are loaded once, before
+    // the component loop: per-lane loads are vector-memory instructions, and
+    // the compiler cannot see that the per-component loads repeat.
+    constexpr bool CHI_W = DWF_HOP_COEF_HOIST && (6 % CPW) == 0;
+    auto load_a = [&](int chi, R (&ap)[KK], R (&al)[KK], R (&ap2)[KK], R (&al2)[KK]) {
 #pragma unroll
         for (int kk = 0; kk < KK; ++kk) {
             const int idx = (chi * 16 + j) * 16 + 4 * kk + sc;
@@ -568,6 +574,25 @@ __device__ __forceinline__ void hop_tile(const HopParams& P, long tile, int rhs,
             al[kk] = dense_loc ? lmix[idx] : ((has_loc && !L::LOC && j == 4 * kk + sc) ? lscale : R(0));
             ap2[kk] = has_out2 ? post2[idx] : R(0);
             al2[kk] = (has_out2 && has_loc && !chain) ? lmix2[idx] : R(0);
+        }
+    };
+    R apw[KK], alw[KK], ap2w[KK], al2w[KK];
+    if constexpr (CHI_W) load_a(w * CPW >= 6 ? 1 : 0, apw, alw, ap2w, al2w);
+#pragma unroll
+    for (int q = 0; q < CPW; ++q) {
+        const int cp = w * CPW + q;
+        const int chi = cp >= 6 ? 1 : 0;
+        R ap[KK], al[KK], ap2[KK], al2[KK];
+        if constexpr (CHI_W) {
+#pragma unroll
+            for (int kk = 0; kk < KK; ++kk) {
+                ap[kk] = apw[kk];
+                al[kk] = alw[kk];
+                ap2[kk] = ap2w[kk];
+                al2[kk] = al2w[kk];
+            }
+        } else {
+            load_a(chi, ap, al, ap2, al2);
         }
         // local values in the B layout: slice 4 kk + sc of site j
         R lr[KK], li[KK];
