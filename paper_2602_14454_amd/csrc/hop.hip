@@ -67,10 +67,10 @@ namespace dwf {
 #ifndef DWF_HOP_NBR_PRELOAD
 #define DWF_HOP_NBR_PRELOAD 1
 #endif
-// Load the phase-2 MFMA A operands once per wave when all its components
-// share a chirality (see hop_tile).
+// Load the phase-2 MFMA A operands once per wave (see hop_tile): 1 when all
+// its components share a chirality, 2 also when they straddle the two.
 #ifndef DWF_HOP_COEF_HOIST
-#define DWF_HOP_COEF_HOIST 1
+#define DWF_HOP_COEF_HOIST 2
 #endif
 // Stage the block's links and neighbour indices in LDS once (all lanes of a
 // block need the same 16 sites' links; loaded per lane they would be fetched
@@ -561,11 +561,14 @@ __device__ __forceinline__ void hop_tile(const HopParams& P, long tile, int rhs,
         return sxb + (unsigned)s * (12u / PK) * gb + (unsigned)(cp / PK) * gb + (unsigned)(cp % PK) * CB;
     };
     double nrm = 0.0;
-    // A operands of one chirality.  When the components of a wave all have
-    // the same chirality (6 divisible by CPW) they are loaded once, before
-    // the component loop: per-lane loads are vector-memory instructions, and
-    // the compiler cannot see that the per-component loads repeat.
+    // A operands of one chirality, loaded once per wave before the component
+    // loop (per-lane loads are vector-memory instructions, and the compiler
+    // cannot see that the per-component loads repeat).  When the components
+    // of a wave all have the same chirality (6 divisible by CPW) one set is
+    // loaded; otherwise a wave whose components straddle the two chiralities
+    // loads a second set and each component selects its own.
     constexpr bool CHI_W = DWF_HOP_COEF_HOIST && (6 % CPW) == 0;
+    constexpr bool CHI_2 = DWF_HOP_COEF_HOIST >= 2 && !CHI_W;
     auto load_a = [&](int chi, R (&ap)[KK], R (&al)[KK], R (&ap2)[KK], R (&al2)[KK]) {
 #pragma unroll
         for (int kk = 0; kk < KK; ++kk) {
@@ -577,7 +580,23 @@ __device__ __forceinline__ void hop_tile(const HopParams& P, long tile, int rhs,
         }
     };
     R apw[KK], alw[KK], ap2w[KK], al2w[KK];
-    if constexpr (CHI_W) load_a(w * CPW >= 6 ? 1 : 0, apw, alw, ap2w, al2w);
+    R apv[KK], alv[KK], ap2v[KK], al2v[KK];
+    const int chi_a = w * CPW >= 6 ? 1 : 0;             // first component of the wave
+    const int chi_b = w * CPW + CPW - 1 >= 6 ? 1 : 0;   // last component of the wave
+    if constexpr (CHI_W || CHI_2) load_a(chi_a, apw, alw, ap2w, al2w);
+    if constexpr (CHI_2) {
+        if (chi_b != chi_a) {   // wave-uniform
+            load_a(chi_b, apv, alv, ap2v, al2v);
+        } else {
+#pragma unroll
+            for (int kk = 0; kk < KK; ++kk) {
+                apv[kk] = apw[kk];
+                alv[kk] = alw[kk];
+                ap2v[kk] = ap2w[kk];
+                al2v[kk] = al2w[kk];
+            }
+        }
+    }
 #pragma unroll
     for (int q = 0; q < CPW; ++q) {
         const int cp = w * CPW + q;
@@ -590,6 +609,15 @@ __device__ __forceinline__ void hop_tile(const HopParams& P, long tile, int rhs,
                 al[kk] = alw[kk];
                 ap2[kk] = ap2w[kk];
                 al2[kk] = al2w[kk];
+            }
+        } else if constexpr (CHI_2) {
+            const bool second = chi != chi_a;
+#pragma unroll
+            for (int kk = 0; kk < KK; ++kk) {
+                ap[kk] = second ? apv[kk] : apw[kk];
+                al[kk] = second ? alv[kk] : alw[kk];
+                ap2[kk] = second ? ap2v[kk] : ap2w[kk];
+                al2[kk] = second ? al2v[kk] : al2w[kk];
             }
         } else {
             load_a(chi, ap, al, ap2, al2);
