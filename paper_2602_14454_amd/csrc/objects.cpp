@@ -27,7 +27,8 @@ static uint16_t host_f32_to_bf16(float f) {
 // XCD's 4 MB L2) at the cost of re-reading brick faces.  Measured on MI355X
 // (fused hop, Ls = 16): on 16^3x32 bricks of 1024 sites per slice beat whole
 // slices (FP64 193 -> 185 us, FP32 84 -> 78 us); on 24^3x48 bricks of 4096
-// sites are best (FP32 479 us vs 519 us at 2048 and 546 us at 1024).  Default:
+// sites are best (FP32 479 us vs 519 us at 2048 and 546 us at 1024; larger
+// bricks are slower: 440 us vs 459 us at 8192 and 501 us for whole slices).  Default:
 // 1024 up to 16^3 spatial sites, 4096 above; DWF_BRICK_SITES overrides.
 static void choose_brick(const int dims[4], int b[3]) {
     b[0] = dims[0];
