@@ -104,6 +104,7 @@ def _load():
         "or_residual_4d": (ctypes.c_double, [P, vp, vp, vp, ctypes.c_double]),
         "or_true_residual": (ctypes.c_double, [P, vp, vp, vp]),
         "or_num_threads": (ctypes.c_int, []),
+        "or_set_num_threads": (None, [ctypes.c_int]),
     }
     for name, (res, args) in sig.items():
         f = getattr(lib, name)
@@ -124,6 +125,11 @@ def _c128(a) -> np.ndarray:
 
 def num_threads() -> int:
     return _load().or_num_threads()
+
+
+def set_num_threads(n: int) -> None:
+    """OpenMP threads used by later oracle calls (for CPU-baseline timing)."""
+    _load().or_set_num_threads(int(n))
 
 
 def gamma(mu: int) -> np.ndarray:

@@ -25,6 +25,14 @@ int or_num_threads(void) {
 #endif
 }
 
+void or_set_num_threads(int n) {
+#ifdef _OPENMP
+    if (n >= 1) omp_set_num_threads(n);
+#else
+    (void)n;
+#endif
+}
+
 long or_volume(const int dims[4]) {
     return (long)dims[0] * dims[1] * dims[2] * dims[3];
 }

@@ -72,5 +72,7 @@ double or_residual_4d(const or_params* p, const or_cplx* U, const or_cplx* x4,
                       const or_cplx* b4, double tol_inner);
 double or_true_residual(const or_params* p, const or_cplx* U, const or_cplx* x5, const or_cplx* b5);
 int  or_num_threads(void);
+/* OpenMP threads of later calls (CPU-baseline timing only; no arithmetic) */
+void or_set_num_threads(int n);
 
 #endif
