@@ -79,7 +79,8 @@ typedef struct {
     double   inner_tol;   /* relative reduction asked of each inner solve (DC) */
     int      check_every; /* host convergence check period of the CG loop (>= 1) */
     int      paper_mode;  /* 1: plain CGNR in inner_prec stopping at |r|^2/|D^dag b~|^2 < 1e-14
-                             (Sec. 3.2 criterion), no defect correction; iteration counting only */
+                             (Sec. 3.2 criterion), no defect correction; iteration counting only.
+                             Returns DWF_NOT_CONVERGED (converged = 0) if maxiter stops it first. */
     void*    ptc_model;   /* dwf_ptc* for DWF_ALGO_FGCR_LEARNED (NULL: FGCR without preconditioner) */
     int      restart;     /* FGCR restart length (1..64) */
     int      autotune;    /* batched solves: 0 cached tiles or defaults, 1 tune when not cached,
@@ -87,6 +88,11 @@ typedef struct {
     int      use_graph;   /* batched solves: 1 replay the CG iteration body as a HIP graph */
 } dwf_solve_params;
 
+/* Solve report.  Against the survey's sketch of this struct: `iters` is the
+ * total of inner CG iterations over all defect-correction steps (what the
+ * sketch calls inner_iters_total; for plain FP64 CGNR the two counts
+ * coincide), and the 4D residual is not a field because dwf_solve receives
+ * b5 only: it comes from dwf_residual_4d(x4, b4) after dwf_project_4d. */
 typedef struct {
     int    iters;              /* total CG iterations (each = one D^ and one D^dag) */
     int    outer_iters;        /* defect-correction steps */
@@ -95,6 +101,7 @@ typedef struct {
     double true_res5;          /* |b5 - D x5| / |b5| computed in FP64 at the end */
     double seconds;            /* wall time of the solve on the stream, b5 on device -> x5 on device */
     double final_rel_res_even; /* recursive relative residual of the even system at exit */
+    int    final_inner_prec;   /* dwf_prec of the last inner solve (after any stagnation step-up) */
 } dwf_solve_info;
 
 /* Default solve parameters (FP64 CGNR to 1e-10). */
@@ -138,6 +145,17 @@ int dwf_apply(const dwf_op* op, int space, int dagger, int prec, void* out, cons
 
 /* out = D^dag D^ in on even canonical vectors (the CGNR normal operator). */
 int dwf_apply_normal(const dwf_op* op, int prec, void* out, const void* in, void* stream);
+
+/* One CGNR residual update (Sec. 2.3, CG on D^dag D^): with rr = |r|^2,
+ * alpha = rr / |D^ p|^2 and r <- r - alpha D^dag D^ p, computed as inside
+ * dwf_solve (the update is fused into the last hop of D^dag D^, the norms
+ * reduced in FP64).  r and p are even canonical complex128 device vectors;
+ * r is updated in place (rounded through the compute type: FP64 for
+ * DWF_F64, FP32 otherwise), p is read in precision prec.  alpha and rr_new
+ * (= |r|^2 after the update; each may be NULL) are host outputs.
+ * Synchronises the stream. */
+int dwf_cg_residual_update(const dwf_op* op, int prec, void* r, const void* p, double* alpha, double* rr_new,
+                           void* stream);
 
 /* b5 = (-D_-) P^dag (0, ..., 0, b4)  (Sec. 2.3, eq. 5D_linear_equation). */
 int dwf_source_4d(const dwf_op* op, void* b5, const void* b4, void* stream);
@@ -198,7 +216,9 @@ int dwf_true_residual(const dwf_op* op, const void* x5, const void* b5, double* 
  * at alpha = 1, the exact x4 of any alpha satisfies (1-m) x4 + b4 =
  * D_eff^-1 b4 (the 4D solution is alpha independent, Sec. 2.3), so
  * r4 = b4 - D_eff((1-m) x4 + b4).  Costs one D(m) and one m = 1 FP64
- * solve to tol_inner (<= 0: 1e-13).  Synchronises the stream. */
+ * solve to tol_inner (<= 0: 1e-13).  Returns DWF_NOT_CONVERGED (rel still
+ * written) when that inner solve stops short of tol_inner.  Synchronises
+ * the stream. */
 int dwf_residual_4d(const dwf_op* op, const void* x4, const void* b4, double tol_inner, double* rel,
                     void* stream);
 

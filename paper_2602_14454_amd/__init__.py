@@ -48,7 +48,7 @@ class SolveParams(ctypes.Structure):
 class SolveInfo(ctypes.Structure):
     _fields_ = [("iters", ctypes.c_int), ("outer_iters", ctypes.c_int), ("fallback_used", ctypes.c_int),
                 ("converged", ctypes.c_int), ("true_res5", ctypes.c_double), ("seconds", ctypes.c_double),
-                ("final_rel_res_even", ctypes.c_double)]
+                ("final_rel_res_even", ctypes.c_double), ("final_inner_prec", ctypes.c_int)]
 
     def as_dict(self) -> dict:
         return {k: getattr(self, k) for k, _ in self._fields_}
@@ -70,6 +70,7 @@ SIGNATURES = {
     "dwf_apply": (_i, [_vp, _i, _i, _i, _vp, _vp, _vp]),
     "dwf_apply_normal": (_i, [_vp, _i, _vp, _vp, _vp]),
     "dwf_source_4d": (_i, [_vp, _vp, _vp, _vp]),
+    "dwf_cg_residual_update": (_i, [_vp, _i, _vp, _vp, _dp, _dp, _vp]),
     "dwf_project_4d": (_i, [_vp, _vp, _vp, _vp]),
     "dwf_solve": (_i, [_vp, _vp, _vp, ctypes.POINTER(SolveParams), ctypes.POINTER(SolveInfo), _vp]),
     "dwf_true_residual": (_i, [_vp, _vp, _vp, _dp, _vp]),
@@ -402,6 +403,13 @@ class Op:
                "dwf_apply_normal")
         return out
 
+    def cg_residual_update(self, r, p, prec=F64, stream=None):
+        """r <- r - alpha D^dag D^ p with alpha = |r|^2 / |D^ p|^2; returns (alpha, |r_new|^2)."""
+        a, rr = ctypes.c_double(), ctypes.c_double()
+        _check(load().dwf_cg_residual_update(self._h, int(prec), _dev_ptr(r), _dev_ptr(p), ctypes.byref(a),
+                                             ctypes.byref(rr), _stream(stream)), "dwf_cg_residual_update")
+        return a.value, rr.value
+
     def source_4d(self, b5, b4, stream=None):
         _check(load().dwf_source_4d(self._h, _dev_ptr(b5), _dev_ptr(b4), _stream(stream)), "dwf_source_4d")
         return b5
@@ -425,8 +433,11 @@ class Op:
 
     def residual_4d(self, x4, b4, tol_inner=1e-13, stream=None) -> float:
         r = ctypes.c_double()
-        _check(load().dwf_residual_4d(self._h, _dev_ptr(x4), _dev_ptr(b4), float(tol_inner), ctypes.byref(r),
-                                      _stream(stream)), "dwf_residual_4d")
+        st = load().dwf_residual_4d(self._h, _dev_ptr(x4), _dev_ptr(b4), float(tol_inner), ctypes.byref(r),
+                                    _stream(stream))
+        _check(st, "dwf_residual_4d")
+        if st != 0:   # the inner m = 1 solve stopped short: the value is not a residual bound
+            raise DwfError(st, "dwf_residual_4d", load().dwf_last_error().decode())
         return r.value
 
     def lanczos_extremes(self, basis=64, keep=24, max_restarts=50, tol=1e-10, stream=None):

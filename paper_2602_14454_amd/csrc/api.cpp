@@ -6,6 +6,8 @@
 #include <exception>
 #include <memory>
 #include <new>
+#include <vector>
+#include <algorithm>
 
 #include "blas.h"
 #include "dwf_internal.h"
@@ -202,6 +204,39 @@ int dwf_apply_normal(const dwf_op* op, int prec, void* out, const void* in, void
     });
 }
 
+int dwf_cg_residual_update(const dwf_op* op, int prec, void* r, const void* p, double* alpha, double* rr_new,
+                           void* stream) {
+    return guarded([&] {
+        DWF_REQUIRE(op && r && p, DWF_EINVAL, "null argument");
+        DWF_REQUIRE(r != p, DWF_EINVAL, "r and p must not alias");
+        const int k = kind_of(prec);
+        const int kx = k == ST_F64 ? ST_F64 : ST_F32;   // r in the compute type
+        DWF_REQUIRE(op->lat->has_gauge, DWF_ESTATE, "gauge field not set");
+        const long Vh = op->lat->Vh, Vhp = op->lat->Vhp, n = (long)op->Ls * 12 * Vhp;
+        hipStream_t st = S(stream);
+        DevBuf rb(complex_bytes_of(kx) * n), pb(complex_bytes_of(k) * n), to(complex_bytes_of(k) * n),
+            tv(complex_bytes_of(k) * n);
+        DevBuf partial((std::max<long>(hop_partials(op, 1), blas_grid(n)) + 16) * sizeof(double)),
+            scal(CG_NSLOTS * sizeof(double));
+        const int* lex = op->lat->lex_of_site_dev.as<int>();
+        pack_half(kx, rb.p, r, lex, Vh, Vhp, op->Ls, st);
+        pack_half(k, pb.p, p, lex, Vh, Vhp, op->Ls, st);
+        double* pp = partial.as<double>();
+        double* sc = scal.as<double>();
+        norm2_partial(kx, rb.p, n, pp, st);
+        finalize(pp, blas_grid(n), 1, sc + CG_RR, 0, st);
+        apply_normal_update_r(op, k, rb.p, pb.p, to.p, tv.p, pp, sc, 1, st);
+        finalize(pp, hop_partials(op, 1), 1, sc + CG_TMP, 0, st);
+        unpack_half(kx, r, rb.p, lex, Vh, Vhp, op->Ls, st);
+        double h[CG_NSLOTS];
+        DWF_HIP(hipMemcpyAsync(h, sc, sizeof h, hipMemcpyDeviceToHost, st));
+        DWF_HIP(hipStreamSynchronize(st));
+        if (alpha) *alpha = h[CG_ALPHA];
+        if (rr_new) *rr_new = h[CG_TMP];
+        return DWF_OK;
+    });
+}
+
 int dwf_source_4d(const dwf_op* op, void* b5, const void* b4, void* stream) {
     return guarded([&] {
         DWF_REQUIRE(op && b5 && b4, DWF_EINVAL, "null argument");
@@ -279,16 +314,32 @@ int dwf_bench_hop(const dwf_op* op, int prec, int nrep, double* ms_per_launch, d
         const long Vh = L->Vh, n = (long)op->Ls * 12 * L->Vhp;
         const size_t cb = complex_bytes_of(k);
         hipStream_t st = S(stream);
-        DevBuf in(cb * n), out(cb * n);
-        DWF_HIP(hipMemsetAsync(in.p, 0, in.bytes, st));
-        // warm up
-        hop(op, k, 1, in.p, nullptr, out.p, PRE_K, MAT_Q, -1, 0.0, nullptr, 0, 0, nullptr, 0, 1, st, 0, 1);
+        // seeded non-zero inputs; launches rotate over enough (in, out) sets
+        // that the sets together exceed the 256 MB Infinity Cache, so every
+        // launch reads its fields from HBM
+        const size_t fb = cb * (size_t)n;
+        const int nsets = (int)std::min<size_t>(8, std::max<size_t>(1, ((size_t)768 << 20) / (2 * fb) + 1));
+        std::vector<DevBuf> ins(nsets), outs(nsets);
+        {
+            DevBuf tmp(16 * (size_t)n);
+            for (int i = 0; i < nsets; ++i) {
+                ins[i].alloc(fb);
+                outs[i].alloc(fb);
+                random_fill_f64(tmp.p, (long)op->Ls * 12, Vh, L->Vhp, 0x5eedULL + (unsigned long long)i, st);
+                convert(k, ST_F64, ins[i].p, tmp.p, n, st, L->Vhp);
+            }
+            DWF_HIP(hipStreamSynchronize(st));
+        }
+        auto launch = [&](int i) {
+            hop(op, k, 1, ins[i % nsets].p, nullptr, outs[i % nsets].p, PRE_K, MAT_Q, -1, 0.0, nullptr, 0, 0,
+                nullptr, 0, 1, st, 0, 1);
+        };
+        for (int i = 0; i < nsets; ++i) launch(i);   // warm up
         hipEvent_t e0, e1;
         DWF_HIP(hipEventCreate(&e0));
         DWF_HIP(hipEventCreate(&e1));
         DWF_HIP(hipEventRecord(e0, st));
-        for (int i = 0; i < nrep; ++i)
-            hop(op, k, 1, in.p, nullptr, out.p, PRE_K, MAT_Q, -1, 0.0, nullptr, 0, 0, nullptr, 0, 1, st, 0, 1);
+        for (int i = 0; i < nrep; ++i) launch(i);
         DWF_HIP(hipEventRecord(e1, st));
         DWF_HIP(hipEventSynchronize(e1));
         float ms = 0;
@@ -526,8 +577,10 @@ int dwf_residual_4d(const dwf_op* op, const void* x4, const void* b4, double tol
     return guarded([&] {
         DWF_REQUIRE(op && x4 && b4 && rel, DWF_EINVAL, "null argument");
         DWF_REQUIRE(op->lat->has_gauge, DWF_ESTATE, "gauge field not set");
-        *rel = residual_4d(op, x4, b4, tol_inner > 0 ? tol_inner : 1e-13, S(stream));
-        return DWF_OK;
+        bool ok = false;
+        *rel = residual_4d(op, x4, b4, tol_inner > 0 ? tol_inner : 1e-13, S(stream), &ok);
+        if (!ok) set_error("the inner m = 1 solve of the 4D residual did not reach tol_inner");
+        return ok ? DWF_OK : DWF_NOT_CONVERGED;
     });
 }
 

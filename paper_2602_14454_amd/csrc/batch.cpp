@@ -727,6 +727,7 @@ int solve_batch(int n, const dwf_op* const* ops, void* const* x5, const void* co
             f.true_res5 = tr;
             f.seconds = ms * 1e-3;
             f.final_rel_res_even = inner_rel[v];
+            f.final_inner_prec = I->kp;
         }
     }
     if (nan_seen) throw Error{DWF_ENAN, "NaN/Inf in a batched CG reduction"};

@@ -113,6 +113,7 @@ struct dwf_lattice {
     int antiperiodic_t;
     long V, Vh, Vhp;   // sites, sites per parity, padded row stride
     int brick[3] = {0, 0, 0};       // spatial brick extents of the internal site order
+    int site_order = 0;             // 0 bricks swept in t, 1 t columns (build_geometry)
     std::vector<int> lex_of_site;   // host [2][Vh]: lexicographic index of internal site
     std::vector<int> nbr_host;    // host [2][8][Vh]
     dwf::DevBuf nbr;              // device [2][8][Vh]

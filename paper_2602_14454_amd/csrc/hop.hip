@@ -34,6 +34,9 @@
 #include "hop.h"
 #include "precision.h"
 
+#include <algorithm>
+#include <cstdlib>
+
 namespace dwf {
 
 // Tuning knobs (compile time): occupancy target per precision, 4-slice
@@ -66,6 +69,14 @@ namespace dwf {
 #endif
 #ifndef DWF_HOP_NBR_PRELOAD
 #define DWF_HOP_NBR_PRELOAD 1
+#endif
+// Software pipelining of the direction loop: the neighbour spinors of
+// direction d+1 are loaded (raw 16-byte groups, decoded at use) while
+// direction d is computed, so every wave keeps one direction's loads in
+// flight during its arithmetic instead of exposing the memory latency once
+// per direction.
+#ifndef DWF_HOP_PREFETCH
+#define DWF_HOP_PREFETCH 0
 #endif
 // Load the phase-2 MFMA A operands once per wave (see hop_tile): 1 when all
 // its components share a chirality, 2 also when they straddle the two.
@@ -345,6 +356,111 @@ __device__ __forceinline__ void hop_direction(const HopParams& P, const HopRes& 
     }
 }
 
+// Pipelined form of hop_direction (DWF_HOP_PREFETCH): hop_fetch issues the
+// neighbour loads of direction D for the wave's slice groups into raw
+// 16-byte words; hop_apply decodes them and does the rest of hop_direction
+// (the K pre-mix, the link from LDS, the spin-projected colour products).
+template <class S>
+__device__ __forceinline__ void decode_group(u32x4 w, typename Traits<S>::R (&v)[8]) {
+    if constexpr (sizeof(S) == 8) {
+        v[0] = __hiloint2double(w.y, w.x);
+        v[1] = __hiloint2double(w.w, w.z);
+    } else if constexpr (sizeof(S) == 4) {
+        v[0] = __uint_as_float(w.x);
+        v[1] = __uint_as_float(w.y);
+        v[2] = __uint_as_float(w.z);
+        v[3] = __uint_as_float(w.w);
+    } else {
+        const unsigned u[4] = {w.x, w.y, w.z, w.w};
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+            v[2 * k] = bf16_to_f32(u[k] & 0xffffu);
+            v[2 * k + 1] = bf16_to_f32(u[k] >> 16);
+        }
+    }
+}
+
+template <class S, int G>
+__device__ __forceinline__ void hop_fetch(const HopParams& P, const HopRes& R_, unsigned gb, int D, const int (&s)[G],
+                                          const unsigned* lnbr, int j, u32x4 (&raw)[G][12 / fpack<S>()],
+                                          unsigned& yg) {
+    constexpr unsigned CB = cbytes<S>();
+    constexpr int PK = fpack<S>();
+    constexpr int NGR = 12 / PK;
+    static_assert(PK * CB == 16, "16-byte field groups expected");
+    const unsigned y = lnbr[D * 16 + j];
+    yg = y * (unsigned)PK * CB;
+#pragma unroll
+    for (int g = 0; g < G; ++g) {
+        const int sg_ = s[g] < P.Ls ? s[g] : 0;   // slices past Ls read slice 0 (zeroed later)
+        const unsigned vb = yg + (unsigned)sg_ * NGR * gb;
+#pragma unroll
+        for (int q = 0; q < NGR; ++q) raw[g][q] = __builtin_amdgcn_raw_buffer_load_b128(R_.in, vb, (unsigned)q * gb, 0);
+    }
+}
+
+template <class S, int G>
+__device__ __forceinline__ void hop_apply(const HopParams& P, const HopRes& R_, unsigned gb, int D, const int (&s)[G],
+                                          const typename Traits<S>::R (&pd)[G][2],
+                                          const typename Traits<S>::R (&pe)[G][2],
+                                          const typename Traits<S>::R (&kr)[G],
+                                          typename Traits<S>::R (&h)[G][24], const u32x4* lnk,
+                                          const u32x4 (&raw)[G][12 / fpack<S>()], unsigned yg, int j) {
+    using R = typename Traits<S>::R;
+    constexpr unsigned CB = cbytes<S>();
+    constexpr unsigned NG = link_ng(CB);
+    constexpr int PK = fpack<S>();
+    constexpr int NGR = 12 / PK;
+    const int Ls = P.Ls;
+    R U[18];
+#pragma unroll
+    for (unsigned g = 0; g < NG; ++g) decode_link_group<S>(lnk[(D * NG + g) * 16 + j], (int)g, U);
+#pragma unroll
+    for (int g = 0; g < G; ++g) {
+        const int sg_ = s[g] < Ls ? s[g] : 0;
+        R p[24];
+#pragma unroll
+        for (int q = 0; q < NGR; ++q) {
+            R v[8];
+            decode_group<S>(raw[g][q], v);
+#pragma unroll
+            for (int k = 0; k < 2 * PK; ++k) p[2 * PK * q + k] = v[k];
+        }
+        if (P.pre_mode == 2) {
+#pragma unroll
+            for (int k = 0; k < 12; ++k) p[k] *= pd[g][0];
+#pragma unroll
+            for (int k = 12; k < 24; ++k) p[k] *= pd[g][1];
+            const unsigned sm = (unsigned)(sg_ == 0 ? Ls - 1 : sg_ - 1) * NGR * gb;
+            const unsigned sp = (unsigned)(sg_ == Ls - 1 ? 0 : sg_ + 1) * NGR * gb;
+#pragma unroll
+            for (int q = 0; q < NGR; ++q) {
+                if (PK * q < 6) {
+                    R v[8];
+                    bload_group<S>(R_.in, yg + sm, (unsigned)q * gb, v);
+#pragma unroll
+                    for (int k = 0; k < PK; ++k)
+                        if (PK * q + k < 6) {
+                            p[2 * (PK * q + k)] += pe[g][0] * v[2 * k];
+                            p[2 * (PK * q + k) + 1] += pe[g][0] * v[2 * k + 1];
+                        }
+                }
+                if (PK * q + PK > 6) {
+                    R v[8];
+                    bload_group<S>(R_.in, yg + sp, (unsigned)q * gb, v);
+#pragma unroll
+                    for (int k = 0; k < PK; ++k)
+                        if (PK * q + k >= 6) {
+                            p[2 * (PK * q + k)] += pe[g][1] * v[2 * k];
+                            p[2 * (PK * q + k) + 1] += pe[g][1] * v[2 * k + 1];
+                        }
+                }
+            }
+        }
+        hop_dir<R>(D, U, p, h[g], kr[g]);
+    }
+}
+
 // Number of 4-slice groups each wave computes in the hop phase, and waves
 // per block, for KK = ceil(Ls/4) groups.
 __host__ __device__ constexpr int hop_kpw(int KK, bool f64) {
@@ -504,15 +620,33 @@ __device__ __forceinline__ void hop_tile(const HopParams& P, long tile, int rhs,
             ynb[d] = (DWF_HOP_NBR_PRELOAD && !DWF_HOP_LDS_LINKS)
                          ? __builtin_amdgcn_raw_buffer_load_b32(R_.nbr, (unsigned)sx * 4u, (unsigned)d * (unsigned)P.Vhp * 4u, 0)
                          : 0u;
-#pragma unroll DWF_HOP_UNROLL
-        for (int d = 0; d < 8; ++d) {
-            hop_direction<S, G>(P, R_, gb, (unsigned)sx, d, ynb[d], sg, pd, pe, kr, h, lnk, lnbr, j);
-            // unrolled: keep each direction's loads after the previous one's
-            // arithmetic (hoisting them all raises the register count past
-            // the occupancy target)
-            if constexpr (DWF_HOP_UNROLL > 1) {
-                asm volatile("" ::: "memory");
+        if constexpr (DWF_HOP_PREFETCH && DWF_HOP_LDS_LINKS) {
+            // ping-pong over two raw buffers: the loads of the next direction
+            // are in flight while the current one is computed
+            constexpr int NGR = 12 / fpack<S>();
+            u32x4 ra[G][NGR], rb[G][NGR];
+            unsigned ya, yb;
+            hop_fetch<S, G>(P, R_, gb, 0, sg, lnbr, j, ra, ya);
+#pragma unroll 1
+            for (int d = 0; d < 8; d += 2) {
+                hop_fetch<S, G>(P, R_, gb, d + 1, sg, lnbr, j, rb, yb);
                 __builtin_amdgcn_sched_barrier(0);
+                hop_apply<S, G>(P, R_, gb, d, sg, pd, pe, kr, h, lnk, ra, ya, j);
+                if (d + 2 < 8) hop_fetch<S, G>(P, R_, gb, d + 2, sg, lnbr, j, ra, ya);
+                __builtin_amdgcn_sched_barrier(0);
+                hop_apply<S, G>(P, R_, gb, d + 1, sg, pd, pe, kr, h, lnk, rb, yb, j);
+            }
+        } else {
+#pragma unroll DWF_HOP_UNROLL
+            for (int d = 0; d < 8; ++d) {
+                hop_direction<S, G>(P, R_, gb, (unsigned)sx, d, ynb[d], sg, pd, pe, kr, h, lnk, lnbr, j);
+                // unrolled: keep each direction's loads after the previous one's
+                // arithmetic (hoisting them all raises the register count past
+                // the occupancy target)
+                if constexpr (DWF_HOP_UNROLL > 1) {
+                    asm volatile("" ::: "memory");
+                    __builtin_amdgcn_sched_barrier(0);
+                }
             }
         }
 #pragma unroll
@@ -981,11 +1115,23 @@ static unsigned hop_smem_bytes(int KK, bool loc) {
 int hop_grid_blocks(long Vh) { return (int)((Vh + 15) / 16); }
 int mix_grid_blocks(long Vh) { return (int)((Vh + 63) / 64); }
 
+// Minimum shared memory per hop block ($DWF_HOP_MIN_LDS bytes, default 0):
+// a larger request caps the blocks resident per CU (160 KB of LDS each),
+// i.e. the sites an XCD has in flight, without changing the code.
+static unsigned hop_min_lds() {
+    static const unsigned v = [] {
+        const char* e = std::getenv("DWF_HOP_MIN_LDS");
+        const long x = e ? std::atol(e) : 0;
+        return (unsigned)std::min<long>(std::max<long>(x, 0), 160 * 1024);
+    }();
+    return v;
+}
+
 template <class S, int TAG>
 static void launch_hop_t(const HopParams& P, int nrhs, hipStream_t st) {
     const int KK = (P.Ls + 3) / 4;
     dim3 grid(hop_grid_blocks(P.Vh), nrhs), block(64 * hop_waves(KK, sizeof(S) == 8));
-    const unsigned smem_b = hop_smem_bytes<S>(KK, P.loc != nullptr);
+    const unsigned smem_b = std::max(hop_smem_bytes<S>(KK, P.loc != nullptr), hop_min_lds());
     switch (KK) {
         case 1: hipLaunchKernelGGL((hop_mfma_kernel<S, 1, TAG>), grid, block, smem_b, st, P); break;
         case 2: hipLaunchKernelGGL((hop_mfma_kernel<S, 2, TAG>), grid, block, smem_b, st, P); break;
@@ -1048,15 +1194,33 @@ void launch_hop(int kind, const HopParams& P, int nrhs, hipStream_t st, int benc
     }
 }
 
-// Plain streaming copy (16-byte vectors), used to calibrate memory counters.
-__global__ void copy_kernel(float4* __restrict__ dst, const float4* __restrict__ src, long n) {
-    for (long i = (long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (long)gridDim.x * blockDim.x)
-        dst[i] = src[i];
+// Plain streaming copy (16-byte vectors), used to calibrate memory counters
+// and as the measured streaming ceiling: every lane moves four 16-byte
+// vectors whose loads are all issued before the first store, one block per
+// 4 x 256 vectors (no grid-stride loop), the form that kept the most bytes
+// in flight in a sweep of vectors per lane and block counts.
+constexpr int COPY_VPL = 4;
+__global__ __launch_bounds__(256) void copy_kernel(float4* __restrict__ dst, const float4* __restrict__ src, long n) {
+    const long base = (long)blockIdx.x * (256 * COPY_VPL) + threadIdx.x;
+    float4 v[COPY_VPL];
+#pragma unroll
+    for (int k = 0; k < COPY_VPL; ++k) {
+        const long i = base + (long)k * 256;
+        if (i < n) v[k] = src[i];
+    }
+#pragma unroll
+    for (int k = 0; k < COPY_VPL; ++k) {
+        const long i = base + (long)k * 256;
+        if (i < n) dst[i] = v[k];
+    }
 }
 
 void launch_copy(void* dst, const void* src, size_t bytes, hipStream_t st) {
     const long n = (long)(bytes / 16);
-    hipLaunchKernelGGL(copy_kernel, dim3(4096), dim3(256), 0, st, (float4*)dst, (const float4*)src, n);
+    const long blocks = (n + 256 * COPY_VPL - 1) / (256 * COPY_VPL);
+    DWF_REQUIRE(blocks < (1L << 31), DWF_EINVAL, "copy too large");
+    if (blocks == 0) return;
+    hipLaunchKernelGGL(copy_kernel, dim3((unsigned)blocks), dim3(256), 0, st, (float4*)dst, (const float4*)src, n);
     DWF_HIP(hipGetLastError());
 }
 

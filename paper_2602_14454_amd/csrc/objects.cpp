@@ -1,6 +1,8 @@
 // Lattice geometry, gauge-link packing and operator coefficient setup.
 #include <cmath>
 #include <complex>
+#include <cstdio>
+#include <cstdlib>
 #include <cstring>
 
 #include "dwf_internal.h"
@@ -19,26 +21,42 @@ static uint16_t host_f32_to_bf16(float f) {
     return (uint16_t)(u >> 16);
 }
 
-// Internal site order: the spatial volume is cut into bricks and every
-// brick is swept in t (brick index slowest, then t, z, y, x).  With bricks of
-// the whole spatial volume this is the lexicographic order.  Smaller bricks
-// keep the t neighbours of the sites a GPU die has in flight inside its L2
-// (a t slice of 24^3 sites is ~10 MB of FP32 input at Ls = 16, beyond an
-// XCD's 4 MB L2) at the cost of re-reading brick faces.  Measured on MI355X
-// (fused hop, Ls = 16): on 16^3x32 bricks of 1024 sites per slice beat whole
-// slices (FP64 193 -> 185 us, FP32 84 -> 78 us); on 24^3x48 bricks of 4096
-// sites are best (FP32 479 us vs 519 us at 2048 and 546 us at 1024; larger
-// bricks are slower: 440 us vs 459 us at 8192 and 501 us for whole slices).  Default:
-// 1024 up to 16^3 spatial sites, 4096 above; DWF_BRICK_SITES overrides.
+// Internal site order.  Two orders exist; both are bijections onto the
+// sites of each parity, and every kernel goes through the site and
+// neighbour tables, so the choice only changes cache behaviour.
+//
+// "brick": the spatial volume is cut into bricks and every brick is swept
+// in t (brick index slowest, then t, z, y, x).  With bricks of the whole
+// spatial volume this is the lexicographic order.  Smaller bricks keep the
+// t neighbours of the sites a GPU die has in flight inside its L2 (a t slice
+// of 24^3 sites is ~10 MB of FP32 input at Ls = 16, beyond an XCD's 4 MB L2)
+// at the cost of re-reading brick faces.  Measured on MI355X (fused hop,
+// Ls = 16): on 16^3x32 bricks of 1024 sites per slice beat whole slices
+// (FP64 193 -> 185 us, FP32 84 -> 78 us); on 24^3x48 bricks of 4096 sites
+// are best (FP32 479 us vs 519 us at 2048 and 546 us at 1024; larger bricks
+// are slower: 440 us vs 459 us at 8192 and 501 us for whole slices).
+// Brick limit: 1024 sites up to 16^3 spatial sites, 4096 above
+// ($DWF_BRICK_SITES overrides).
+//
+// "tcol": t columns.  The sites of one parity at one spatial position (every
+// other t) are consecutive, so a block of 16 sites is (most of) one t
+// column: its t neighbours are the column of the other parity at the same
+// position, and each spatial neighbour direction maps the block onto one
+// column of a neighbouring position.  Spatial positions are visited octant
+// by octant (one octant per XCD under the block remap of the hop), tile by
+// tile inside an octant and x-fastest inside a tile, so that the columns a
+// die reads are re-read while they are still in its L2.  Tile extents
+// ($DWF_TCOL_TILE="tx,ty,tz", default 4,4,4) are shrunk to divide the
+// octant.
 static void choose_brick(const int dims[4], int b[3]) {
     b[0] = dims[0];
     b[1] = dims[1];
     b[2] = dims[2];
-#ifdef DWF_BRICK_SITES
-    const long fmax = DWF_BRICK_SITES;   // sites (both parities) per brick slice
-#else
-    const long fmax = (long)dims[0] * dims[1] * dims[2] <= 4096 ? 1024L : 4096L;
-#endif
+    long fmax = (long)dims[0] * dims[1] * dims[2] <= 4096 ? 1024L : 4096L;   // sites (both parities) per brick slice
+    if (const char* e = std::getenv("DWF_BRICK_SITES")) {
+        const long v = std::atol(e);
+        if (v >= 8) fmax = v;
+    }
     while ((long)b[0] * b[1] * b[2] > fmax) {
         int best = -1;
         for (int mu = 2; mu >= 0; --mu)   // prefer z, then y, then x on ties
@@ -48,10 +66,50 @@ static void choose_brick(const int dims[4], int b[3]) {
     }
 }
 
+static int site_order_kind() {
+    const char* e = std::getenv("DWF_SITE_ORDER");
+    if (e && std::strcmp(e, "tcol") == 0) return 1;
+    return 0;
+}
+
+static int gcd_int(int a, int b) {
+    while (b) { const int t = a % b; a = b; b = t; }
+    return a;
+}
+
+// spatial positions (x, y, z) in the visiting order of the t-column order
+static std::vector<int> tcol_spatial_order(const int dims[4]) {
+    int oct[3], tile[3] = {4, 4, 4};
+    if (const char* e = std::getenv("DWF_TCOL_TILE")) {
+        int a = 0, b = 0, c = 0;
+        if (std::sscanf(e, "%d,%d,%d", &a, &b, &c) == 3 && a > 0 && b > 0 && c > 0) {
+            tile[0] = a; tile[1] = b; tile[2] = c;
+        }
+    }
+    for (int mu = 0; mu < 3; ++mu) {
+        oct[mu] = dims[mu] % 2 == 0 && dims[mu] >= 4 ? dims[mu] / 2 : dims[mu];
+        tile[mu] = gcd_int(oct[mu], tile[mu]);
+    }
+    std::vector<int> order;
+    order.reserve((size_t)dims[0] * dims[1] * dims[2]);
+    for (int oz = 0; oz < dims[2]; oz += oct[2])
+        for (int oy = 0; oy < dims[1]; oy += oct[1])
+            for (int ox = 0; ox < dims[0]; ox += oct[0])
+                for (int tz = oz; tz < oz + oct[2]; tz += tile[2])
+                    for (int ty = oy; ty < oy + oct[1]; ty += tile[1])
+                        for (int tx = ox; tx < ox + oct[0]; tx += tile[0])
+                            for (int z = tz; z < tz + tile[2]; ++z)
+                                for (int y = ty; y < ty + tile[1]; ++y)
+                                    for (int x = tx; x < tx + tile[0]; ++x)
+                                        order.push_back(x + dims[0] * (y + dims[1] * z));
+    return order;
+}
+
 void build_geometry(dwf_lattice* L) {
     const int Lx = L->dims[0], Ly = L->dims[1], Lz = L->dims[2], Lt = L->dims[3];
     const long V = L->V, Vh = L->Vh;
     choose_brick(L->dims, L->brick);
+    L->site_order = site_order_kind();
     // row stride: 32 x odd, so consecutive rows of a field land in different cache sets
     L->Vhp = ((Vh + 31) / 32) * 32;
     if ((L->Vhp / 32) % 2 == 0) L->Vhp += 32;
@@ -60,19 +118,27 @@ void build_geometry(dwf_lattice* L) {
     L->lex_of_site.assign(2 * Vh, -1);
     std::vector<int> site_of_lex(V, -1);
     long next[2] = {0, 0};
-    for (int zb = 0; zb < Lz / bz; ++zb)
-        for (int yb = 0; yb < Ly / by; ++yb)
-            for (int xb = 0; xb < Lx / bx; ++xb)
-                for (int t = 0; t < Lt; ++t)
-                    for (int z = zb * bz; z < (zb + 1) * bz; ++z)
-                        for (int y = yb * by; y < (yb + 1) * by; ++y)
-                            for (int x = xb * bx; x < (xb + 1) * bx; ++x) {
-                                const int p = (x + y + z + t) & 1;
-                                const long lex = x + (long)Lx * (y + (long)Ly * (z + (long)Lz * t));
-                                const long i = next[p]++;
-                                L->lex_of_site[p * Vh + i] = (int)lex;
-                                site_of_lex[lex] = (int)i;
-                            }
+    auto place = [&](int x, int y, int z, int t) {
+        const int p = (x + y + z + t) & 1;
+        const long lex = x + (long)Lx * (y + (long)Ly * (z + (long)Lz * t));
+        const long i = next[p]++;
+        L->lex_of_site[p * Vh + i] = (int)lex;
+        site_of_lex[lex] = (int)i;
+    };
+    if (L->site_order == 1) {
+        for (const int pos : tcol_spatial_order(L->dims)) {
+            const int x = (int)(pos % Lx), y = (int)((pos / Lx) % Ly), z = (int)(pos / ((long)Lx * Ly));
+            for (int t = 0; t < Lt; ++t) place(x, y, z, t);
+        }
+    } else {
+        for (int zb = 0; zb < Lz / bz; ++zb)
+            for (int yb = 0; yb < Ly / by; ++yb)
+                for (int xb = 0; xb < Lx / bx; ++xb)
+                    for (int t = 0; t < Lt; ++t)
+                        for (int z = zb * bz; z < (zb + 1) * bz; ++z)
+                            for (int y = yb * by; y < (yb + 1) * by; ++y)
+                                for (int x = xb * bx; x < (xb + 1) * bx; ++x) place(x, y, z, t);
+    }
     DWF_REQUIRE(next[0] == Vh && next[1] == Vh, DWF_EDIMS, "internal site order is not a bijection");
     L->nbr_host.assign(2 * 8 * Vhp, 0);
     const int ext[4] = {Lx, Ly, Lz, Lt};

@@ -437,18 +437,22 @@ int solve(const dwf_op* op, void* x5, const void* b5, const dwf_solve_params* pr
     DWF_HIP(hipEventDestroy(e0));
     DWF_HIP(hipEventDestroy(e1));
     const double true_res = b2 > 0 ? std::sqrt(r2 / b2) : 0.0;
+    // paper mode: converged only when the CG met its own stopping test
+    // (|r|^2 / |r0|^2 < 1e-14), not when it ran out of iterations
+    const bool paper_ok = prm->paper_mode && !nan_seen && last_inner_rel <= inner_tol;
     if (info) {
         info->iters = total;
         info->outer_iters = outer;
         info->fallback_used = fallback;
-        info->converged = (converged || (prm->paper_mode && !nan_seen)) ? 1 : 0;
+        info->converged = (converged || paper_ok) ? 1 : 0;
         info->true_res5 = true_res;
         info->seconds = ms * 1e-3;
         info->final_rel_res_even = last_inner_rel;
+        info->final_inner_prec = use_fgcr ? ST_F32 : kp;
     }
     if (nan_seen) throw Error{DWF_ENAN, "NaN/Inf in a CG reduction"};
     guard.ok = true;
-    if (prm->paper_mode) return DWF_OK;
+    if (prm->paper_mode) return paper_ok ? DWF_OK : DWF_NOT_CONVERGED;
     return (converged || true_res <= tol) ? DWF_OK : DWF_NOT_CONVERGED;
 }
 
@@ -482,7 +486,8 @@ double true_residual(const dwf_op* op, const void* x5, const void* b5, hipStream
 //   r4 = b4 - D_eff((1 - m) x4 + b4)
 // vanishes for the exact x4.  Cost: one D(m) application and one well
 // conditioned m = 1 solve (FP64 CGNR to tol_inner).
-double residual_4d(const dwf_op* op, const void* x4, const void* b4, double tol_inner, hipStream_t st) {
+double residual_4d(const dwf_op* op, const void* x4, const void* b4, double tol_inner, hipStream_t st,
+                   bool* converged) {
     dwf_lattice* L = op->lat;
     const long V = L->V, Vh = L->Vh, Vhp = L->Vhp;
     const int Ls = op->Ls;
@@ -517,7 +522,8 @@ double residual_4d(const dwf_op* op, const void* x4, const void* b4, double tol_
     prm.algo = DWF_ALGO_CGNR;
     prm.inner_prec = DWF_F64;
     prm.check_every = 4;
-    solve(&o1, v5.p, z5.p, &prm, nullptr, st);
+    if (converged) *converged = solve(&o1, v5.p, z5.p, &prm, nullptr, st) == DWF_OK;
+    else solve(&o1, v5.p, z5.p, &prm, nullptr, st);
     project_4d(y.p, v5.p, V, Ls, st);
     axpby(ST_F64, ST_F64, y.p, b4, n4, nullptr, 1.0, nullptr, -1.0, nullptr, st);   // y = b4 - D_eff(...)
     double* pp = partial.as<double>();

@@ -53,7 +53,9 @@ bool trace_on();
 int solve(const dwf_op* op, void* x5, const void* b5, const dwf_solve_params* prm, dwf_solve_info* info,
           hipStream_t st);
 double true_residual(const dwf_op* op, const void* x5, const void* b5, hipStream_t st);
-double residual_4d(const dwf_op* op, const void* x4, const void* b4, double tol_inner, hipStream_t st);
+// *converged (may be NULL): whether the inner m = 1 solve met tol_inner
+double residual_4d(const dwf_op* op, const void* x4, const void* b4, double tol_inner, hipStream_t st,
+                   bool* converged = nullptr);
 
 // batch.cpp: batched solves and the tile autotuner of the work-list hop
 int solve_batch(int n, const dwf_op* const* ops, void* const* x5, const void* const* b5, const int* nrhs,

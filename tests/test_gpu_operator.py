@@ -102,7 +102,7 @@ def test_schur_operator(case, prec, dagger):
 
 
 @pytest.mark.parametrize("case", CASES[:3])
-@pytest.mark.parametrize("prec", [0, 1])
+@pytest.mark.parametrize("prec", [0, 1, 2])
 def test_normal_operator(case, prec):
     import torch
     lat, op, p, U = _make(case)
@@ -148,3 +148,28 @@ def test_free_field_plane_wave_eigen():
     wu = np.einsum("ij,jc->ic", Dp, u.reshape(Ls * 4, 3)).reshape(Ls, 4, 3)
     want = np.stack([ff.plane_wave_4d(dims, mom, wu[s]) for s in range(Ls)])[:, le]
     assert _rel(_host(out), want) < 1e-13
+
+
+# compute type of the CG residual for each operator precision
+R_TOL = {0: 1e-13, 1: 1e-5, 2: 3e-2}
+
+
+@pytest.mark.parametrize("case", CASES[:4])
+@pytest.mark.parametrize("prec", [0, 1, 2])
+def test_cg_residual_update(case, prec):
+    """The fused CGNR step (r -= alpha D^dag D^ p inside the last hop, |r|^2
+    in its epilogue) against the oracle: alpha = |r|^2 / |D^ p|^2,
+    r_new = r - alpha D^dag D^ p, |r_new|^2."""
+    import torch
+    lat, op, p, U = _make(case)
+    r = dwfgen.gaussian_source_5d(p.dims, p.Ls, 21)[:, : p.Vh].copy()
+    pv = dwfgen.gaussian_source_5d(p.dims, p.Ls, 22)[:, : p.Vh].copy()
+    q = oracle.dhat(p, U, pv)
+    a_want = np.vdot(r, r).real / np.vdot(q, q).real
+    r_want = r - a_want * oracle.dhat(p, U, q, dagger=True)
+    rd = _dev(r)
+    a, rr = op.cg_residual_update(rd, _dev(pv), prec=prec)
+    assert abs(a - a_want) <= R_TOL[prec] * abs(a_want)
+    got = _host(rd)
+    assert _rel(got, r_want) < R_TOL[prec]
+    assert abs(rr - np.vdot(got, got).real) <= 1e-5 * rr if prec else abs(rr - np.vdot(got, got).real) <= 1e-12 * rr
