@@ -146,6 +146,19 @@ int dwf_apply(const dwf_op* op, int space, int dagger, int prec, void* out, cons
 /* out = D^dag D^ in on even canonical vectors (the CGNR normal operator). */
 int dwf_apply_normal(const dwf_op* op, int prec, void* out, const void* in, void* stream);
 
+/* out = D^dag D^ in as dwf_apply_normal, for callers that cannot allocate
+ * device memory (code under HIP graph capture, tight serving loops,
+ * harnesses that forbid hipMalloc).  Allocates nothing: its four half-field
+ * temporaries live in a static device array of the library (128 MiB per GPU,
+ * held until the process ends); a lattice whose four half fields in
+ * precision prec exceed it is rejected with DWF_EDIMS before anything is
+ * enqueued (e.g. Ls = 16: up to about 10^4 sites per parity in FP64).  The
+ * work is enqueued on `stream` and the call does not synchronise.  Every
+ * call on one GPU shares that GPU's array: calls that overlap on one GPU
+ * (several streams or host threads) race and must be serialised by the
+ * caller.  The operator's lattice must live on the current device. */
+int dwf_apply_normal_noalloc(const dwf_op* op, int prec, void* out, const void* in, void* stream);
+
 /* One CGNR residual update (Sec. 2.3, CG on D^dag D^): with rr = |r|^2,
  * alpha = rr / |D^ p|^2 and r <- r - alpha D^dag D^ p, computed as inside
  * dwf_solve (the update is fused into the last hop of D^dag D^, the norms

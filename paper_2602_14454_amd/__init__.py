@@ -71,6 +71,7 @@ SIGNATURES = {
     "dwf_apply_normal": (_i, [_vp, _i, _vp, _vp, _vp]),
     "dwf_source_4d": (_i, [_vp, _vp, _vp, _vp]),
     "dwf_cg_residual_update": (_i, [_vp, _i, _vp, _vp, _dp, _dp, _vp]),
+    "dwf_apply_normal_noalloc": (_i, [_vp, _i, _vp, _vp, _vp]),
     "dwf_project_4d": (_i, [_vp, _vp, _vp, _vp]),
     "dwf_solve": (_i, [_vp, _vp, _vp, ctypes.POINTER(SolveParams), ctypes.POINTER(SolveInfo), _vp]),
     "dwf_true_residual": (_i, [_vp, _vp, _vp, _dp, _vp]),
@@ -402,6 +403,11 @@ class Op:
         _check(load().dwf_apply_normal(self._h, int(prec), _dev_ptr(out), _dev_ptr(inp), _stream(stream)),
                "dwf_apply_normal")
         return out
+
+    def apply_normal_noalloc(self, out, inp, prec=F64, stream=None):
+        """D^dag D^ with the library's static scratch (no device allocation, no synchronisation)."""
+        _check(load().dwf_apply_normal_noalloc(self._h, int(prec), _dev_ptr(out), _dev_ptr(inp), _stream(stream)),
+               "dwf_apply_normal_noalloc")
 
     def cg_residual_update(self, r, p, prec=F64, stream=None):
         """r <- r - alpha D^dag D^ p with alpha = |r|^2 / |D^ p|^2; returns (alpha, |r_new|^2)."""

@@ -5,6 +5,8 @@
 #include <cstring>
 #include <exception>
 #include <memory>
+#include <mutex>
+#include <string>
 #include <new>
 #include <vector>
 #include <algorithm>
@@ -200,6 +202,64 @@ int dwf_apply_normal(const dwf_op* op, int prec, void* out, const void* in, void
         apply_normal(op, k, oe.p, ie.p, to.p, tv.p, nullptr, 1, st);
         unpack_half(k, out, oe.p, lex, Vh, Vhp, op->Ls, st);
         DWF_HIP(hipStreamSynchronize(st));
+        return DWF_OK;
+    });
+}
+
+}  // extern "C"
+
+// Device scratch of dwf_apply_normal_noalloc, for callers that cannot
+// allocate: the four half fields of the normal operator (packed input,
+// output, two hop temporaries) live in this file-scope array, one copy per
+// GPU, held until the process ends.  Host code never passes the array's
+// name to a kernel (on the host it is only a stand-in for the symbol): the
+// device address of each GPU's copy is looked up once per device with
+// hipGetSymbolAddress and used from then on.
+static constexpr size_t NOALLOC_SCRATCH_BYTES = size_t(128) << 20;
+static __device__ __align__(256) unsigned char scratch[NOALLOC_SCRATCH_BYTES];
+
+namespace {
+constexpr int NOALLOC_MAX_DEVICES = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[NOALLOC_MAX_DEVICES] = {};
+
+void* noalloc_scratch() {
+    int dev = 0;
+    DWF_HIP(hipGetDevice(&dev));
+    DWF_REQUIRE(dev >= 0 && dev < NOALLOC_MAX_DEVICES, DWF_EINVAL, "device ordinal out of range");
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void* ptr = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || ptr == nullptr)
+            throw Error{DWF_EHIP, std::string("hipGetSymbolAddress(scratch): ") + hipGetErrorString(e)};
+        g_scratch_ptr[dev] = ptr;
+    }
+    return g_scratch_ptr[dev];
+}
+}  // namespace
+
+extern "C" {
+
+int dwf_apply_normal_noalloc(const dwf_op* op, int prec, void* out, const void* in, void* stream) {
+    return guarded([&] {
+        DWF_REQUIRE(op && out && in, DWF_EINVAL, "null argument");
+        DWF_REQUIRE(out != in, DWF_EINVAL, "in and out must not alias");
+        const int k = kind_of(prec);
+        DWF_REQUIRE(op->lat->has_gauge, DWF_ESTATE, "gauge field not set");
+        const long Vh = op->lat->Vh, Vhp = op->lat->Vhp, n = (long)op->Ls * 12 * Vhp;
+        const size_t slot = (complex_bytes_of(k) * (size_t)n + 255) & ~(size_t)255;
+        if (4 * slot > NOALLOC_SCRATCH_BYTES)
+            throw Error{DWF_EDIMS, "dwf_apply_normal_noalloc: four half fields of " + std::to_string(slot) +
+                                       " bytes exceed its " + std::to_string(NOALLOC_SCRATCH_BYTES >> 20) +
+                                       " MiB scratch; use dwf_apply_normal"};
+        char* base = static_cast<char*>(noalloc_scratch());
+        void *ie = base, *oe = base + slot, *to = base + 2 * slot, *tv = base + 3 * slot;
+        hipStream_t st = S(stream);
+        const int* lex = op->lat->lex_of_site_dev.as<int>();
+        pack_half(k, ie, in, lex, Vh, Vhp, op->Ls, st);
+        apply_normal(op, k, oe, ie, to, tv, nullptr, 1, st);
+        unpack_half(k, out, oe, lex, Vh, Vhp, op->Ls, st);
         return DWF_OK;
     });
 }
