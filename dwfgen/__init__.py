@@ -11,7 +11,10 @@ sources that both sides take as inputs:
 * stout smearing of the links (paper Sec. 2.2, "Link smearing", eq. of the
   stout projection): C_mu = rho * sum of the six staples,
   U' = exp([C U^dagger]_AT) U, all links updated simultaneously;
-* Gaussian 4D / 5D sources and spin-colour point sources.
+* Gaussian 4D / 5D sources and spin-colour point sources;
+* operator coefficients: Zolotarev's optimal rational sign function and the
+  s-dependent weights omega_s (b_s = c_s, Chiu's optimal domain-wall choice of
+  Sec. 2.2) that realise it.
 
 Array layouts (lex = x + Lx*(y + Ly*(z + Lz*t))):
   links   complex128 (V, 4, 3, 3)   U[lex, mu, row, col], mu = x, y, z, t
@@ -25,7 +28,7 @@ import numpy as np
 __all__ = [
     "uniform01", "gaussian", "random_su3_links", "stout_smear", "plaquette",
     "gaussian_source_4d", "gaussian_source_5d", "point_source_4d",
-    "unit_links", "make_links", "lattice_volume",
+    "unit_links", "make_links", "lattice_volume", "zolotarev_sign", "zolotarev_omega",
 ]
 
 _GOLD = np.uint64(0x9E3779B97F4A7C15)
@@ -219,3 +222,69 @@ def point_source_4d(dims, spin: int, colour: int, site: int = 0) -> np.ndarray:
     b = np.zeros((V, 4, 3), dtype=np.complex128)
     b[site, spin, colour] = 1.0
     return b
+
+
+# ---------------------------------------------------------------------------
+# Operator coefficients (inputs of the operator, no solver arithmetic).
+# ---------------------------------------------------------------------------
+
+def _zolotarev_coeffs(Ls: int, k: float):
+    from scipy.special import ellipj, ellipk
+    kp2 = 1.0 - k * k
+    Kp = ellipk(kp2)
+    ls = np.arange(1, Ls)
+    sn, cn, _, _ = ellipj(ls * Kp / Ls, kp2)
+    c = k * k * sn ** 2 / cn ** 2
+
+    def shape(x):
+        x = np.asarray(x, dtype=np.float64)
+        r = x.copy()
+        for l, cl in zip(ls, c):
+            r = r * (x * x + cl) if l % 2 == 0 else r / (x * x + cl)
+        return r
+
+    g = shape(np.geomspace(k, 1.0, 200001))
+    d = 2.0 / (g.max() + g.min())
+    delta = (g.max() - g.min()) / (g.max() + g.min())
+    return (lambda x: d * shape(x)), delta
+
+
+def zolotarev_sign(y, Ls: int, k: float):
+    """Zolotarev's best uniform rational approximation of sign on [k, 1]
+    (odd, numerator degree Ls or Ls - 1 by parity, denominator Ls - 1 or Ls):
+        R(y) = d * y * prod_{l even} (y^2 + c_l) / prod_{l odd} (y^2 + c_l),
+        c_l = k^2 sn^2(l K'/Ls; k') / cn^2(l K'/Ls; k'),  l = 1 .. Ls-1,
+    with k' = sqrt(1 - k^2), K' the complete elliptic integral of modulus k'
+    (Jacobi elliptic functions), and d fixed so that 1 - R equioscillates
+    between +delta and -delta on [k, 1].  Returns (R(y), delta)."""
+    R, delta = _zolotarev_coeffs(Ls, k)
+    return R(y), delta
+
+
+def zolotarev_omega(Ls: int, lmin: float, lmax: float) -> np.ndarray:
+    """Chiu's optimal domain-wall weights: b_s = c_s = omega_s such that
+    (prod(1 + w x) - prod(1 - w x)) / (prod(1 + w x) + prod(1 - w x)) is
+    Zolotarev's approximation of sign(x) on lmin <= |x| <= lmax.  Both sides
+    have (1 + R) / (1 - R) = prod (1 + w_s x) / (1 - w_s x), so 1 / omega_s
+    are the Ls points of [lmin, lmax] where the approximation equals 1
+    (found by bracketing on a grid and bisection).  Sorted descending."""
+    k = lmin / lmax
+    R, _ = _zolotarev_coeffs(Ls, k)
+    y = np.geomspace(k, 1.0, 400001)
+    f = R(y) - 1.0
+    idx = np.nonzero(np.sign(f[:-1]) * np.sign(f[1:]) < 0)[0]
+    roots = []
+    for i in idx:
+        a, b = y[i], y[i + 1]
+        fa = f[i]
+        for _ in range(80):
+            mid = 0.5 * (a + b)
+            fm = float(R(np.array([mid]))[0]) - 1.0
+            if np.sign(fm) == np.sign(fa):
+                a, fa = mid, fm
+            else:
+                b = mid
+        roots.append(0.5 * (a + b))
+    if len(roots) != Ls:
+        raise ValueError(f"expected {Ls} crossings of 1, found {len(roots)}")
+    return np.sort(1.0 / (lmax * np.array(roots)))[::-1].copy()

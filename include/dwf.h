@@ -135,6 +135,14 @@ int dwf_lattice_maps(const dwf_lattice* lat, int* lex_of_site, int* nbr);
  * 2 <= Ls <= 16.  The op references lat (lat must outlive it). */
 int dwf_op_create(dwf_lattice* lat, int Ls, double M0, double m, double b, double c,
                   double alpha, dwf_op** out);
+/* The same with s-dependent coefficients: D_+^(s) = b[s] D_W + 1 and
+ * D_-^(s) = c[s] D_W - 1 in row s = 0..Ls-1 (paper s = 1..Ls) of
+ * eq. domainwall_general (Sec. 2.2: Shamir (1,0), Borici (1,1), Moebius
+ * b - c constant, and Chiu's optimal b_s = c_s = omega_s), Neff form by
+ * alpha as above.  b, c: host arrays of Ls finite doubles, copied.  The
+ * source -D_- P^dag (0,..,b4) of dwf_source_4d uses c[0] and c[Ls-1]. */
+int dwf_op_create_sdep(dwf_lattice* lat, int Ls, double M0, double m, const double* b, const double* c,
+                       double alpha, dwf_op** out);
 void dwf_op_destroy(dwf_op* op);
 
 /* out = D^(alpha) in (space = FULL5D, 5D canonical) or D^ in (EVEN5D, even

@@ -37,7 +37,8 @@ def build(force: bool = True) -> str:
 class _Params(ctypes.Structure):
     _fields_ = [("dims", ctypes.c_int * 4), ("antiperiodic_t", ctypes.c_int),
                 ("Ls", ctypes.c_int), ("M0", ctypes.c_double), ("m", ctypes.c_double),
-                ("b", ctypes.c_double), ("c", ctypes.c_double), ("alpha", ctypes.c_double)]
+                ("b", ctypes.c_double), ("c", ctypes.c_double), ("alpha", ctypes.c_double),
+                ("bs", ctypes.POINTER(ctypes.c_double)), ("cs", ctypes.POINTER(ctypes.c_double))]
 
 
 @dataclass(frozen=True)
@@ -50,6 +51,8 @@ class Params:
     c: float = 0.0
     alpha: float = 1.0
     antiperiodic_t: int = 1
+    bs: tuple = None   # s-dependent b_i (Ls values) or None: b for every s
+    cs: tuple = None   # s-dependent c_i (Ls values) or None: c for every s
 
     @property
     def V(self) -> int:
@@ -72,6 +75,18 @@ class Params:
         p.Ls = int(self.Ls)
         p.M0, p.m, p.b, p.c, p.alpha = (float(self.M0), float(self.m), float(self.b),
                                         float(self.c), float(self.alpha))
+        keep = []
+        for name in ("bs", "cs"):
+            v = getattr(self, name)
+            if v is None:
+                setattr(p, name, None)
+                continue
+            arr = (ctypes.c_double * int(self.Ls))(*[float(x) for x in v])
+            if len(v) != int(self.Ls):
+                raise ValueError(f"{name} needs Ls entries")
+            keep.append(arr)
+            setattr(p, name, ctypes.cast(arr, ctypes.POINTER(ctypes.c_double)))
+        p._keep = keep   # the arrays live as long as the struct
         return p
 
 

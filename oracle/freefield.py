@@ -145,3 +145,36 @@ def normal_spectrum_extremes(dims, Ls, M0, m, b, c, alpha, antiperiodic_t=True):
         lo = min(lo, s.min() ** 2)
         hi = max(hi, s.max() ** 2)
     return lo, hi
+
+
+# ---------------------------------------------------------------------------
+# s-dependent coefficients (Sec. 2.2: b_i, c_i depending on the row i).  For
+# b_s - c_s = kappa independent of s (Moebius-type, including Chiu's
+# b_s = c_s) the kernels H_s = (b_s + c_s) Ht with
+# Ht = g5 D_W (2 + kappa D_W)^-1 commute, and the 4D operator is
+#   D_eff = (1+m)/2 + (1-m)/2 g5 eps,
+#   eps = (prod_s (1 + H_s) - prod_s (1 - H_s)) / (prod_s (1 + H_s) + prod_s (1 - H_s)).
+# ---------------------------------------------------------------------------
+
+def eps_product(Ht, a):
+    """eps of the kernels a_s * Ht (Ht Hermitian), by eigendecomposition."""
+    w, v = np.linalg.eigh(0.5 * (Ht + Ht.conj().T))
+    P = np.prod(1 + np.outer(a, w), axis=0)
+    Q = np.prod(1 - np.outer(a, w), axis=0)
+    return (v * ((P - Q) / (P + Q))) @ v.conj().T
+
+
+def deff_from_dw_sdep(Dw, m, bs, cs):
+    bs, cs = np.asarray(bs, float), np.asarray(cs, float)
+    kappa = bs[0] - cs[0]
+    assert np.all(np.abs((bs - cs) - kappa) < 1e-14), "closed form needs b_s - c_s independent of s"
+    _, g5 = gammas()
+    n = Dw.shape[0]
+    G5 = np.kron(np.eye(n // 4), g5) if n != 4 else g5
+    Ht = hermitian_kernel(Dw, 0.5 * (1 + kappa), 0.5 * (1 - kappa))   # (b + c) = 1, (b - c) = kappa
+    return 0.5 * (1 + m) * np.eye(n) + 0.5 * (1 - m) * G5 @ eps_product(Ht, bs + cs)
+
+
+def g_from_deff(D, m):
+    n = D.shape[0]
+    return (np.linalg.inv(D) - np.eye(n)) / (1 - m)

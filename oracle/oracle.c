@@ -261,6 +261,10 @@ static int build_blocks(const or_params* p, or_block* blk) {
     return n;
 }
 
+/* coefficients of D_+^(i) and D_-^(i) in row i (i = 0..Ls-1) */
+static double coef_b(const or_params* p, int i) { return p->bs ? p->bs[i] : p->b; }
+static double coef_c(const or_params* p, int i) { return p->cs ? p->cs[i] : p->c; }
+
 static void apply_spin(const or_cplx* S, const or_cplx* in4, or_cplx* out4, long V, int adjoint) {
 #pragma omp parallel for schedule(static)
     for (long x = 0; x < V; ++x)
@@ -287,7 +291,8 @@ void or_dwf_apply(const or_params* p, const or_cplx* U, const or_cplx* in5, or_c
     memset(out5, 0, sizeof(or_cplx) * n4 * Ls);
     for (int k = 0; k < nb; ++k) {
         const or_block* B = &blk[k];
-        const double dw = B->kind == 0 ? p->b : p->c;   /* coefficient of D_W in D_kind */
+        /* coefficient of D_W in D_kind of this block's row */
+        const double dw = B->kind == 0 ? coef_b(p, B->row) : coef_c(p, B->row);
         const double id = B->kind == 0 ? 1.0 : -1.0;    /* coefficient of 1 in D_kind   */
         if (!dagger) {
             /* out_row += coef * D_kind (S in_col) */
@@ -336,7 +341,7 @@ void or_local_block(const or_params* p, or_cplx* Mloc) {
     const double dwdiag = 4.0 - p->M0;
     for (int k = 0; k < nb; ++k) {
         const or_block* B = &blk[k];
-        double dw = B->kind == 0 ? p->b : p->c;
+        double dw = B->kind == 0 ? coef_b(p, B->row) : coef_c(p, B->row);
         double id = B->kind == 0 ? 1.0 : -1.0;
         double f = B->coef * (dw * dwdiag + id);
         for (int sp = 0; sp < 4; ++sp)
@@ -596,8 +601,9 @@ void or_source_4d(const or_params* p, const or_cplx* U, const or_cplx* b4, or_cp
         int s = side == 0 ? 0 : p->Ls - 1;
         apply_spin(side == 0 ? Pp : Pm, b4, t, V, 0);
         or_wilson(p, U, t, w, 0, 3);
-        /* -D_- t = -(c D_W t - t) */
-        for (long i = 0; i < n4; ++i) b5[s * n4 + i] += -(p->c * w[i] - t[i]);
+        /* -D_-^(s) t = -(c_s D_W t - t) */
+        const double cs = coef_c(p, s);
+        for (long i = 0; i < n4; ++i) b5[s * n4 + i] += -(cs * w[i] - t[i]);
     }
     free(t);
     free(w);

@@ -46,6 +46,11 @@ typedef struct {
     double m;      /* quark mass */
     double b, c;   /* D_+ = b D_W + 1, D_- = c D_W - 1 (s-independent) */
     double alpha;  /* Neff parameter, alpha = 1 is the standard form */
+    /* s-dependent coefficients (Sec. 2.2: D_+^(i) = b_i D_W + 1 and
+     * D_-^(i) = c_i D_W - 1 in row i of the 5D matrix): Ls doubles each, or
+     * NULL to use b, c for every row */
+    const double* bs;
+    const double* cs;
 } or_params;
 
 long or_volume(const int dims[4]);

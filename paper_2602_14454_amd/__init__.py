@@ -66,6 +66,7 @@ SIGNATURES = {
     "dwf_lattice_set_gauge": (_i, [_vp, _vp, _i, _vp]),
     "dwf_lattice_maps": (_i, [_vp, _vp, _vp]),
     "dwf_op_create": (_i, [_vp, _i, _d, _d, _d, _d, _d, ctypes.POINTER(_vp)]),
+    "dwf_op_create_sdep": (_i, [_vp, _i, _d, _d, _dp, _dp, _d, ctypes.POINTER(_vp)]),
     "dwf_op_destroy": (None, [_vp]),
     "dwf_apply": (_i, [_vp, _i, _i, _i, _vp, _vp, _vp]),
     "dwf_apply_normal": (_i, [_vp, _i, _vp, _vp, _vp]),
@@ -385,12 +386,22 @@ class Op:
     """dwf_op: D^(alpha) on a lattice (the lattice must outlive the op)."""
 
     def __init__(self, lattice: Lattice, Ls, M0, m, b=1.0, c=0.0, alpha=1.0):
+        """b, c: numbers (s-independent) or sequences of Ls numbers (b_s, c_s, s = 0..Ls-1)."""
         lib = load()
         self.lattice = lattice
         self.params = OpParams(Ls, M0, m, b, c, alpha)
         h = ctypes.c_void_p()
-        _check(lib.dwf_op_create(lattice._h, int(Ls), float(M0), float(m), float(b), float(c), float(alpha),
-                                 ctypes.byref(h)), "dwf_op_create")
+        if isinstance(b, (int, float)) and isinstance(c, (int, float)):
+            _check(lib.dwf_op_create(lattice._h, int(Ls), float(M0), float(m), float(b), float(c), float(alpha),
+                                     ctypes.byref(h)), "dwf_op_create")
+        else:
+            bs = [float(v) for v in (b if not isinstance(b, (int, float)) else [b] * int(Ls))]
+            cs = [float(v) for v in (c if not isinstance(c, (int, float)) else [c] * int(Ls))]
+            if len(bs) != int(Ls) or len(cs) != int(Ls):
+                raise ValueError("b and c need Ls entries")
+            arr_b, arr_c = (ctypes.c_double * int(Ls))(*bs), (ctypes.c_double * int(Ls))(*cs)
+            _check(lib.dwf_op_create_sdep(lattice._h, int(Ls), float(M0), float(m), arr_b, arr_c, float(alpha),
+                                          ctypes.byref(h)), "dwf_op_create_sdep")
         self._h = h
         self.Ls = int(Ls)
 

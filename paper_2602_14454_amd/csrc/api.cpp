@@ -1,6 +1,7 @@
 // extern "C" entry points of libdwf (declared in include/dwf.h).  Every call
 // catches internal errors and turns them into status codes; the message is
 // kept per thread for dwf_last_error().
+#include <cmath>
 #include <complex>
 #include <cstring>
 #include <exception>
@@ -130,22 +131,35 @@ int dwf_lattice_maps(const dwf_lattice* lat, int* lex_of_site, int* nbr) {
     });
 }
 
-int dwf_op_create(dwf_lattice* lat, int Ls, double M0, double m, double b, double c, double alpha, dwf_op** out) {
+int dwf_op_create_sdep(dwf_lattice* lat, int Ls, double M0, double m, const double* b, const double* c,
+                       double alpha, dwf_op** out) {
     return guarded([&] {
-        DWF_REQUIRE(lat && out, DWF_EINVAL, "null argument");
+        DWF_REQUIRE(lat && out && b && c, DWF_EINVAL, "null argument");
         DWF_REQUIRE(Ls >= 2 && Ls <= LS_MAX, DWF_EDIMS, "Ls must be in [2, 16]");
+        for (int s = 0; s < Ls; ++s)
+            DWF_REQUIRE(std::isfinite(b[s]) && std::isfinite(c[s]), DWF_EINVAL, "non-finite b_s or c_s");
+        DWF_REQUIRE(std::isfinite(M0) && std::isfinite(m) && std::isfinite(alpha), DWF_EINVAL, "non-finite parameter");
         std::unique_ptr<dwf_op> op(new dwf_op());
         op->lat = lat;
         op->Ls = Ls;
         op->M0 = M0;
         op->m = m;
-        op->b = b;
-        op->c = c;
+        op->b.assign(b, b + Ls);
+        op->c.assign(c, c + Ls);
         op->alpha = alpha;
         setup_op(op.get());
         *out = op.release();
         return DWF_OK;
     });
+}
+
+int dwf_op_create(dwf_lattice* lat, int Ls, double M0, double m, double b, double c, double alpha, dwf_op** out) {
+    if (Ls < 2 || Ls > LS_MAX) {
+        set_error("Ls must be in [2, 16]");
+        return DWF_EDIMS;
+    }
+    const std::vector<double> bs(Ls, b), cs(Ls, c);
+    return dwf_op_create_sdep(lat, Ls, M0, m, bs.data(), cs.data(), alpha, out);
 }
 
 void dwf_op_destroy(dwf_op* op) { delete op; }

@@ -99,7 +99,9 @@ struct FifthDim {
     // per chirality chi (0: P+ = spins 0,1; 1: P- = spins 2,3), row-major Ls x Ls
     std::vector<double> T[2], M5[2], K[2], N[2], M[2], Minv[2], Q[2];
 };
-FifthDim build_fifth_dim(int Ls, double M0, double m, double b, double c, double alpha);
+// b, c: the coefficients b_s, c_s of D_+^(s), D_-^(s), s = 0..Ls-1
+FifthDim build_fifth_dim(int Ls, double M0, double m, const std::vector<double>& b, const std::vector<double>& c,
+                         double alpha);
 
 enum StoreKind { ST_F64 = 0, ST_F32 = 1, ST_BF16 = 2 };
 
@@ -126,7 +128,7 @@ struct dwf_lattice {
 // [2][16][16] in the compute type (zero padded beyond Ls).
 enum MatSlot {
     MAT_Q = 0, MAT_QT, MAT_MQMINV, MAT_G5MIT, MAT_G5MIT_MQMINV, MAT_MQG5KT, MAT_G5MT, MAT_HALFMINV,
-    MAT_MINV, MAT_M, MAT_MT, MAT_MHALFI, MAT_MHALFKTG5, MAT_IDENT, MAT_CHALF, NMAT
+    MAT_MINV, MAT_M, MAT_MT, MAT_MHALFI, MAT_MHALFKTG5, MAT_IDENT, MAT_CHALF, MAT_SRCLOC, NMAT
 };
 // Slots of the sparse pre-mix coefficient sets, each [d0 | d1 | e0 | e1] x 16.
 enum PreSlot { PRE_K = 0, PRE_G5 = 1, NPRE };
@@ -136,7 +138,13 @@ constexpr int PRE_ELEMS = 4 * 16;
 struct dwf_op {
     dwf_lattice* lat = nullptr;
     int Ls = 0;
-    double M0 = 0, m = 0, b = 0, c = 0, alpha = 1;
+    double M0 = 0, m = 0, alpha = 1;
+    std::vector<double> b, c;   // b_s, c_s, s = 0..Ls-1 (Sec. 2.2; constant for s-independent (b, c))
+    bool any_c() const {
+        for (double v : c)
+            if (v != 0.0) return true;
+        return false;
+    }
     dwf::FifthDim fd;
     dwf::DevBuf mats[2];   // compute kind 0: double, 1: float; NMAT * MAT_ELEMS
     dwf::DevBuf pres[2];   // NPRE * PRE_ELEMS

@@ -8,12 +8,14 @@
 // writes P A^-1 P^dag; the relation itself fixes P A P^dag, and only the
 // locality of T matters for its argument.)
 //
-// Writing D_+ = b D_W + 1, D_- = c D_W - 1 (Sec. 2.2) and collecting the
-// s-structure of eq. domainwall_general into the shift M5
+// Writing D_+^(s) = b_s D_W + 1, D_-^(s) = c_s D_W - 1 (Sec. 2.2; row s of
+// eq. domainwall_general carries the coefficients of that s) and collecting
+// the s-structure into the shift M5
 //   (M5 psi)_s = P_- psi_{s+1} + P_+ psi_{s-1},  P_+ psi_0 -> -m P_+ psi_Ls,
 //                                                P_- psi_{Ls+1} -> -m P_- psi_1,
-// gives D^(alpha) = D_W K + N with K = (b + c M5) T and N = (1 - M5) T, both
-// real Ls x Ls per chirality.  With D_W = (4 - M0) - H/2 (H the hopping term):
+// gives D^(alpha) = D_W K + N with K = (B + C M5) T and N = (1 - M5) T,
+// B = diag(b_s), C = diag(c_s) acting on the row index, all real Ls x Ls per
+// chirality (s-independent (b, c): K = (b + c M5) T).  With D_W = (4 - M0) - H/2 (H the hopping term):
 //   D = M - (1/2) H K,  M = (4 - M0) K + N   (site-diagonal, D_ee = D_oo = M),
 // and the even-odd Schur operator of Sec. 2.3 becomes
 //   D^ = 1 - (1/4) M^-1 H_eo Q H_oe K,  Q = K M^-1,
@@ -62,7 +64,9 @@ static std::vector<double> inverse(std::vector<double> A, int n) {
     return X;
 }
 
-FifthDim build_fifth_dim(int Ls, double M0, double m, double b, double c, double alpha) {
+FifthDim build_fifth_dim(int Ls, double M0, double m, const std::vector<double>& b, const std::vector<double>& c,
+                         double alpha) {
+    DWF_REQUIRE((int)b.size() == Ls && (int)c.size() == Ls, DWF_EINVAL, "b and c need Ls entries");
     FifthDim f;
     f.Ls = Ls;
     const int n = Ls;
@@ -80,10 +84,12 @@ FifthDim build_fifth_dim(int Ls, double M0, double m, double b, double c, double
             M5[(n - 1) * n + 0] += -m;
         }
         std::vector<double> bcM5(n * n), omM5(n * n);
-        for (int i = 0; i < n * n; ++i) {
-            bcM5[i] = b * I[i] + c * M5[i];
-            omM5[i] = I[i] - M5[i];
-        }
+        for (int r = 0; r < n; ++r)
+            for (int q = 0; q < n; ++q) {
+                const int i = r * n + q;
+                bcM5[i] = b[r] * I[i] + c[r] * M5[i];
+                omM5[i] = I[i] - M5[i];
+            }
         std::vector<double> K = matmul(bcM5, T, n);
         std::vector<double> N = matmul(omM5, T, n);
         std::vector<double> M(n * n);

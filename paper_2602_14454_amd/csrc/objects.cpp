@@ -1,6 +1,8 @@
 // Lattice geometry, gauge-link packing and operator coefficient setup.
+#include <algorithm>
 #include <cmath>
 #include <complex>
+#include <utility>
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
@@ -47,7 +49,8 @@ static uint16_t host_f32_to_bf16(float f) {
 // tile inside an octant and x-fastest inside a tile, so that the columns a
 // die reads are re-read while they are still in its L2.  Tile extents
 // ($DWF_TCOL_TILE="tx,ty,tz", default 4,4,4) are shrunk to divide the
-// octant.
+// octant; $DWF_TCOL_CURVE=morton visits an octant's positions along the
+// Morton (bit-interleaved) curve instead of by tiles.
 static void choose_brick(const int dims[4], int b[3]) {
     b[0] = dims[0];
     b[1] = dims[1];
@@ -92,6 +95,31 @@ static std::vector<int> tcol_spatial_order(const int dims[4]) {
     }
     std::vector<int> order;
     order.reserve((size_t)dims[0] * dims[1] * dims[2]);
+    const char* curve = std::getenv("DWF_TCOL_CURVE");
+    if (curve && std::strcmp(curve, "morton") == 0) {
+        // inside each octant, positions sorted by the Morton code of their
+        // octant-relative coordinates (bit-interleaved x, y, z)
+        auto morton = [](unsigned x, unsigned y, unsigned z) {
+            unsigned long long code = 0;
+            for (int bit = 0; bit < 10; ++bit)
+                code |= ((unsigned long long)((x >> bit) & 1u) << (3 * bit)) |
+                        ((unsigned long long)((y >> bit) & 1u) << (3 * bit + 1)) |
+                        ((unsigned long long)((z >> bit) & 1u) << (3 * bit + 2));
+            return code;
+        };
+        for (int oz = 0; oz < dims[2]; oz += oct[2])
+            for (int oy = 0; oy < dims[1]; oy += oct[1])
+                for (int ox = 0; ox < dims[0]; ox += oct[0]) {
+                    std::vector<std::pair<unsigned long long, int>> v;
+                    for (int z = oz; z < oz + oct[2]; ++z)
+                        for (int y = oy; y < oy + oct[1]; ++y)
+                            for (int x = ox; x < ox + oct[0]; ++x)
+                                v.push_back({morton(x - ox, y - oy, z - oz), x + dims[0] * (y + dims[1] * z)});
+                    std::sort(v.begin(), v.end());
+                    for (const auto& e : v) order.push_back(e.second);
+                }
+        return order;
+    }
     for (int oz = 0; oz < dims[2]; oz += oct[2])
         for (int oy = 0; oy < dims[1]; oy += oct[1])
             for (int ox = 0; ox < dims[0]; ox += oct[0])
@@ -288,9 +316,15 @@ void setup_op(dwf_op* op) {
     put_dense(h, MAT_MHALFI, Ls, I, one, -0.5);
     put_dense(h, MAT_MHALFKTG5, Ls, Kt, g5, -0.5);
     put_dense(h, MAT_IDENT, Ls, I, one, 1.0);
-    // (c/2) * identity on all 16 rows: used with fields of any s-extent
-    for (int chi = 0; chi < 2; ++chi)
-        for (int r = 0; r < 16; ++r) h[(size_t)MAT_CHALF * MAT_ELEMS + (chi * 16 + r) * 16 + r] = 0.5 * op->c;
+    // the source pair (s = 1 and s = Ls as slices 0 and 1):
+    // -D_-^(s) y = (c_s / 2) H y + (1 - c_s (4 - M0)) y on each slice
+    const double cf = op->c[0], cl = op->c[Ls - 1];
+    for (int chi = 0; chi < 2; ++chi) {
+        h[(size_t)MAT_CHALF * MAT_ELEMS + (chi * 16 + 0) * 16 + 0] = 0.5 * cf;
+        h[(size_t)MAT_CHALF * MAT_ELEMS + (chi * 16 + 1) * 16 + 1] = 0.5 * cl;
+        h[(size_t)MAT_SRCLOC * MAT_ELEMS + (chi * 16 + 0) * 16 + 0] = 1.0 - cf * (4.0 - op->M0);
+        h[(size_t)MAT_SRCLOC * MAT_ELEMS + (chi * 16 + 1) * 16 + 1] = 1.0 - cl * (4.0 - op->M0);
+    }
     op->mats_host = h;
 
     std::vector<double> pre((size_t)NPRE * PRE_ELEMS, 0.0);

@@ -11,7 +11,8 @@
 //   D^dag    : out_p = (-1/2 K^T g5) H g5 x_{1-p} + M^T x_p
 //   b~_e     : (1/2 Minv) H_eo (Q b_o) + Minv b_e              (Schur RHS)
 //   x_o      : (1/2 Minv) H_oe K x_e + Minv b_o                 (reconstruction)
-//   -D_- P^dag (0,..,b4): (c/2) H y + (1 - c(4 - M0)) y on the pair (P+ b4, P- b4)
+//   -D_- P^dag (0,..,b4): (c_s/2) H y + (1 - c_s(4 - M0)) y on the pair (P+ b4, P- b4),
+//                       s = 1 and s = Ls
 #include "ops.h"
 
 #include "blas.h"
@@ -35,7 +36,7 @@ HopParams hop_params(const dwf_op* op, int kind, int out_parity, const void* in,
     P.links = static_cast<const char*>(L->links[kind].p) + (size_t)out_parity * link_elems_parity(Vhp, (int)cb) * cb;
     P.nbr = L->nbr.as<int>() + (size_t)out_parity * 8 * Vhp;
     P.pre = pre_slot >= 0 ? op->pre(kind, pre_slot) : nullptr;
-    P.pre_mode = pre_slot < 0 ? 0 : (pre_slot == PRE_K && op->c != 0.0 ? 2 : 1);
+    P.pre_mode = pre_slot < 0 ? 0 : (pre_slot == PRE_K && op->any_c() ? 2 : 1);
     if (P.pre_mode == 1 && pre_slot == PRE_K) {
         // the kernel factors the upper-chirality diagonal out of the hop sum;
         // a zero entry takes the general pre-mix path instead
@@ -159,9 +160,8 @@ void reconstruct_odd(const dwf_op* op, int kind, void* x_o, const void* x_e, con
 
 void source_pair(const dwf_op* op, void* out_pair_p, const void* pair_other, const void* pair_p, int parity,
                  hipStream_t st) {
-    const double diag = 1.0 - op->c * (4.0 - op->M0);
-    hop(op, ST_F64, parity, pair_other, pair_p, out_pair_p, -1, MAT_CHALF, -1, diag, nullptr, 0, 0, nullptr, 0,
-        1, st, 2);
+    hop(op, ST_F64, parity, pair_other, pair_p, out_pair_p, -1, MAT_CHALF, MAT_SRCLOC, 0.0, nullptr, 0, 0, nullptr,
+        0, 1, st, 2);
 }
 
 }  // namespace dwf

@@ -497,7 +497,7 @@ double residual_4d(const dwf_op* op, const void* x4, const void* b4, double tol_
     om.Ls = o1.Ls = Ls;
     om.M0 = o1.M0 = op->M0;
     om.b = o1.b = op->b;
-    om.c = o1.c = op->c;
+    om.c = o1.c = op->c;   // b_s, c_s
     om.alpha = o1.alpha = 1.0;
     om.m = op->m;
     o1.m = 1.0;
