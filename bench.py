@@ -312,7 +312,21 @@ def run_learned(args):
         return p
 
     M0 = dwf.PtcModel(8, seed=1, init_scale=0.02)
+    # cost of one network application against one hop of D^ (FP32, same lattice)
+    lat_b, op_b = op_of(test_f[0])
+    net_ms = M.bench_apply(op_b, nrep=20)
+    hop_ms, _ = op_b.bench_hop(prec=dwf.F32, nrep=50)
+    log(f"network application {net_ms:.3f} ms = {net_ms / hop_ms:.1f} FP32 hops ({hop_ms * 1e3:.1f} us each)")
+    del op_b, lat_b
+
+    def fgcr_r(model, k):
+        p = fgcr_params(model)
+        p.restart = k
+        return p
+
     variants = {"fgcr_trained": fgcr_params(M), "fgcr_identity": fgcr_params(None),
+                "fgcr_trained_restart32": fgcr_r(M, 32), "fgcr_identity_restart32": fgcr_r(None, 32),
+                "fgcr_trained_restart64": fgcr_r(M, 64), "fgcr_identity_restart64": fgcr_r(None, 64),
                 "fgcr_untrained": fgcr_params(M0),
                 "dc_f32_cgnr": dwf.default_params(algo=dwf.ALGO_DC, inner_prec=dwf.F32, tol=1e-10, check_every=8),
                 "fp64_cgnr": dwf.default_params(tol=1e-10, check_every=8)}
@@ -344,6 +358,13 @@ def run_learned(args):
                         "seconds": t_train, "loss_before": loss0, "loss_after": loss1,
                         "loss_first10": float(np.mean(h1[:10])), "loss_last50": float(np.mean(h2[-50:]))},
            "iteration_reduction_vs_identity": 1.0 - summary["fgcr_trained"]["mean_iters"] / base,
+           "network_application_ms": net_ms, "fp32_hop_ms": hop_ms,
+           "network_cost_in_hops": net_ms / hop_ms,
+           "cost_model": ("an FGCR iteration applies A = D^dag D^ (4 hops) and, with the network, one network "
+                          "application; hop-equivalents per solve = iters x (4 + network_cost_in_hops)"),
+           "hop_equivalents": {k: v["mean_iters"] * (4.0 + (net_ms / hop_ms if k.startswith("fgcr_trained")
+                                                            or k == "fgcr_untrained" else 0.0))
+                               for k, v in summary.items() if k.startswith("fgcr")},
            "speedup_vs_fp64": summary["fp64_cgnr"]["mean_seconds"] / summary["fgcr_trained"]["mean_seconds"],
            "variants": summary}
     print(json.dumps(out))
@@ -491,6 +512,68 @@ def run_sdep_study(args):
     print(json.dumps(out))
 
 
+def run_schur_study(args):
+    """Left against right even-odd Schur form (Sec. 2.3: the alpha of the Neff
+    form cancels in the right form): paper-mode FP32 CGNR iterations against
+    alpha on three 16^4 fields, Ls = 8, M0 = 1.8, m = 0.01, for three (b, c),
+    and the FP64 CGNR time of both forms at alpha = 1 and 0.5."""
+    import numpy as np
+    import torch
+
+    import dwfgen
+    import paper_2602_14454_amd as dwf
+
+    dev = "cuda:0"
+    dims, Ls, M0, m = (16, 16, 16, 16), 8, 1.8, 0.01
+    V = int(np.prod(dims))
+    alphas = [1.0, 0.8, 0.6, 0.5, 0.4]
+    rows = []
+    t0 = time.time()
+    for seed in (701, 702, 703):
+        U = dwfgen.make_links(dims, 0.5, seed, rho=0.1, nsmear=3)
+        lat = dwf.Lattice(dims)
+        lat.set_gauge(U)
+        b4 = torch.from_numpy(dwfgen.gaussian_source_4d(dims, seed + 1000)).to(dev)
+        b5 = torch.empty((Ls, V, 4, 3), dtype=torch.complex128, device=dev)
+        x5 = torch.zeros_like(b5)
+        for cname, b, c in (("shamir", 1.0, 0.0), ("moebius", 1.5, 0.5), ("borici", 1.0, 1.0)):
+            for al in alphas:
+                op = dwf.Op(lat, Ls, M0, m, b, c, al)
+                op.source_4d(b5, b4)
+                row = {"seed": seed, "coef": cname, "alpha": al}
+                for form, schur in (("left", 0), ("right", 1)):
+                    x5.zero_()
+                    st, info = op.solve(x5, b5, dwf.default_params(check_every=8, paper_mode=1, inner_prec=dwf.F32,
+                                                                   schur=schur, maxiter=20000))
+                    row[f"{form}_paper_mode_f32_iters"] = info.iters
+                    if al in (1.0, 0.5):
+                        x5.zero_()
+                        torch.cuda.synchronize()
+                        t = time.perf_counter()
+                        st, info = op.solve(x5, b5, dwf.default_params(tol=1e-10, check_every=8, schur=schur))
+                        torch.cuda.synchronize()
+                        row[f"{form}_fp64_cgnr_iters"] = info.iters
+                        row[f"{form}_fp64_cgnr_seconds"] = time.perf_counter() - t
+                        row[f"{form}_true_res5"] = info.true_res5
+                rows.append(row)
+                log(f"[{time.time() - t0:5.0f}s] seed {seed} {cname} alpha {al}: left {row['left_paper_mode_f32_iters']} "
+                    f"right {row['right_paper_mode_f32_iters']} iterations")
+                del op
+    summary = {}
+    for cname in ("shamir", "moebius", "borici"):
+        ent = {}
+        for form in ("left", "right"):
+            it = {al: float(np.mean([r[f"{form}_paper_mode_f32_iters"] for r in rows
+                                     if r["coef"] == cname and r["alpha"] == al])) for al in alphas}
+            ent[form] = {"mean_iters_by_alpha": it, "reduction_at_best_alpha": 1.0 - min(it.values()) / it[1.0]}
+        summary[cname] = ent
+    print(json.dumps({"metric": "paper-mode FP32 CGNR iterations against alpha, left vs right even-odd Schur form",
+                      "data": "synthetic", "n_gpus": 1,
+                      "config": {"lattice": list(dims), "Ls": Ls, "M0": M0, "m": m,
+                                 "fields": "exp(i 0.5 H) + 3 stout rho=0.1, seeds 701-703"},
+                      "summary": summary, "rows": rows, "seconds": time.time() - t0}))
+
+
 def cpu_model():
     try:
         with open("/proc/cpuinfo") as fh:
@@ -574,6 +657,8 @@ def main():
     ap.add_argument("--train-steps", type=int, default=1500)
     ap.add_argument("--alpha-scan", action="store_true",
                     help="run the alpha scan instead: iteration counts against alpha for three (b, c) choices")
+    ap.add_argument("--schur-study", action="store_true",
+                    help="run the left vs right even-odd Schur comparison against alpha on 16^4 instead")
     ap.add_argument("--sdep-study", action="store_true",
                     help="run the alpha x (b, c) x Ls x m iteration / condition-number study on 16^4 instead")
     ap.add_argument("--spectrum", action="store_true",
@@ -602,6 +687,9 @@ def main():
         return
     if args.sdep_study:
         run_sdep_study(args)
+        return
+    if args.schur_study:
+        run_schur_study(args)
         return
     dev = "cuda:0"
     cfg = dict(CONFIGS[args.config])

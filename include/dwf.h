@@ -86,6 +86,12 @@ typedef struct {
     int      autotune;    /* batched solves: 0 cached tiles or defaults, 1 tune when not cached,
                              2 always re-tune */
     int      use_graph;   /* batched solves: 1 replay the CG iteration body as a HIP graph */
+    int      schur;       /* single solves: 0 the left Schur system (1 - Dee^-1 Deo Doo^-1 Doe) x_e = b~_e
+                             (the solver; Sec. 2.3 eq. even-odd_linear_equation); 1 the right form
+                             (1 - Deo Doo^-1 Doe Dee^-1) y_e = b'_e, x_e = Dee^-1 y_e (Sec. 2.3
+                             eq. another_even-odd_linear_equation), CGNR on its normal equations,
+                             composed from unfused kernels (algo CGNR or DC only); the alpha of the
+                             Neff form cancels in it, the measurement of that claim */
 } dwf_solve_params;
 
 /* Solve report.  Against the survey's sketch of this struct: `iters` is the
@@ -327,6 +333,11 @@ int dwf_ptc_load(const char* path, dwf_ptc** out);
  * mean kernel time in ms and the algorithmic bytes of one launch. */
 int dwf_bench_hop(const dwf_op* op, int prec, int nrep, double* ms_per_launch,
                   double* bytes_per_launch, void* stream);
+
+/* Times `nrep` applications of the learned preconditioner (its three layer
+ * kernels on internal FP32 fields of `op`, seeded non-zero input) with HIP
+ * events on `stream`; writes the mean time of one application in ms. */
+int dwf_ptc_bench_apply(dwf_ptc* m, const dwf_op* op, int nrep, double* ms_per_apply, void* stream);
 
 /* Times `nrep` launches of a plain 16-byte-vector copy of `bytes` bytes
  * (device buffers owned by the library); used to calibrate memory counters. */

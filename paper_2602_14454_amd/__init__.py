@@ -42,7 +42,7 @@ class SolveParams(ctypes.Structure):
                 ("inner_prec", ctypes.c_int), ("inner_tol", ctypes.c_double),
                 ("check_every", ctypes.c_int), ("paper_mode", ctypes.c_int),
                 ("ptc_model", ctypes.c_void_p), ("restart", ctypes.c_int),
-                ("autotune", ctypes.c_int), ("use_graph", ctypes.c_int)]
+                ("autotune", ctypes.c_int), ("use_graph", ctypes.c_int), ("schur", ctypes.c_int)]
 
 
 class SolveInfo(ctypes.Structure):
@@ -101,6 +101,7 @@ SIGNATURES = {
     "dwf_ptc_save": (_i, [_vp, ctypes.c_char_p]),
     "dwf_ptc_load": (_i, [ctypes.c_char_p, ctypes.POINTER(_vp)]),
     "dwf_bench_copy": (_i, [ctypes.c_size_t, _i, _dp, _vp]),
+    "dwf_ptc_bench_apply": (_i, [_vp, _vp, _i, _dp, _vp]),
     "dwf_status_string": (ctypes.c_char_p, [_i]),
     "dwf_last_error": (ctypes.c_char_p, []),
 }
@@ -246,6 +247,13 @@ class PtcModel:
     def apply(self, op, out_e, in_e, stream=None) -> None:
         _check(load().dwf_ptc_apply(self._h, op._h, _dev_ptr(out_e), _dev_ptr(in_e), _stream(stream)),
                "dwf_ptc_apply")
+
+    def bench_apply(self, op, nrep=20, stream=None) -> float:
+        """Mean time (ms) of one network application on op's lattice (HIP events)."""
+        ms = ctypes.c_double()
+        _check(load().dwf_ptc_bench_apply(self._h, op._h, int(nrep), ctypes.byref(ms), _stream(stream)),
+               "dwf_ptc_bench_apply")
+        return ms.value
 
     def gradient(self, op, r_e, e_e, stream=None):
         """(loss, (G1, G2)) with G = dL/dRe W + i dL/dIm W (complex64)."""

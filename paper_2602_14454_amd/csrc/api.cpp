@@ -366,6 +366,8 @@ int dwf_solve(const dwf_op* op, void* x5, const void* b5, const dwf_solve_params
                     DWF_EINVAL, "unsupported algorithm");
         DWF_REQUIRE(!(p->algo == DWF_ALGO_FGCR_LEARNED && p->paper_mode), DWF_EINVAL,
                     "paper_mode applies to CGNR only");
+        DWF_REQUIRE(p->schur == 0 || (p->schur == 1 && (p->algo == DWF_ALGO_CGNR || p->algo == DWF_ALGO_DC)),
+                    DWF_EINVAL, "schur: 0 (left) for every algorithm, 1 (right) with CGNR or DC only");
         return solve(op, x5, b5, p, info, S(stream));
     });
 }
@@ -435,6 +437,7 @@ int dwf_solve_batch(int n, const dwf_op* const* ops, void* const* x5, const void
         dwf_solve_params_default(&def);
         def.algo = DWF_ALGO_DC;
         def.check_every = 8;
+        DWF_REQUIRE(!prm || prm->schur == 0, DWF_EINVAL, "batched solves use the left Schur system (schur = 0)");
         return solve_batch(n, ops, x5, b5, nrhs, prm ? prm : &def, infos, S(stream));
     });
 }
@@ -540,6 +543,33 @@ int dwf_ptc_apply(dwf_ptc* m, const dwf_op* op, void* out_e, const void* in_e, v
         m->forward(op, a.as<float2>(), b.as<float2>(), st);
         unpack_half(ST_F32, out_e, b.p, lex, L->Vh, L->Vhp, op->Ls, st);
         DWF_HIP(hipStreamSynchronize(st));
+        return DWF_OK;
+    });
+}
+
+int dwf_ptc_bench_apply(dwf_ptc* m, const dwf_op* op, int nrep, double* ms_per_apply, void* stream) {
+    return guarded([&] {
+        DWF_REQUIRE(m && op && nrep > 0 && ms_per_apply, DWF_EINVAL, "bad argument");
+        const dwf_lattice* L = op->lat;
+        DWF_REQUIRE(L->has_gauge, DWF_ESTATE, "gauge field not set");
+        hipStream_t st = S(stream);
+        const long n = ptc_field_elems(op);
+        DevBuf a(8 * (size_t)n), b(8 * (size_t)n), t(16 * (size_t)n);
+        random_fill_f64(t.p, (long)op->Ls * 12, L->Vh, L->Vhp, 0x7ee5ULL, st);
+        convert(ST_F32, ST_F64, a.p, t.p, n, st, L->Vhp);
+        m->forward(op, a.as<float2>(), b.as<float2>(), st);   // warm-up (workspace)
+        hipEvent_t e0, e1;
+        DWF_HIP(hipEventCreate(&e0));
+        DWF_HIP(hipEventCreate(&e1));
+        DWF_HIP(hipEventRecord(e0, st));
+        for (int i = 0; i < nrep; ++i) m->forward(op, a.as<float2>(), b.as<float2>(), st);
+        DWF_HIP(hipEventRecord(e1, st));
+        DWF_HIP(hipEventSynchronize(e1));
+        float ms = 0;
+        DWF_HIP(hipEventElapsedTime(&ms, e0, e1));
+        DWF_HIP(hipEventDestroy(e0));
+        DWF_HIP(hipEventDestroy(e1));
+        *ms_per_apply = ms / nrep;
         return DWF_OK;
     });
 }

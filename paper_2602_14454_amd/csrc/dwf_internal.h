@@ -128,7 +128,7 @@ struct dwf_lattice {
 // [2][16][16] in the compute type (zero padded beyond Ls).
 enum MatSlot {
     MAT_Q = 0, MAT_QT, MAT_MQMINV, MAT_G5MIT, MAT_G5MIT_MQMINV, MAT_MQG5KT, MAT_G5MT, MAT_HALFMINV,
-    MAT_MINV, MAT_M, MAT_MT, MAT_MHALFI, MAT_MHALFKTG5, MAT_IDENT, MAT_CHALF, MAT_SRCLOC, NMAT
+    MAT_MINV, MAT_M, MAT_MT, MAT_MHALFI, MAT_MHALFKTG5, MAT_IDENT, MAT_CHALF, MAT_SRCLOC, MAT_MIT, NMAT
 };
 // Slots of the sparse pre-mix coefficient sets, each [d0 | d1 | e0 | e1] x 16.
 enum PreSlot { PRE_K = 0, PRE_G5 = 1, NPRE };

@@ -316,6 +316,7 @@ void setup_op(dwf_op* op) {
     put_dense(h, MAT_MHALFI, Ls, I, one, -0.5);
     put_dense(h, MAT_MHALFKTG5, Ls, Kt, g5, -0.5);
     put_dense(h, MAT_IDENT, Ls, I, one, 1.0);
+    put_dense(h, MAT_MIT, Ls, Mit, one, 1.0);
     // the source pair (s = 1 and s = Ls as slices 0 and 1):
     // -D_-^(s) y = (c_s / 2) H y + (1 - c_s (4 - M0)) y on each slice
     const double cf = op->c[0], cl = op->c[Ls - 1];

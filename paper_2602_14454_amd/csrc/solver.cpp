@@ -135,6 +135,77 @@ int cgnr(const dwf_op* op, CgWork& W, const void* b_kp, double tol_rel, int maxi
     return k;
 }
 
+// CG on the normal equations of the right-preconditioned Schur operator
+// (Sec. 2.3, eq. another_even-odd_linear_equation)
+//   D_R = 1 - D_eo D_oo^-1 D_oe D_ee^-1 = M D^ M^-1   (D_ee = D_oo = M),
+// D_R^dag = M^-T D^dag M^T (M real per chirality), composed from the local
+// mixes and the D^ hops: D_R^dag D_R y = D_R^dag b from y = 0, same
+// stopping rule as cgnr; y in W.x.  The alpha factors of the Neff form cancel
+// in D_R (D^(alpha) = D T with T 5D-local), so its iterations do not depend on
+// alpha.  This path measures that claim; the fused left form is the solver.
+static int cgnr_right(const dwf_op* op, CgWork& W, const void* b_kp, double tol_rel, int maxiter, int check_every,
+                      hipStream_t st, double* final_rel, bool* nan_seen) {
+    const long n = W.n;
+    const long Vhp = op->lat->Vhp;
+    double* partial = W.partial.as<double>();
+    double* scal = W.scal.as<double>();
+    Pinned& hs = W.hs;
+    if (check_every < 1) check_every = 1;
+    const size_t pbytes = complex_bytes_of(W.kp) * (size_t)n;
+    if (!W.p.p) W.p.alloc(pbytes);
+    if (!W.ra.p) W.ra.alloc(pbytes);
+    if (!W.rb.p) W.rb.alloc(pbytes);
+    void *ra = W.ra.p, *rb = W.rb.p;
+    auto apply_rdag = [&](void* out, const void* in) {   // out = M^-T D^dag M^T in
+        mix(op, W.kp, in, rb, MAT_MT, nullptr, 1, st);
+        apply_dhat(op, W.kp, 1, ra, rb, W.t.p, W.v.p, 1, st);
+        mix(op, W.kp, ra, out, MAT_MIT, nullptr, 1, st);
+    };
+    DWF_HIP(hipMemsetAsync(W.scal.p, 0, CG_NSLOTS * sizeof(double), st));
+    apply_rdag(W.w.p, b_kp);
+    convert(W.kx, W.kp, W.r.p, W.w.p, n, st, Vhp);
+    convert(W.kp, W.kx, W.p.p, W.r.p, n, st, Vhp);
+    DWF_HIP(hipMemsetAsync(W.x.p, 0, complex_bytes_of(W.kx) * n, st));
+    norm2_partial(W.kx, W.r.p, n, partial, st);
+    finalize(partial, blas_grid(n), 1, scal + CG_RR, 0, st);
+    read_scalars(scal, hs, st);
+    const double rr0 = hs.h[CG_RR];
+    *nan_seen = !std::isfinite(rr0);
+    if (rr0 == 0.0 || *nan_seen) {
+        if (final_rel) *final_rel = 0.0;
+        return 0;
+    }
+    const double stop = tol_rel * tol_rel * rr0;
+    double rr = rr0;
+    int k = 0;
+    while (k < maxiter) {
+        // q = D_R p = M D^ M^-1 p, alpha = rr / |q|^2
+        mix(op, W.kp, W.p.p, ra, MAT_MINV, nullptr, 1, st);
+        apply_dhat(op, W.kp, 0, rb, ra, W.t.p, W.v.p, 1, st);
+        mix(op, W.kp, rb, W.w.p, MAT_M, partial, 1, st);
+        finalize(partial, mix_partials(op, 1), 1, scal, 1, st);
+        // w = D_R^dag q; x += alpha p, r -= alpha w
+        mix(op, W.kp, W.w.p, rb, MAT_MT, nullptr, 1, st);
+        apply_dhat(op, W.kp, 1, ra, rb, W.t.p, W.v.p, 1, st);
+        mix(op, W.kp, ra, W.w.p, MAT_MIT, nullptr, 1, st);
+        cg_update_xr(W.kx, W.kp, W.x.p, W.r.p, W.p.p, W.w.p, n, scal + CG_ALPHA, partial, st, Vhp);
+        finalize(partial, blas_grid(n), 1, scal, 2, st);
+        cg_update_p(W.kx, W.kp, W.p.p, W.r.p, n, scal + CG_BETA, st, Vhp);
+        ++k;
+        if (k % check_every == 0 || k == maxiter) {
+            read_scalars(scal, hs, st);
+            rr = hs.h[CG_RR];
+            if (hs.h[CG_NANFLAG] != 0.0 || !std::isfinite(rr)) {
+                *nan_seen = true;
+                break;
+            }
+            if (rr <= stop) break;
+        }
+    }
+    if (final_rel) *final_rel = std::sqrt(rr / rr0);
+    return k;
+}
+
 // |v|^2 of a half field (device reduction, host result)
 static double norm2_host(int kind, const void* v, long n, double* partial, double* scal, Pinned& hs,
                          hipStream_t st) {
@@ -360,6 +431,7 @@ int solve(const dwf_op* op, void* x5, const void* b5, const dwf_solve_params* pr
         rel5 = r5;
         converged = !nan_seen && r5 <= tol;
     }
+    const bool right_schur = prm->schur == 1;
     // flexible GCR with the learned preconditioner as the inner solver (FP32);
     // on failure (NaN, stagnation) the solve falls back to CGNR
     bool use_fgcr = prm->algo == DWF_ALGO_FGCR_LEARNED;
@@ -387,6 +459,15 @@ int solve(const dwf_op* op, void* x5, const void* b5, const dwf_solve_params* pr
                 continue;
             }
             xin = FW->x.p;
+        } else if (right_schur) {
+            // the right system for the current residual: D_R y = M r^, then x_e += M^-1 y
+            mix(op, ST_F64, rh.p, te.p, MAT_M, nullptr, 1, st);
+            convert(kp, ST_F64, rin.p, te.p, n, st, Vhp);
+            it = cgnr_right(op, *W, rin.p, itol, maxiter - total, prm->check_every, st, &last_inner_rel, &nan_seen);
+            total += it;
+            convert(ST_F64, kx, te.p, W->x.p, n, st, Vhp);
+            mix(op, ST_F64, te.p, to.p, MAT_MINV, nullptr, 1, st);
+            xin = to.p;
         } else {
             it = cgnr(op, *W, rin.p, itol, maxiter - total, prm->check_every, st, &last_inner_rel, &nan_seen);
             total += it;
@@ -394,7 +475,7 @@ int solve(const dwf_op* op, void* x5, const void* b5, const dwf_solve_params* pr
         }
         ++outer;
         if (nan_seen) break;
-        axpby(ST_F64, kx, xe.p, xin, n, nullptr, 1.0, nullptr, 1.0, nullptr, st, Vhp);
+        axpby(ST_F64, right_schur ? ST_F64 : kx, xe.p, xin, n, nullptr, 1.0, nullptr, 1.0, nullptr, st, Vhp);
         // r^ = b~ - D^ xe (FP64), formed where D^ xe was written; the buffers
         // then trade names so that rh holds r^.  r5_e = -M r^ with |M r^|^2
         // reduced by the mix itself; r5_o = 0 exactly after reconstruction.

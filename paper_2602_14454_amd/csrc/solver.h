@@ -29,6 +29,7 @@ struct CgWork {
     // being read and written by every iteration
     int ring_len = 0;
     DevBuf ring, alphas;
+    DevBuf ra, rb;   // temporaries of the right-preconditioned Schur CG (allocated on first use)
     CgWork(const dwf_op* op, int kx, int kp, int nrhs);
 };
 

@@ -191,3 +191,51 @@ def test_workspace_reuse_across_solves_and_after_an_error():
                 first = xg
             else:
                 assert np.array_equal(first, xg)
+
+
+@pytest.mark.parametrize("b,c", [(1.0, 0.0), (1.5, 0.5)])
+def test_right_schur_solve_and_alpha_independence(b, c):
+    """The right-preconditioned Schur system (Sec. 2.3, eq.
+    another_even-odd_linear_equation) solves the same 5D system (oracle true
+    residual, same x4 as the left form), and its CGNR iteration count does not
+    depend on alpha, while the left form's does."""
+    import torch
+    import paper_2602_14454_amd as dwf
+    dims, Ls = (4, 4, 4, 6), 8
+    counts = {"left": [], "right": []}
+    x4s = []
+    for al in (1.0, 0.6, 0.4):
+        lat, op, p, U = _setup(dims, Ls, 1.8, 0.02, b, c, al, eps=0.5, seed=13, nsmear=1)
+        b4 = dwfgen.gaussian_source_4d(dims, 14)
+        b5 = torch.empty((Ls, p.V, 4, 3), dtype=torch.complex128, device="cuda")
+        op.source_4d(b5, _dev(b4))
+        for form, schur in (("left", 0), ("right", 1)):
+            x5 = torch.zeros_like(b5)
+            st, info = op.solve(x5, b5, dwf.default_params(tol=1e-11, check_every=1, schur=schur))
+            assert st == 0
+            assert oracle.true_residual(p, U, x5.cpu().numpy(), b5.cpu().numpy()) <= 1e-11
+            pp = dwf.default_params(check_every=1, paper_mode=1, inner_prec=dwf.F32, schur=schur)
+            xp = torch.zeros_like(b5)
+            st, ip = op.solve(xp, b5, pp)
+            assert st == 0
+            counts[form].append(ip.iters)
+            x4 = torch.empty((p.V, 4, 3), dtype=torch.complex128, device="cuda")
+            op.project_4d(x4, x5)
+            x4s.append(x4.cpu().numpy())
+    assert max(counts["right"]) - min(counts["right"]) <= 2, counts
+    assert max(counts["left"]) - min(counts["left"]) > 2, counts
+    for x in x4s[1:]:
+        assert np.abs(x - x4s[0]).max() <= 1e-8 * np.abs(x4s[0]).max()
+
+
+def test_right_schur_rejected_where_unsupported():
+    import torch
+    import paper_2602_14454_amd as dwf
+    dims, Ls = (4, 4, 4, 4), 4
+    lat, op, p, U = _setup(dims, Ls, 1.6, 0.05)
+    b5 = torch.zeros((Ls, p.V, 4, 3), dtype=torch.complex128, device="cuda")
+    x5 = torch.zeros_like(b5)
+    with pytest.raises(dwf.DwfError):
+        op.solve(x5, b5, dwf.default_params(algo=dwf.ALGO_MIXED, schur=1))
+    with pytest.raises(dwf.DwfError):
+        dwf.solve_batch([op], [x5[None]], [b5[None]], [1], dwf.default_params(algo=dwf.ALGO_DC, schur=1))
