@@ -115,25 +115,69 @@ __device__ __forceinline__ bool path_input(const PtcLayerParams& P, int q, int b
     return true;
 }
 
-// grid (ceil(Vh / PT), Ls, A / AC); AC output channels per thread
+// grid (ceil(Vh / PT), Ls, A / AC); AC output channels per thread.  The
+// path loop is outside the channel loop: a hop path's link (9 complex) and
+// neighbour index are loaded once per thread and serve every input channel,
+// and the weights of a path are read with wave-uniform addresses.
 template <int AC>
 __global__ __launch_bounds__(PT) void ptc_layer_kernel(PtcLayerParams P) {
     const long i = (long)blockIdx.x * PT + threadIdx.x;
     if (i >= P.Vh) return;
     const int s = blockIdx.y;
     const int a0 = blockIdx.z * AC;
+    const long Vhp = P.Vhp;
     float2 acc[AC][12];
 #pragma unroll
     for (int a = 0; a < AC; ++a)
 #pragma unroll
         for (int k = 0; k < 12; ++k) acc[a][k] = make_float2(0.f, 0.f);
-    for (int b = 0; b < P.B; ++b) {
-        for (int q = 0; q < 11; ++q) {
-            float2 t[12];
-            if (!path_input(P, q, b, s, i, t)) continue;
+    // local paths: 0 (same slice), 9 (s + 1), 10 (s - 1)
+    if (P.in_loc) {
+        for (int qi = 0; qi < 3; ++qi) {
+            const int q = qi == 0 ? 0 : 8 + qi;
+            const int ss = qi == 0 ? s : (qi == 1 ? s + 1 : s - 1);
+            if (ss < 0 || ss >= P.Ls) continue;
+            for (int b = 0; b < P.B; ++b) {
+                float2 t[12];
+                load12(P.in_loc, ((long)b * P.Ls + ss) * 12, i, Vhp, t);
 #pragma unroll
-            for (int a = 0; a < AC; ++a)
-                spin_apply(P.W + (((long)q * P.A + a0 + a) * P.B + b) * 16, t, acc[a]);
+                for (int a = 0; a < AC; ++a)
+                    spin_apply(P.W + (((long)q * P.A + a0 + a) * P.B + b) * 16, t, acc[a]);
+            }
+        }
+    }
+    // link paths 1..8: the link and neighbour of direction d once for all channels
+    if (P.in_hop) {
+        for (int d = 0; d < 8; ++d) {
+            const long y = P.nbr[(long)d * Vhp + i];
+            float2 L[10];
+            if constexpr (link_lp(8) == 2) {
+#pragma unroll
+                for (int g = 0; g < 5; ++g) {
+                    const float4 v4 = *reinterpret_cast<const float4*>(P.links + lidx(d, 2 * g, i, Vhp, 8));
+                    L[2 * g] = make_float2(v4.x, v4.y);
+                    L[2 * g + 1] = make_float2(v4.z, v4.w);
+                }
+            } else {
+#pragma unroll
+                for (int e = 0; e < 9; ++e) L[e] = P.links[lidx(d, e, i, Vhp, 8)];
+            }
+            for (int b = 0; b < P.B; ++b) {
+                float2 v[12], t[12];
+                load12(P.in_hop, ((long)b * P.Ls + s) * 12, y, Vhp, v);
+#pragma unroll
+                for (int sp = 0; sp < 4; ++sp)
+#pragma unroll
+                    for (int a = 0; a < 3; ++a) {
+                        float2 c = make_float2(0.f, 0.f);
+#pragma unroll
+                        for (int bb = 0; bb < 3; ++bb) cfma(c, L[a * 3 + bb], v[sp * 3 + bb]);
+                        t[sp * 3 + a] = c;
+                    }
+#pragma unroll
+                for (int a = 0; a < AC; ++a)
+                    spin_apply(P.W + (((long)(1 + d) * P.A + a0 + a) * P.B + b) * 16, t, acc[a]);
+            }
         }
     }
 #pragma unroll
