@@ -574,6 +574,115 @@ def run_schur_study(args):
                       "summary": summary, "rows": rows, "seconds": time.time() - t0}))
 
 
+def cpu_baseline_gauge_step():
+    """CPU baseline of the gauge generator: the numpy oracle's step (one heatbath
+    and four over-relaxation sweeps) on 8^4, seconds (scale x16 to 16^4)."""
+    import dwfgen
+    from oracle import gauge as G
+    dims = (8, 8, 8, 8)
+    U8 = dwfgen.random_su3_links(dims, 3.0, 1)
+    tc = time.perf_counter()
+    G.sweep(U8, dims, 6.0, 1, 0, heatbath=True)
+    for _ in range(4):
+        G.sweep(U8, dims, 6.0, 1, 0, heatbath=False)
+    return time.perf_counter() - tc
+
+
+def run_quenched(args):
+    """Quenched ensembles of the plaquette action on 16^4 (the paper's Sec. 3.1:
+    beta = 6.0 and 5.7) generated by the library's heatbath / over-relaxation
+    kernels (hot start, 1 heatbath + 4 over-relaxation sweeps per step, 400
+    thermalisation steps, configurations every 100 steps), then the paper's
+    alpha study on them: paper-mode FP32 CGNR iterations for (b, c) = (1.5, 0.5)
+    and (1, 1), M0 = 1.8 (unsmeared, Ls = 8 and 16) and M0 = 1.0 (3 stout steps
+    rho = 0.1, Ls = 8), m = 0.001 and 0.01."""
+    import numpy as np
+    import torch
+
+    import dwfgen
+    import paper_2602_14454_amd as dwf
+
+    dev = "cuda:0"
+    dims = (16, 16, 16, 16)
+    V = int(np.prod(dims))
+    alphas = [1.0, 0.8, 0.6, 0.5, 0.4]
+    masses = [0.001, 0.01]
+    t0 = time.time()
+    ens = {}
+    gen = {}
+    for beta, ncfg, seed in ((6.0, 2, 61), (5.7, 1, 57)):
+        U = torch.from_numpy(dwfgen.random_su3_links(dims, 3.0, seed)).to(dev)
+        hist = []
+        torch.cuda.synchronize()
+        tg = time.perf_counter()
+        sweep = 0
+        for k in range(40):
+            dwf.gauge_sweeps(U, dims, beta, nsweeps=10, n_or=4, seed=seed, sweep0=sweep)
+            sweep += 10
+            hist.append(dwf.gauge_plaquette(U, dims))
+        torch.cuda.synchronize()
+        t_therm = time.perf_counter() - tg
+        cfgs = []
+        for c in range(ncfg):
+            if c:
+                dwf.gauge_sweeps(U, dims, beta, nsweeps=100, n_or=4, seed=seed, sweep0=sweep)
+                sweep += 100
+            cfgs.append(U.cpu().numpy())
+            hist.append(dwf.gauge_plaquette(U, dims))
+        ens[beta] = cfgs
+        gen[str(beta)] = {"plaquette_history_every_10_steps": hist, "steps": sweep,
+                          "seconds_per_step": t_therm / 400, "configs": ncfg,
+                          "final_plaquettes": [float(h) for h in hist[-ncfg:]]}
+        log(f"[{time.time() - t0:5.0f}s] beta {beta}: plaquette {hist[-1]:.5f}, {t_therm / 400 * 1e3:.2f} ms per step")
+    t_or = cpu_baseline_gauge_step()
+    rows = []
+    setups = [("beta6.0", 6.0, 0, 1.8, [8, 16]), ("beta6.0_stout3", 6.0, 3, 1.0, [8]), ("beta5.7", 5.7, 0, 1.8, [8])]
+    for name, beta, nsm, M0, Ls_list in setups:
+        for ci, U in enumerate(ens[beta]):
+            Uc = dwfgen.stout_smear(U, dims, 0.1, nsm) if nsm else U
+            lat = dwf.Lattice(dims)
+            lat.set_gauge(Uc)
+            plaq = dwfgen.plaquette(Uc, dims)
+            b4 = torch.from_numpy(dwfgen.gaussian_source_4d(dims, 900 + ci)).to(dev)
+            for Ls in Ls_list:
+                b5 = torch.empty((Ls, V, 4, 3), dtype=torch.complex128, device=dev)
+                x5 = torch.zeros_like(b5)
+                for (b, c) in ((1.5, 0.5), (1.0, 1.0)):
+                    for m in masses:
+                        for al in alphas:
+                            op = dwf.Op(lat, Ls, M0, m, b, c, al)
+                            op.source_4d(b5, b4)
+                            x5.zero_()
+                            st, info = op.solve(x5, b5, dwf.default_params(check_every=8, paper_mode=1,
+                                                                           inner_prec=dwf.F32, maxiter=60000))
+                            rows.append({"setup": name, "config": ci, "plaquette": plaq, "Ls": Ls, "b": b, "c": c,
+                                         "M0": M0, "m": m, "alpha": al, "iters": info.iters, "status": st})
+                            del op
+                    log(f"[{time.time() - t0:5.0f}s] {name} cfg {ci} Ls {Ls} (b,c)=({b},{c}): " +
+                        " ".join(str(r["iters"]) for r in rows[-len(masses) * len(alphas):]))
+            del lat
+    summary = []
+    for name, beta, nsm, M0, Ls_list in setups:
+        for Ls in Ls_list:
+            for (b, c) in ((1.5, 0.5), (1.0, 1.0)):
+                for m in masses:
+                    sel = [r for r in rows if r["setup"] == name and r["Ls"] == Ls and r["b"] == b and r["m"] == m]
+                    it = {al: float(np.mean([r["iters"] for r in sel if r["alpha"] == al])) for al in alphas}
+                    best = min(alphas, key=lambda a: it[a])
+                    summary.append({"setup": name, "Ls": Ls, "b": b, "c": c, "m": m, "mean_iters_by_alpha": it,
+                                    "alpha_opt": best, "reduction": 1.0 - it[best] / it[1.0]})
+    print(json.dumps({"metric": "paper-mode FP32 CGNR iterations against alpha on quenched 16^4 ensembles generated "
+                                "by the library (the paper's Sec. 3 study)",
+                      "data": "synthetic (quenched Monte Carlo)", "n_gpus": 1,
+                      "generation": gen, "oracle_8c4_step_seconds": t_or,
+                      "paper_reported": {"beta6.0_(1.5,0.5)_Ls8": "about 25 % at alpha ~0.6",
+                                         "beta6.0_(1.5,0.5)_Ls16": "25 % (m=0.001) to 20 % (m=0.01) at alpha ~0.5",
+                                         "beta6.0_(1,1)": "about 36 % at alpha ~0.5",
+                                         "beta6.0_stout3_M0=1.0": "37 % ((1.5,0.5)) and 40 % ((1,1)) at m=0.001",
+                                         "beta5.7_Ls8": "20-30 % at m=0.001, alpha 0.4-0.5"},
+                      "summary": summary, "rows": rows, "seconds": time.time() - t0}))
+
+
 def cpu_model():
     try:
         with open("/proc/cpuinfo") as fh:
@@ -657,6 +766,8 @@ def main():
     ap.add_argument("--train-steps", type=int, default=1500)
     ap.add_argument("--alpha-scan", action="store_true",
                     help="run the alpha scan instead: iteration counts against alpha for three (b, c) choices")
+    ap.add_argument("--quenched", action="store_true",
+                    help="generate quenched 16^4 ensembles (beta 6.0, 5.7) and run the paper's alpha study on them")
     ap.add_argument("--schur-study", action="store_true",
                     help="run the left vs right even-odd Schur comparison against alpha on 16^4 instead")
     ap.add_argument("--sdep-study", action="store_true",
@@ -690,6 +801,9 @@ def main():
         return
     if args.schur_study:
         run_schur_study(args)
+        return
+    if args.quenched:
+        run_quenched(args)
         return
     dev = "cuda:0"
     cfg = dict(CONFIGS[args.config])

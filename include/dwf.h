@@ -325,6 +325,25 @@ int dwf_ptc_eval(dwf_ptc* m, int nsets, dwf_ptc_pairs* const* sets, double* mean
 int dwf_ptc_save(const dwf_ptc* m, const char* path);
 int dwf_ptc_load(const char* path, dwf_ptc** out);
 
+/* ---- quenched gauge fields ------------------------------------------
+ * The paper's ensembles are quenched configurations of the plaquette gauge
+ * action S = beta sum_P (1 - Re tr U_P / 3) at beta = 6.0 and 5.7 (Sec. 3.1).
+ * U: canonical complex128 links U[lex][mu][3][3] on the device, periodic in
+ * every direction, updated in place; every extent even and >= 2.
+ *
+ * dwf_gauge_sweeps: nsweeps times (one heatbath sweep, then n_or
+ * over-relaxation sweeps) over all links: Cabibbo-Marinari SU(2)-subgroup
+ * heatbath with Kennedy-Pendleton's sampler and the microcanonical reflection
+ * in the same subgroups, links of one direction and one site parity updated
+ * together (mu = 0..3, parity 0 then 1), re-projection onto SU(3) after
+ * every sweep.  Random numbers are a pure function of (seed, sweep index
+ * sweep0 + k, link, subgroup, draw) (SplitMix64 of counters), so a run is
+ * reproducible and can be continued by passing sweep0.  Synchronises. */
+int dwf_gauge_sweeps(const int dims[4], void* U, double beta, int nsweeps, int n_or, unsigned long long seed,
+                     long long sweep0, void* stream);
+/* average Re tr U_P / 3 over all sites and planes (FP64); synchronises */
+int dwf_gauge_plaquette(const int dims[4], const void* U, double* plaq, void* stream);
+
 /* ---- measurement helpers ------------------------------------------ */
 
 /* Times `nrep` launches of the fused half-lattice hop kernel of D^ (the

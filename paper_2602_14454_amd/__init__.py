@@ -18,7 +18,7 @@ __all__ = [
     "load", "DwfError", "SolveParams", "SolveInfo", "Lattice", "Op",
     "F64", "F32", "BF16", "FULL5D", "EVEN5D", "ALGO_CGNR", "ALGO_DC", "ALGO_FGCR_LEARNED", "ALGO_MIXED",
     "solve_batch", "autotune_batch", "tune_cache_put", "tune_cache_get", "tune_cache_reload",
-    "PtcModel", "PtcPairs",
+    "PtcModel", "PtcPairs", "gauge_sweeps", "gauge_plaquette",
 ]
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
@@ -101,6 +101,8 @@ SIGNATURES = {
     "dwf_ptc_save": (_i, [_vp, ctypes.c_char_p]),
     "dwf_ptc_load": (_i, [ctypes.c_char_p, ctypes.POINTER(_vp)]),
     "dwf_bench_copy": (_i, [ctypes.c_size_t, _i, _dp, _vp]),
+    "dwf_gauge_sweeps": (_i, [_ip, _vp, _d, _i, _i, ctypes.c_ulonglong, ctypes.c_longlong, _vp]),
+    "dwf_gauge_plaquette": (_i, [_ip, _vp, _dp, _vp]),
     "dwf_ptc_bench_apply": (_i, [_vp, _vp, _i, _dp, _vp]),
     "dwf_status_string": (ctypes.c_char_p, [_i]),
     "dwf_last_error": (ctypes.c_char_p, []),
@@ -485,6 +487,21 @@ class Op:
         if getattr(self, "_h", None) and _lib is not None:
             _lib.dwf_op_destroy(self._h)
             self._h = None
+
+
+def gauge_sweeps(U, dims, beta, nsweeps=1, n_or=0, seed=1, sweep0=0, stream=None):
+    """dwf_gauge_sweeps on a canonical complex128 device tensor U (V, 4, 3, 3), in place."""
+    d = (ctypes.c_int * 4)(*[int(v) for v in dims])
+    _check(load().dwf_gauge_sweeps(d, _dev_ptr(U), float(beta), int(nsweeps), int(n_or), int(seed), int(sweep0),
+                                   _stream(stream)), "dwf_gauge_sweeps")
+    return U
+
+
+def gauge_plaquette(U, dims, stream=None) -> float:
+    d = (ctypes.c_int * 4)(*[int(v) for v in dims])
+    v = ctypes.c_double()
+    _check(load().dwf_gauge_plaquette(d, _dev_ptr(U), ctypes.byref(v), _stream(stream)), "dwf_gauge_plaquette")
+    return v.value
 
 
 def bench_copy(nbytes: int, nrep: int = 20, stream=None) -> float:

@@ -13,6 +13,7 @@
 #include <algorithm>
 
 #include "blas.h"
+#include "gauge.h"
 #include "dwf_internal.h"
 #include "hop.h"
 #include "ops.h"
@@ -648,6 +649,40 @@ int dwf_ptc_load(const char* path, dwf_ptc** out) {
     return guarded([&] {
         DWF_REQUIRE(out, DWF_EINVAL, "null argument");
         *out = ptc_load(path);
+        return DWF_OK;
+    });
+}
+
+int dwf_gauge_sweeps(const int dims[4], void* U, double beta, int nsweeps, int n_or, unsigned long long seed,
+                     long long sweep0, void* stream) {
+    return guarded([&] {
+        DWF_REQUIRE(dims && U, DWF_EINVAL, "null argument");
+        for (int mu = 0; mu < 4; ++mu)
+            DWF_REQUIRE(dims[mu] >= 2 && dims[mu] % 2 == 0, DWF_EDIMS, "every lattice extent must be even and >= 2");
+        DWF_REQUIRE(nsweeps >= 0 && n_or >= 0 && beta > 0.0 && std::isfinite(beta), DWF_EINVAL,
+                    "nsweeps, n_or >= 0 and beta > 0 required");
+        const double V = (double)dims[0] * dims[1] * dims[2] * dims[3];
+        DWF_REQUIRE(V * 4.0 * 3.0 * 4096.0 < 1.8e19, DWF_EDIMS, "lattice too large for the random-number counters");
+        hipStream_t st = S(stream);
+        for (int k = 0; k < nsweeps; ++k) {
+            gauge_sweep(U, dims, beta, seed, sweep0 + k, true, st);
+            for (int o = 0; o < n_or; ++o) gauge_sweep(U, dims, beta, seed, sweep0 + k, false, st);
+        }
+        DWF_HIP(hipStreamSynchronize(st));
+        return DWF_OK;
+    });
+}
+
+int dwf_gauge_plaquette(const int dims[4], const void* U, double* plaq, void* stream) {
+    return guarded([&] {
+        DWF_REQUIRE(dims && U && plaq, DWF_EINVAL, "null argument");
+        for (int mu = 0; mu < 4; ++mu) DWF_REQUIRE(dims[mu] >= 1, DWF_EDIMS, "bad lattice extent");
+        hipStream_t st = S(stream);
+        DevBuf partial((size_t)(gauge_plaquette_partials(dims) + 1) * sizeof(double));
+        double* out = partial.as<double>() + gauge_plaquette_partials(dims);
+        gauge_plaquette(U, dims, partial.as<double>(), out, st);
+        DWF_HIP(hipMemcpyAsync(plaq, out, sizeof(double), hipMemcpyDeviceToHost, st));
+        DWF_HIP(hipStreamSynchronize(st));
         return DWF_OK;
     });
 }
