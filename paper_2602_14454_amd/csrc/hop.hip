@@ -42,21 +42,28 @@ namespace dwf {
 // Tuning knobs (compile time): occupancy target per precision, 4-slice
 // groups per wave in the hop phase (KPW > 1: each link load serves KPW
 // groups), unrolling of the direction loop, and whether the 8 neighbour
-// indices are loaded up front.  Defaults are the best of sweeps on MI355X
-// (16^3x32, Ls = 16): with one slice group per wave and no unrolling of the
-// direction loop the FP32/BF16 kernels fit in 96 / 88 VGPRs at 5 waves per
-// SIMD without spills (FP32 hop 75 -> 73 us against 4 waves, BF16 unchanged);
-// unrolling lets the compiler hoist the loads of several directions and
-// spill.  The work-list kernel that loops over several right-hand sides
-// keeps 4 waves (it spills already there).
+// indices are loaded up front.  Defaults are the best of sweeps on MI355X:
+// one slice group per wave; the single-lattice kernels run the pipelined
+// direction loop (below) in FP32 at 4 waves per SIMD (<= 127 VGPRs) and in
+// BF16 at 5 (<= 95), FP64 runs the rolled loop at 3 (<= 168); without the
+// pipelining, unrolling only lets the compiler hoist the loads of several
+// directions and spill.  The work-list kernels, whose pre-mix mode is a
+// runtime value, keep 4 waves (FP64: 2).
 #ifndef DWF_HOP_WAVES_PER_EU
-#define DWF_HOP_WAVES_PER_EU 5
+#define DWF_HOP_WAVES_PER_EU 4
 #endif
 #ifndef DWF_HOP_BATCHN_WPE
 #define DWF_HOP_BATCHN_WPE 4
 #endif
 #ifndef DWF_HOP_WAVES_PER_EU64
-#define DWF_HOP_WAVES_PER_EU64 2
+#define DWF_HOP_WAVES_PER_EU64 3
+#endif
+// FP64 kernels whose pre-mix mode is a runtime value (work lists) or 2
+#ifndef DWF_HOP_WAVES_PER_EU64_BATCH
+#define DWF_HOP_WAVES_PER_EU64_BATCH 2
+#endif
+#ifndef DWF_HOP_WAVES_PER_EU16
+#define DWF_HOP_WAVES_PER_EU16 5
 #endif
 #ifndef DWF_HOP_UNROLL
 #define DWF_HOP_UNROLL 1
@@ -74,9 +81,18 @@ namespace dwf {
 // direction d+1 are loaded (raw 16-byte groups, decoded at use) while
 // direction d is computed, so every wave keeps one direction's loads in
 // flight during its arithmetic instead of exposing the memory latency once
-// per direction.
+// per direction.  1: a rolled ping-pong loop; 2: the eight directions
+// unrolled with compile-time spin structure.  Single-lattice launches only
+// (their pre-mix mode is a template constant; with the mode a runtime value
+// the extra registers spill).  Measured on 24^3x48, Ls = 16 (hop us):
+// FP32 451 (off, 5 waves) / 437 (2, 4 waves) / 469 (2, 5 waves, spills);
+// BF16 292 (off) / 266 (2, 5 waves); FP64 spills with it (951 -> 5189) and
+// takes 910 at 3 waves without it.
 #ifndef DWF_HOP_PREFETCH
-#define DWF_HOP_PREFETCH 0
+#define DWF_HOP_PREFETCH 2
+#endif
+#ifndef DWF_HOP_PREFETCH64
+#define DWF_HOP_PREFETCH64 0
 #endif
 // Load the phase-2 MFMA A operands once per wave (see hop_tile): 1 when all
 // its components share a chirality, 2 also when they straddle the two.
@@ -267,12 +283,22 @@ __device__ __forceinline__ void hop_dir(int d, const R* __restrict__ U, const R*
     }
 }
 
+// Pre-mix mode of a launch: a template constant for the single-lattice
+// kernel (PM >= 0: the code of the other modes, and the registers it would
+// hold, is not generated), the launch parameter for work-list launches
+// (PM < 0: the items of one launch may differ).
+template <int PM>
+__device__ __forceinline__ int pre_mode_of(const HopParams& P) {
+    if constexpr (PM >= 0) return PM;
+    else return P.pre_mode;
+}
+
 // Buffer descriptors of one hop launch (wave-uniform, scalar registers).
 struct HopRes {
     __amdgpu_buffer_rsrc_t in, loc, out, out2, upd, links, nbr;
 };
 
-template <class S, int G>
+template <class S, int G, int PM>
 __device__ __forceinline__ void hop_direction(const HopParams& P, const HopRes& R_, unsigned gb, unsigned sx,
                                               int D, unsigned ynb, const int (&s)[G],
                                               const typename Traits<S>::R (&pd)[G][2],
@@ -316,13 +342,13 @@ __device__ __forceinline__ void hop_direction(const HopParams& P, const HopRes& 
 #pragma unroll
             for (int k = 0; k < 2 * PK; ++k) p[2 * PK * q + k] = v[k];
         }
-        if (P.pre_mode == 2) {   // mode 1 (diagonal) enters through kr and a final scale
+        if (pre_mode_of<PM>(P) == 2) {   // mode 1 (diagonal) enters through kr and a final scale
 #pragma unroll
             for (int k = 0; k < 12; ++k) p[k] *= pd[g][0];
 #pragma unroll
             for (int k = 12; k < 24; ++k) p[k] *= pd[g][1];
         }
-        if (P.pre_mode == 2) {
+        if (pre_mode_of<PM>(P) == 2) {
             // K pattern: upper chirality (components 0-5) couples s-1, lower
             // (6-11) s+1 (cyclic); groups that straddle the boundary are read
             // from both slices
@@ -399,7 +425,7 @@ __device__ __forceinline__ void hop_fetch(const HopParams& P, const HopRes& R_, 
     }
 }
 
-template <class S, int G>
+template <class S, int G, int PM>
 __device__ __forceinline__ void hop_apply(const HopParams& P, const HopRes& R_, unsigned gb, int D, const int (&s)[G],
                                           const typename Traits<S>::R (&pd)[G][2],
                                           const typename Traits<S>::R (&pe)[G][2],
@@ -426,7 +452,7 @@ __device__ __forceinline__ void hop_apply(const HopParams& P, const HopRes& R_, 
 #pragma unroll
             for (int k = 0; k < 2 * PK; ++k) p[2 * PK * q + k] = v[k];
         }
-        if (P.pre_mode == 2) {
+        if (pre_mode_of<PM>(P) == 2) {
 #pragma unroll
             for (int k = 0; k < 12; ++k) p[k] *= pd[g][0];
 #pragma unroll
@@ -516,7 +542,7 @@ template <class S, int KK> struct HopSmem {
     static constexpr unsigned bytes(bool has_loc) { return loc_off + (has_loc ? loc_b : 0u); }
 };
 
-template <class S, int KK>
+template <class S, int KK, int PM = -1>
 __device__ __forceinline__ void hop_tile(const HopParams& P, long tile, int rhs, double* part_out,
                                          unsigned char* smem) {
     using R = typename Traits<S>::R;
@@ -607,7 +633,7 @@ __device__ __forceinline__ void hop_tile(const HopParams& P, long tile, int rhs,
             pe[g][1] = pre ? pre[3 * 16 + sc_] : R(0);
             // diagonal pre-mix (mode 1; the host guarantees d_up != 0 on valid
             // slices): lower/upper ratio inside the projection, d_up at the end
-            kr[g] = (P.pre_mode == 1 && pd[g][0] != R(0)) ? pd[g][1] / pd[g][0] : R(1);
+            kr[g] = (pre_mode_of<PM>(P) == 1 && pd[g][0] != R(0)) ? pd[g][1] / pd[g][0] : R(1);
 #pragma unroll
             for (int k = 0; k < 24; ++k) h[g][k] = 0;
         }
@@ -620,7 +646,39 @@ __device__ __forceinline__ void hop_tile(const HopParams& P, long tile, int rhs,
             ynb[d] = (DWF_HOP_NBR_PRELOAD && !DWF_HOP_LDS_LINKS)
                          ? __builtin_amdgcn_raw_buffer_load_b32(R_.nbr, (unsigned)sx * 4u, (unsigned)d * (unsigned)P.Vhp * 4u, 0)
                          : 0u;
-        if constexpr (DWF_HOP_PREFETCH && DWF_HOP_LDS_LINKS) {
+        constexpr int PF = PM < 0 ? 0 : (sizeof(S) == 8 ? DWF_HOP_PREFETCH64 : DWF_HOP_PREFETCH);
+        if constexpr (PF == 2 && DWF_HOP_LDS_LINKS) {
+            // fully unrolled, double-buffered: direction d is a compile-time
+            // constant in each step (its spin structure folds), and the loads
+            // of d+1 are issued before the arithmetic of d
+            constexpr int NGR = 12 / fpack<S>();
+            u32x4 ra[G][NGR], rb[G][NGR];
+            unsigned ya, yb;
+            hop_fetch<S, G>(P, R_, gb, 0, sg, lnbr, j, ra, ya);
+            hop_fetch<S, G>(P, R_, gb, 1, sg, lnbr, j, rb, yb);
+            __builtin_amdgcn_sched_barrier(0);
+            hop_apply<S, G, PM>(P, R_, gb, 0, sg, pd, pe, kr, h, lnk, ra, ya, j);
+            hop_fetch<S, G>(P, R_, gb, 2, sg, lnbr, j, ra, ya);
+            __builtin_amdgcn_sched_barrier(0);
+            hop_apply<S, G, PM>(P, R_, gb, 1, sg, pd, pe, kr, h, lnk, rb, yb, j);
+            hop_fetch<S, G>(P, R_, gb, 3, sg, lnbr, j, rb, yb);
+            __builtin_amdgcn_sched_barrier(0);
+            hop_apply<S, G, PM>(P, R_, gb, 2, sg, pd, pe, kr, h, lnk, ra, ya, j);
+            hop_fetch<S, G>(P, R_, gb, 4, sg, lnbr, j, ra, ya);
+            __builtin_amdgcn_sched_barrier(0);
+            hop_apply<S, G, PM>(P, R_, gb, 3, sg, pd, pe, kr, h, lnk, rb, yb, j);
+            hop_fetch<S, G>(P, R_, gb, 5, sg, lnbr, j, rb, yb);
+            __builtin_amdgcn_sched_barrier(0);
+            hop_apply<S, G, PM>(P, R_, gb, 4, sg, pd, pe, kr, h, lnk, ra, ya, j);
+            hop_fetch<S, G>(P, R_, gb, 6, sg, lnbr, j, ra, ya);
+            __builtin_amdgcn_sched_barrier(0);
+            hop_apply<S, G, PM>(P, R_, gb, 5, sg, pd, pe, kr, h, lnk, rb, yb, j);
+            hop_fetch<S, G>(P, R_, gb, 7, sg, lnbr, j, rb, yb);
+            __builtin_amdgcn_sched_barrier(0);
+            hop_apply<S, G, PM>(P, R_, gb, 6, sg, pd, pe, kr, h, lnk, ra, ya, j);
+            __builtin_amdgcn_sched_barrier(0);
+            hop_apply<S, G, PM>(P, R_, gb, 7, sg, pd, pe, kr, h, lnk, rb, yb, j);
+        } else if constexpr (PF == 1 && DWF_HOP_LDS_LINKS) {
             // ping-pong over two raw buffers: the loads of the next direction
             // are in flight while the current one is computed
             constexpr int NGR = 12 / fpack<S>();
@@ -631,15 +689,15 @@ __device__ __forceinline__ void hop_tile(const HopParams& P, long tile, int rhs,
             for (int d = 0; d < 8; d += 2) {
                 hop_fetch<S, G>(P, R_, gb, d + 1, sg, lnbr, j, rb, yb);
                 __builtin_amdgcn_sched_barrier(0);
-                hop_apply<S, G>(P, R_, gb, d, sg, pd, pe, kr, h, lnk, ra, ya, j);
+                hop_apply<S, G, PM>(P, R_, gb, d, sg, pd, pe, kr, h, lnk, ra, ya, j);
                 if (d + 2 < 8) hop_fetch<S, G>(P, R_, gb, d + 2, sg, lnbr, j, ra, ya);
                 __builtin_amdgcn_sched_barrier(0);
-                hop_apply<S, G>(P, R_, gb, d + 1, sg, pd, pe, kr, h, lnk, rb, yb, j);
+                hop_apply<S, G, PM>(P, R_, gb, d + 1, sg, pd, pe, kr, h, lnk, rb, yb, j);
             }
         } else {
 #pragma unroll DWF_HOP_UNROLL
             for (int d = 0; d < 8; ++d) {
-                hop_direction<S, G>(P, R_, gb, (unsigned)sx, d, ynb[d], sg, pd, pe, kr, h, lnk, lnbr, j);
+                hop_direction<S, G, PM>(P, R_, gb, (unsigned)sx, d, ynb[d], sg, pd, pe, kr, h, lnk, lnbr, j);
                 // unrolled: keep each direction's loads after the previous one's
                 // arithmetic (hoisting them all raises the register count past
                 // the occupancy target)
@@ -651,7 +709,7 @@ __device__ __forceinline__ void hop_tile(const HopParams& P, long tile, int rhs,
         }
 #pragma unroll
         for (int g = 0; g < G; ++g) {
-            if (P.pre_mode == 1) {
+            if (pre_mode_of<PM>(P) == 1) {
 #pragma unroll
                 for (int k = 0; k < 24; ++k) h[g][k] *= pd[g][0];
             }
@@ -957,12 +1015,23 @@ __device__ __forceinline__ void hop_tile(const HopParams& P, long tile, int rhs,
     }
 }
 
-template <class S, int KK, int TAG = 0>
+// Waves per SIMD the single-lattice hop is compiled for.  The general
+// pre-mix (mode 2, c != 0) holds the extra K row in registers: at the
+// occupancy of modes 0/1 it spills in FP64 and BF16, so it runs one wave
+// lower there.
+template <class S, int PM>
+constexpr int hop_waves_per_eu() {
+    if (sizeof(S) == 8) return PM == 2 ? DWF_HOP_WAVES_PER_EU64_BATCH : DWF_HOP_WAVES_PER_EU64;
+    if (sizeof(S) == 2) return PM == 2 ? DWF_HOP_WAVES_PER_EU16 - 1 : DWF_HOP_WAVES_PER_EU16;
+    return DWF_HOP_WAVES_PER_EU;
+}
+
+template <class S, int KK, int TAG = 0, int PM = 1>
 __global__ __launch_bounds__(256)
-__attribute__((amdgpu_waves_per_eu(sizeof(S) == 8 ? DWF_HOP_WAVES_PER_EU64 : DWF_HOP_WAVES_PER_EU)))
+__attribute__((amdgpu_waves_per_eu(hop_waves_per_eu<S, PM>())))
 void hop_mfma_kernel(HopParams P) {
     extern __shared__ u32x4 hop_smem[];
-    hop_tile<S, KK>(P, xcd_block(blockIdx.x, gridDim.x), blockIdx.y,
+    hop_tile<S, KK, PM>(P, xcd_block(blockIdx.x, gridDim.x), blockIdx.y,
                     P.partial ? P.partial + (long)blockIdx.y * gridDim.x + blockIdx.x : nullptr,
                     reinterpret_cast<unsigned char*>(hop_smem));
 }
@@ -979,7 +1048,7 @@ void hop_mfma_kernel(HopParams P) {
 // (its partial is written as 0).
 template <class S, int KK>
 __global__ __launch_bounds__(256)
-__attribute__((amdgpu_waves_per_eu(sizeof(S) == 8 ? DWF_HOP_WAVES_PER_EU64 : DWF_HOP_BATCHN_WPE)))
+__attribute__((amdgpu_waves_per_eu(sizeof(S) == 8 ? DWF_HOP_WAVES_PER_EU64_BATCH : DWF_HOP_BATCHN_WPE)))
 void hop_batch_kernel(const HopParams* __restrict__ items, const int* __restrict__ meta, int nitems, int nrb,
                       int order) {
     extern __shared__ u32x4 hop_smem[];
@@ -1013,7 +1082,7 @@ void hop_batch_kernel(const HopParams* __restrict__ items, const int* __restrict
 #endif
 template <class S, int KK>
 __global__ __launch_bounds__(256)
-__attribute__((amdgpu_waves_per_eu(sizeof(S) == 8 ? DWF_HOP_WAVES_PER_EU64 : DWF_HOP_BATCH1_WPE)))
+__attribute__((amdgpu_waves_per_eu(sizeof(S) == 8 ? DWF_HOP_WAVES_PER_EU64_BATCH : DWF_HOP_BATCH1_WPE)))
 void hop_batch1_kernel(const HopParams* __restrict__ items, const int* __restrict__ meta, int nitems, int order) {
     extern __shared__ u32x4 hop_smem[];
     const int b = xcd_block(blockIdx.x, gridDim.x);
@@ -1127,19 +1196,29 @@ static unsigned hop_min_lds() {
     return v;
 }
 
-template <class S, int TAG>
-static void launch_hop_t(const HopParams& P, int nrhs, hipStream_t st) {
+template <class S, int TAG, int PM>
+static void launch_hop_pm(const HopParams& P, int nrhs, hipStream_t st) {
     const int KK = (P.Ls + 3) / 4;
     dim3 grid(hop_grid_blocks(P.Vh), nrhs), block(64 * hop_waves(KK, sizeof(S) == 8));
     const unsigned smem_b = std::max(hop_smem_bytes<S>(KK, P.loc != nullptr), hop_min_lds());
     switch (KK) {
-        case 1: hipLaunchKernelGGL((hop_mfma_kernel<S, 1, TAG>), grid, block, smem_b, st, P); break;
-        case 2: hipLaunchKernelGGL((hop_mfma_kernel<S, 2, TAG>), grid, block, smem_b, st, P); break;
-        case 3: hipLaunchKernelGGL((hop_mfma_kernel<S, 3, TAG>), grid, block, smem_b, st, P); break;
-        case 4: hipLaunchKernelGGL((hop_mfma_kernel<S, 4, TAG>), grid, block, smem_b, st, P); break;
+        case 1: hipLaunchKernelGGL((hop_mfma_kernel<S, 1, TAG, PM>), grid, block, smem_b, st, P); break;
+        case 2: hipLaunchKernelGGL((hop_mfma_kernel<S, 2, TAG, PM>), grid, block, smem_b, st, P); break;
+        case 3: hipLaunchKernelGGL((hop_mfma_kernel<S, 3, TAG, PM>), grid, block, smem_b, st, P); break;
+        case 4: hipLaunchKernelGGL((hop_mfma_kernel<S, 4, TAG, PM>), grid, block, smem_b, st, P); break;
         default: throw Error{DWF_EDIMS, "Ls > 16 not supported by the fused hop"};
     }
     DWF_HIP(hipGetLastError());
+}
+
+template <class S, int TAG>
+static void launch_hop_t(const HopParams& P, int nrhs, hipStream_t st) {
+    switch (P.pre_mode) {
+        case 0: launch_hop_pm<S, TAG, 0>(P, nrhs, st); break;
+        case 1: launch_hop_pm<S, TAG, 1>(P, nrhs, st); break;
+        case 2: launch_hop_pm<S, TAG, 2>(P, nrhs, st); break;
+        default: throw Error{DWF_EINVAL, "bad pre-mix mode"};
+    }
 }
 
 template <class S>
