@@ -128,6 +128,7 @@ struct Item {
 struct HopClass {
     int KK;
     std::vector<int> items;   // indices into Batch::items
+    int pm[4] = {-1, -1, -1, -1};   // per stage: the items' common pre-mix mode, -1 if mixed
 };
 
 struct Stream {
@@ -217,7 +218,7 @@ struct NormalHops {
         meta.assign(classes.size() * meta_per_class, 0);
         int pos = 0;
         for (size_t ci = 0; ci < classes.size(); ++ci) {
-            const HopClass& c = classes[ci];
+            HopClass& c = classes[ci];
             int* m = meta.data() + ci * meta_per_class;
             int acc = 0;
             for (size_t q = 0; q < c.items.size(); ++q) {
@@ -251,6 +252,11 @@ struct NormalHops {
                 stage_loc[1] = s2.loc != nullptr;
                 stage_loc[2] = s3.loc != nullptr;
                 stage_loc[3] = s4.loc != nullptr;
+                const HopParams* sp[4] = {&s1, &s2, &s3, &s4};
+                for (int k = 0; k < 4; ++k) {
+                    int& pm = c.pm[k];
+                    pm = q == 0 ? sp[k]->pre_mode : (pm == sp[k]->pre_mode ? pm : -1);
+                }
                 for (int q = 0; q < ring; ++q) {
                     const size_t shift = (size_t)q * ring_bytes;
                     HopParams a = s1, b = s2;
@@ -278,7 +284,7 @@ struct NormalHops {
             const HopParams* it = items_dev.as<HopParams>() + table(sidx, q) * per_stage + first;
             const int* m = meta_dev.as<int>() + ci * meta_per_class;
             launch_hop_batch(kind, classes[ci].KK, it, m, (int)classes[ci].items.size(), blocks[ci], nrb, order,
-                             stage_loc[sidx], st);
+                             stage_loc[sidx], classes[ci].pm[sidx], st);
             first += classes[ci].items.size();
         }
     }

@@ -1046,7 +1046,9 @@ void hop_mfma_kernel(HopParams P) {
 // across tiles of one RHS), order 1 sweeps RHS chunks fastest (link reuse
 // across chunks).  A right-hand side whose done flag is set is skipped
 // (its partial is written as 0).
-template <class S, int KK>
+// PM as in hop_batch1_kernel below (the same arithmetic path, so that every
+// schedule gives the same bits).
+template <class S, int KK, int PM>
 __global__ __launch_bounds__(256)
 __attribute__((amdgpu_waves_per_eu(sizeof(S) == 8 ? DWF_HOP_WAVES_PER_EU64_BATCH : DWF_HOP_BATCHN_WPE)))
 void hop_batch_kernel(const HopParams* __restrict__ items, const int* __restrict__ meta, int nitems, int nrb,
@@ -1070,7 +1072,7 @@ void hop_batch_kernel(const HopParams* __restrict__ items, const int* __restrict
             if (part && threadIdx.x == 0) *part = 0.0;
             continue;
         }
-        hop_tile<S, KK>(P, tile, r, part, reinterpret_cast<unsigned char*>(hop_smem));
+        hop_tile<S, KK, PM>(P, tile, r, part, reinterpret_cast<unsigned char*>(hop_smem));
         __syncthreads();   // shared memory is reused by the next right-hand side
     }
 }
@@ -1080,9 +1082,18 @@ void hop_batch_kernel(const HopParams* __restrict__ items, const int* __restrict
 #ifndef DWF_HOP_BATCH1_WPE
 #define DWF_HOP_BATCH1_WPE 5
 #endif
-template <class S, int KK>
+// PM >= 0: every item of the launch has that pre-mix mode (compiled in, with
+// the single-lattice kernel's pipelined direction loop and occupancy);
+// PM = -1: mixed modes, read per item.
+template <class S, int PM>
+constexpr int hop_batch1_waves_per_eu() {
+    if (PM >= 0) return hop_waves_per_eu<S, PM>();
+    return sizeof(S) == 8 ? DWF_HOP_WAVES_PER_EU64_BATCH : DWF_HOP_BATCH1_WPE;
+}
+
+template <class S, int KK, int PM>
 __global__ __launch_bounds__(256)
-__attribute__((amdgpu_waves_per_eu(sizeof(S) == 8 ? DWF_HOP_WAVES_PER_EU64_BATCH : DWF_HOP_BATCH1_WPE)))
+__attribute__((amdgpu_waves_per_eu(hop_batch1_waves_per_eu<S, PM>())))
 void hop_batch1_kernel(const HopParams* __restrict__ items, const int* __restrict__ meta, int nitems, int order) {
     extern __shared__ u32x4 hop_smem[];
     const int b = xcd_block(blockIdx.x, gridDim.x);
@@ -1106,7 +1117,7 @@ void hop_batch1_kernel(const HopParams* __restrict__ items, const int* __restric
         if (part && threadIdx.x == 0) *part = 0.0;
         return;
     }
-    hop_tile<S, KK>(P, tile, r, part, reinterpret_cast<unsigned char*>(hop_smem));
+    hop_tile<S, KK, PM>(P, tile, r, part, reinterpret_cast<unsigned char*>(hop_smem));
 }
 
 // ---------------------------------------------------------------------
@@ -1221,39 +1232,61 @@ static void launch_hop_t(const HopParams& P, int nrhs, hipStream_t st) {
     }
 }
 
+template <class S, int PM>
+static void launch_hop_batch1_pm(int KK, dim3 grid, dim3 block, unsigned smem_b, const HopParams* items,
+                                 const int* meta, int nitems, int order, hipStream_t st) {
+    switch (KK) {
+        case 1: hipLaunchKernelGGL((hop_batch1_kernel<S, 1, PM>), grid, block, smem_b, st, items, meta, nitems, order); break;
+        case 2: hipLaunchKernelGGL((hop_batch1_kernel<S, 2, PM>), grid, block, smem_b, st, items, meta, nitems, order); break;
+        case 3: hipLaunchKernelGGL((hop_batch1_kernel<S, 3, PM>), grid, block, smem_b, st, items, meta, nitems, order); break;
+        case 4: hipLaunchKernelGGL((hop_batch1_kernel<S, 4, PM>), grid, block, smem_b, st, items, meta, nitems, order); break;
+        default: throw Error{DWF_EDIMS, "Ls > 16 not supported by the fused hop"};
+    }
+}
+
+template <class S, int PM>
+static void launch_hop_batchn_pm(int KK, dim3 grid, dim3 block, unsigned smem_b, const HopParams* items,
+                                 const int* meta, int nitems, int nrb, int order, hipStream_t st) {
+    switch (KK) {
+        case 1: hipLaunchKernelGGL((hop_batch_kernel<S, 1, PM>), grid, block, smem_b, st, items, meta, nitems, nrb, order); break;
+        case 2: hipLaunchKernelGGL((hop_batch_kernel<S, 2, PM>), grid, block, smem_b, st, items, meta, nitems, nrb, order); break;
+        case 3: hipLaunchKernelGGL((hop_batch_kernel<S, 3, PM>), grid, block, smem_b, st, items, meta, nitems, nrb, order); break;
+        case 4: hipLaunchKernelGGL((hop_batch_kernel<S, 4, PM>), grid, block, smem_b, st, items, meta, nitems, nrb, order); break;
+        default: throw Error{DWF_EDIMS, "Ls > 16 not supported by the fused hop"};
+    }
+}
+
 template <class S>
 static void launch_hop_batch_t(int KK, const HopParams* items, const int* meta, int nitems, int blocks, int nrb,
-                               int order, bool loc, hipStream_t st) {
+                               int order, bool loc, int pm, hipStream_t st) {
     dim3 grid(blocks), block(64 * hop_waves(KK, sizeof(S) == 8));
     const unsigned smem_b = hop_smem_bytes<S>(KK, loc);
     if (nrb == 1) {
-        switch (KK) {
-            case 1: hipLaunchKernelGGL((hop_batch1_kernel<S, 1>), grid, block, smem_b, st, items, meta, nitems, order); break;
-            case 2: hipLaunchKernelGGL((hop_batch1_kernel<S, 2>), grid, block, smem_b, st, items, meta, nitems, order); break;
-            case 3: hipLaunchKernelGGL((hop_batch1_kernel<S, 3>), grid, block, smem_b, st, items, meta, nitems, order); break;
-            case 4: hipLaunchKernelGGL((hop_batch1_kernel<S, 4>), grid, block, smem_b, st, items, meta, nitems, order); break;
-            default: throw Error{DWF_EDIMS, "Ls > 16 not supported by the fused hop"};
+        switch (pm) {
+            case 0: launch_hop_batch1_pm<S, 0>(KK, grid, block, smem_b, items, meta, nitems, order, st); break;
+            case 1: launch_hop_batch1_pm<S, 1>(KK, grid, block, smem_b, items, meta, nitems, order, st); break;
+            case 2: launch_hop_batch1_pm<S, 2>(KK, grid, block, smem_b, items, meta, nitems, order, st); break;
+            default: launch_hop_batch1_pm<S, -1>(KK, grid, block, smem_b, items, meta, nitems, order, st); break;
         }
         DWF_HIP(hipGetLastError());
         return;
     }
-    switch (KK) {
-        case 1: hipLaunchKernelGGL((hop_batch_kernel<S, 1>), grid, block, smem_b, st, items, meta, nitems, nrb, order); break;
-        case 2: hipLaunchKernelGGL((hop_batch_kernel<S, 2>), grid, block, smem_b, st, items, meta, nitems, nrb, order); break;
-        case 3: hipLaunchKernelGGL((hop_batch_kernel<S, 3>), grid, block, smem_b, st, items, meta, nitems, nrb, order); break;
-        case 4: hipLaunchKernelGGL((hop_batch_kernel<S, 4>), grid, block, smem_b, st, items, meta, nitems, nrb, order); break;
-        default: throw Error{DWF_EDIMS, "Ls > 16 not supported by the fused hop"};
+    switch (pm) {
+        case 0: launch_hop_batchn_pm<S, 0>(KK, grid, block, smem_b, items, meta, nitems, nrb, order, st); break;
+        case 1: launch_hop_batchn_pm<S, 1>(KK, grid, block, smem_b, items, meta, nitems, nrb, order, st); break;
+        case 2: launch_hop_batchn_pm<S, 2>(KK, grid, block, smem_b, items, meta, nitems, nrb, order, st); break;
+        default: launch_hop_batchn_pm<S, -1>(KK, grid, block, smem_b, items, meta, nitems, nrb, order, st); break;
     }
     DWF_HIP(hipGetLastError());
 }
 
 void launch_hop_batch(int kind, int KK, const HopParams* items, const int* meta, int nitems, int blocks, int nrb,
-                      int order, bool has_loc, hipStream_t st) {
+                      int order, bool has_loc, int pm, hipStream_t st) {
     if (blocks <= 0) return;
     switch (kind) {
-        case ST_F64: launch_hop_batch_t<double>(KK, items, meta, nitems, blocks, nrb, order, has_loc, st); break;
-        case ST_F32: launch_hop_batch_t<float>(KK, items, meta, nitems, blocks, nrb, order, has_loc, st); break;
-        case ST_BF16: launch_hop_batch_t<bf16s>(KK, items, meta, nitems, blocks, nrb, order, has_loc, st); break;
+        case ST_F64: launch_hop_batch_t<double>(KK, items, meta, nitems, blocks, nrb, order, has_loc, pm, st); break;
+        case ST_F32: launch_hop_batch_t<float>(KK, items, meta, nitems, blocks, nrb, order, has_loc, pm, st); break;
+        case ST_BF16: launch_hop_batch_t<bf16s>(KK, items, meta, nitems, blocks, nrb, order, has_loc, pm, st); break;
         default: throw Error{DWF_EINVAL, "bad storage kind"};
     }
 }
