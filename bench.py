@@ -588,6 +588,105 @@ def cpu_baseline_gauge_step():
     return time.perf_counter() - tc
 
 
+def gen_quenched(dims, beta, ncfg, seed, dev):
+    """Quenched configurations of the plaquette action generated by the
+    library: hot start, 1 heatbath + 4 over-relaxation sweeps per step, 400
+    thermalisation steps, then ncfg configurations 100 steps apart.  Returns
+    (host link arrays, generation record)."""
+    import torch
+
+    import dwfgen
+    import paper_2602_14454_amd as dwf
+
+    U = torch.from_numpy(dwfgen.random_su3_links(dims, 3.0, seed)).to(dev)
+    hist = []
+    torch.cuda.synchronize()
+    tg = time.perf_counter()
+    sweep = 0
+    for k in range(40):
+        dwf.gauge_sweeps(U, dims, beta, nsweeps=10, n_or=4, seed=seed, sweep0=sweep)
+        sweep += 10
+        hist.append(dwf.gauge_plaquette(U, dims))
+    torch.cuda.synchronize()
+    t_therm = time.perf_counter() - tg
+    cfgs = []
+    for c in range(ncfg):
+        if c:
+            dwf.gauge_sweeps(U, dims, beta, nsweeps=100, n_or=4, seed=seed, sweep0=sweep)
+            sweep += 100
+        cfgs.append(U.cpu().numpy())
+        hist.append(dwf.gauge_plaquette(U, dims))
+    return cfgs, {"plaquette_history_every_10_steps": hist, "steps": sweep, "seconds_per_step": t_therm / 400,
+                  "configs": ncfg, "final_plaquettes": [float(h) for h in hist[-ncfg:]]}
+
+
+def run_eo5_study(args):
+    """The split by 5D parity against the 4D one (Sec. 2.3 names both and uses
+    the 4D split): paper-mode FP32 CGNR iterations against alpha for the 4D
+    left form, the 4D right form and the 5D left form, on the library's
+    quenched 16^4 ensembles at beta = 6.0 (two configurations), Shamir
+    (b, c) = (1, 0) (the 5D split needs c = 0): M0 = 1.8 unsmeared with
+    Ls = 8 and 16, and M0 = 1.0 with 3 stout steps (rho = 0.1), Ls = 8;
+    m = 0.001 and 0.01; one Gaussian 4D source per configuration."""
+    import numpy as np
+    import torch
+
+    import dwfgen
+    import paper_2602_14454_amd as dwf
+
+    dev = "cuda:0"
+    dims = (16, 16, 16, 16)
+    V = int(np.prod(dims))
+    alphas = [1.0, 0.8, 0.6, 0.5, 0.4]
+    masses = [0.001, 0.01]
+    forms = (("4d_left", 0), ("4d_right", 1), ("5d_left", 2))
+    t0 = time.time()
+    cfgs, gen = gen_quenched(dims, 6.0, 2, 61, dev)
+    log(f"[{time.time() - t0:5.0f}s] beta 6.0: plaquettes {gen['final_plaquettes']}")
+    rows = []
+    setups = [("beta6.0", 0, 1.8, [8, 16]), ("beta6.0_stout3", 3, 1.0, [8])]
+    for name, nsm, M0, Ls_list in setups:
+        for ci, U in enumerate(cfgs):
+            Uc = dwfgen.stout_smear(U, dims, 0.1, nsm) if nsm else U
+            lat = dwf.Lattice(dims)
+            lat.set_gauge(Uc)
+            b4 = torch.from_numpy(dwfgen.gaussian_source_4d(dims, 900 + ci)).to(dev)
+            for Ls in Ls_list:
+                b5 = torch.empty((Ls, V, 4, 3), dtype=torch.complex128, device=dev)
+                x5 = torch.zeros_like(b5)
+                for m in masses:
+                    for al in alphas:
+                        op = dwf.Op(lat, Ls, M0, m, 1.0, 0.0, al)
+                        op.source_4d(b5, b4)
+                        for form, schur in forms:
+                            x5.zero_()
+                            st, info = op.solve(x5, b5, dwf.default_params(check_every=8, paper_mode=1, schur=schur,
+                                                                           inner_prec=dwf.F32, maxiter=60000))
+                            rows.append({"setup": name, "config": ci, "Ls": Ls, "M0": M0, "m": m, "alpha": al,
+                                         "form": form, "iters": info.iters, "status": st,
+                                         "ms_per_iter": info.seconds * 1e3 / max(info.iters, 1),
+                                         "true_res5": info.true_res5})
+                        del op
+                    log(f"[{time.time() - t0:5.0f}s] {name} cfg {ci} Ls {Ls} m {m}: " +
+                        " ".join(f"{r['form']}:{r['iters']}" for r in rows[-len(alphas) * len(forms):]))
+            del lat
+    summary = []
+    for name, nsm, M0, Ls_list in setups:
+        for Ls in Ls_list:
+            for m in masses:
+                for form, _ in forms:
+                    sel = [r for r in rows if r["setup"] == name and r["Ls"] == Ls and r["m"] == m and r["form"] == form]
+                    it = {al: float(np.mean([r["iters"] for r in sel if r["alpha"] == al])) for al in alphas}
+                    best = min(alphas, key=lambda a: it[a])
+                    summary.append({"setup": name, "Ls": Ls, "m": m, "form": form, "mean_iters_by_alpha": it,
+                                    "alpha_opt": best, "reduction": 1.0 - it[best] / it[1.0],
+                                    "ms_per_iter": float(np.mean([r["ms_per_iter"] for r in sel]))})
+    print(json.dumps({"metric": "paper-mode FP32 CGNR iterations against alpha: 4D left / 4D right / 5D left "
+                                "even-odd forms on quenched 16^4 beta 6.0 ensembles generated by the library",
+                      "data": "synthetic (quenched Monte Carlo)", "n_gpus": 1, "generation": gen,
+                      "summary": summary, "rows": rows, "seconds": time.time() - t0}))
+
+
 def run_quenched(args):
     """Quenched ensembles of the plaquette action on 16^4 (the paper's Sec. 3.1:
     beta = 6.0 and 5.7) generated by the library's heatbath / over-relaxation
@@ -611,29 +710,9 @@ def run_quenched(args):
     ens = {}
     gen = {}
     for beta, ncfg, seed in ((6.0, 2, 61), (5.7, 1, 57)):
-        U = torch.from_numpy(dwfgen.random_su3_links(dims, 3.0, seed)).to(dev)
-        hist = []
-        torch.cuda.synchronize()
-        tg = time.perf_counter()
-        sweep = 0
-        for k in range(40):
-            dwf.gauge_sweeps(U, dims, beta, nsweeps=10, n_or=4, seed=seed, sweep0=sweep)
-            sweep += 10
-            hist.append(dwf.gauge_plaquette(U, dims))
-        torch.cuda.synchronize()
-        t_therm = time.perf_counter() - tg
-        cfgs = []
-        for c in range(ncfg):
-            if c:
-                dwf.gauge_sweeps(U, dims, beta, nsweeps=100, n_or=4, seed=seed, sweep0=sweep)
-                sweep += 100
-            cfgs.append(U.cpu().numpy())
-            hist.append(dwf.gauge_plaquette(U, dims))
-        ens[beta] = cfgs
-        gen[str(beta)] = {"plaquette_history_every_10_steps": hist, "steps": sweep,
-                          "seconds_per_step": t_therm / 400, "configs": ncfg,
-                          "final_plaquettes": [float(h) for h in hist[-ncfg:]]}
-        log(f"[{time.time() - t0:5.0f}s] beta {beta}: plaquette {hist[-1]:.5f}, {t_therm / 400 * 1e3:.2f} ms per step")
+        ens[beta], gen[str(beta)] = gen_quenched(dims, beta, ncfg, seed, dev)
+        log(f"[{time.time() - t0:5.0f}s] beta {beta}: plaquette {gen[str(beta)]['final_plaquettes'][-1]:.5f}, "
+            f"{gen[str(beta)]['seconds_per_step'] * 1e3:.2f} ms per step")
     t_or = cpu_baseline_gauge_step()
     rows = []
     setups = [("beta6.0", 6.0, 0, 1.8, [8, 16]), ("beta6.0_stout3", 6.0, 3, 1.0, [8]), ("beta5.7", 5.7, 0, 1.8, [8])]
@@ -770,6 +849,8 @@ def main():
                     help="generate quenched 16^4 ensembles (beta 6.0, 5.7) and run the paper's alpha study on them")
     ap.add_argument("--schur-study", action="store_true",
                     help="run the left vs right even-odd Schur comparison against alpha on 16^4 instead")
+    ap.add_argument("--eo5-study", action="store_true",
+                    help="4D vs 5D even-odd split: alpha scans on generated quenched 16^4 ensembles")
     ap.add_argument("--sdep-study", action="store_true",
                     help="run the alpha x (b, c) x Ls x m iteration / condition-number study on 16^4 instead")
     ap.add_argument("--spectrum", action="store_true",
@@ -804,6 +885,9 @@ def main():
         return
     if args.quenched:
         run_quenched(args)
+        return
+    if args.eo5_study:
+        run_eo5_study(args)
         return
     dev = "cuda:0"
     cfg = dict(CONFIGS[args.config])

@@ -91,7 +91,11 @@ typedef struct {
                              (1 - Deo Doo^-1 Doe Dee^-1) y_e = b'_e, x_e = Dee^-1 y_e (Sec. 2.3
                              eq. another_even-odd_linear_equation), CGNR on its normal equations,
                              composed from unfused kernels (algo CGNR or DC only); the alpha of the
-                             Neff form cancels in it, the measurement of that claim */
+                             Neff form cancels in it, the measurement of that claim; 2 the left form
+                             with the sites split by their 5D parity (x+y+z+t+s) mod 2 (Sec. 2.3: the
+                             split can be made in 5D or 4D), for c_s = 0 and even Ls only, where D_ee
+                             and D_oo are diagonal (algo CGNR or DC, inner_prec F64 or F32;
+                             DWF_EINVAL otherwise) */
 } dwf_solve_params;
 
 /* Solve report.  Against the survey's sketch of this struct: `iters` is the
@@ -159,6 +163,18 @@ int dwf_apply(const dwf_op* op, int space, int dagger, int prec, void* out, cons
 
 /* out = D^dag D^ in on even canonical vectors (the CGNR normal operator). */
 int dwf_apply_normal(const dwf_op* op, int prec, void* out, const void* in, void* stream);
+
+/* Schur operator of the split by 5D parity (Sec. 2.3: even and odd sites in
+ * five instead of four dimensions; eq. even-odd_linear_equation with those
+ * blocks): out5 = D^5 in5 = (1 - D_ee^-1 D_eo D_oo^-1 D_oe) in5, or its
+ * adjoint for dagger = 1, where "e" are the (s, x) with (x+y+z+t+s) even
+ * (s = 0..Ls-1).  in5, out5: canonical 5D complex128 device fields
+ * (Ls*V*12); only the 5D-even entries of in5 are read, the 5D-odd entries of
+ * out5 are set to zero.  prec DWF_F64 or DWF_F32 (inputs and outputs stay
+ * complex128).  Needs c_s = 0 for every s and an even Ls (D_ee, D_oo
+ * diagonal; the mass term joins s = Ls-1 to s = 0), else DWF_EINVAL; in5
+ * and out5 must not alias.  Synchronous on `stream`. */
+int dwf_apply_eo5(const dwf_op* op, int prec, int dagger, void* out5, const void* in5, void* stream);
 
 /* out = D^dag D^ in as dwf_apply_normal, for callers that cannot allocate
  * device memory (code under HIP graph capture, tight serving loops,

@@ -70,6 +70,7 @@ SIGNATURES = {
     "dwf_op_destroy": (None, [_vp]),
     "dwf_apply": (_i, [_vp, _i, _i, _i, _vp, _vp, _vp]),
     "dwf_apply_normal": (_i, [_vp, _i, _vp, _vp, _vp]),
+    "dwf_apply_eo5": (_i, [_vp, _i, _i, _vp, _vp, _vp]),
     "dwf_source_4d": (_i, [_vp, _vp, _vp, _vp]),
     "dwf_cg_residual_update": (_i, [_vp, _i, _vp, _vp, _dp, _dp, _vp]),
     "dwf_apply_normal_noalloc": (_i, [_vp, _i, _vp, _vp, _vp]),
@@ -424,6 +425,12 @@ class Op:
         _check(load().dwf_apply_normal(self._h, int(prec), _dev_ptr(out), _dev_ptr(inp), _stream(stream)),
                "dwf_apply_normal")
         return out
+
+    def apply_eo5(self, out5, in5, dagger=False, prec=F64, stream=None):
+        """Schur operator of the split by 5D parity (or its adjoint) on the 5D-even entries of canonical 5D fields."""
+        _check(load().dwf_apply_eo5(self._h, int(prec), int(bool(dagger)), _dev_ptr(out5), _dev_ptr(in5),
+                                    _stream(stream)), "dwf_apply_eo5")
+        return out5
 
     def apply_normal_noalloc(self, out, inp, prec=F64, stream=None):
         """D^dag D^ with the library's static scratch (no device allocation, no synchronisation)."""

@@ -18,7 +18,7 @@ LIB = os.path.join(HERE, "libdwf.so")
 BUILD_DIR = os.path.join(HERE, "_build")
 ARCH = os.environ.get("DWF_OFFLOAD_ARCH", "gfx950")
 
-SOURCES = ["hop.hip", "blas.hip", "fifth_dim.cpp", "objects.cpp", "ops.cpp", "slot_blas.hip", "ptc_kernels.hip", "fgcr_kernels.hip", "gauge.hip", "solver.cpp", "fgcr.cpp", "ptc.cpp", "batch.cpp", "lanczos.cpp", "api.cpp"]
+SOURCES = ["hop.hip", "blas.hip", "fifth_dim.cpp", "objects.cpp", "ops.cpp", "slot_blas.hip", "ptc_kernels.hip", "fgcr_kernels.hip", "gauge.hip", "eo5d.hip", "eo5d_solve.cpp", "solver.cpp", "fgcr.cpp", "ptc.cpp", "batch.cpp", "lanczos.cpp", "api.cpp"]
 
 
 def _hipcc() -> str:

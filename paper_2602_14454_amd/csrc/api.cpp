@@ -17,6 +17,7 @@
 #include "dwf_internal.h"
 #include "hop.h"
 #include "ops.h"
+#include "eo5d.h"
 #include "solver.h"
 #include "ptc_model.h"
 
@@ -367,9 +368,22 @@ int dwf_solve(const dwf_op* op, void* x5, const void* b5, const dwf_solve_params
                     DWF_EINVAL, "unsupported algorithm");
         DWF_REQUIRE(!(p->algo == DWF_ALGO_FGCR_LEARNED && p->paper_mode), DWF_EINVAL,
                     "paper_mode applies to CGNR only");
-        DWF_REQUIRE(p->schur == 0 || (p->schur == 1 && (p->algo == DWF_ALGO_CGNR || p->algo == DWF_ALGO_DC)),
-                    DWF_EINVAL, "schur: 0 (left) for every algorithm, 1 (right) with CGNR or DC only");
+        DWF_REQUIRE(p->schur == 0 ||
+                        ((p->schur == 1 || p->schur == 2) && (p->algo == DWF_ALGO_CGNR || p->algo == DWF_ALGO_DC)),
+                    DWF_EINVAL,
+                    "schur: 0 (left) for every algorithm, 1 (right) and 2 (5D split) with CGNR or DC only");
         return solve(op, x5, b5, p, info, S(stream));
+    });
+}
+
+int dwf_apply_eo5(const dwf_op* op, int prec, int dagger, void* out5, const void* in5, void* stream) {
+    return guarded([&] {
+        DWF_REQUIRE(op && out5 && in5, DWF_EINVAL, "null argument");
+        DWF_REQUIRE(out5 != in5, DWF_EINVAL, "in and out must not alias");
+        DWF_REQUIRE(dagger == 0 || dagger == 1, DWF_EINVAL, "dagger: 0 or 1");
+        DWF_REQUIRE(prec == DWF_F64 || prec == DWF_F32, DWF_EINVAL, "the 5D even-odd split runs in FP64 or FP32");
+        apply_eo5_schur(op, kind_of(prec), dagger, out5, in5, S(stream));
+        return DWF_OK;
     });
 }
 

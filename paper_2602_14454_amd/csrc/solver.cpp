@@ -6,6 +6,7 @@
 // CG scalars stay on the device (finalize kernels compute alpha and beta from
 // the FP64 partial sums); the host reads them back every `check_every`
 // iterations to test convergence.
+#include "eo5d.h"
 #include "solver.h"
 
 #include <algorithm>
@@ -368,6 +369,7 @@ struct DropOnError {
 
 int solve(const dwf_op* op, void* x5, const void* b5, const dwf_solve_params* prm, dwf_solve_info* info,
           hipStream_t st) {
+    if (prm->schur == 2) return solve_eo5(op, x5, b5, prm, info, st);   // the 5D split (eo5d_solve.cpp)
     const dwf_lattice* L = op->lat;
     DWF_REQUIRE(L->has_gauge, DWF_ESTATE, "gauge field not set");
     const long Vh = L->Vh, Vhp = L->Vhp, V = L->V;

@@ -11,6 +11,7 @@ site- and s-local:
   printed; the 4D-right one does not depend on alpha.
 """
 import numpy as np
+import pytest
 
 import dwfgen
 import oracle
@@ -70,3 +71,54 @@ def test_5d_even_odd_shamir(capsys):
     with capsys.disabled():
         print("\n[eo5d] kappa of the normal operator (2^3x4, Ls=4, Shamir, M0=1.8, m=0.02):",
               {a: {k: round(v, 2) for k, v in d.items()} for a, d in out.items()})
+
+
+def test_dhat5_helper_matches_dense_schur():
+    """oracle.eo5.dhat5 (masks on the oracle's operator and a division by the
+    5D-diagonal block) against the dense Schur complement of the same split,
+    built with dense block solves and pinned above by solving the 5D system;
+    the adjoint against the dense conjugate transpose.  Shamir-type c = 0 with
+    b = 1.3, s-dependent b_s, Ls = 3 (a wrap-around in s at both ends)."""
+    from oracle import eo5
+    dims = (2, 2, 2, 4)
+    U = dwfgen.random_su3_links(dims, 0.5, 23)
+    par4, _, _, _ = oracle.site_maps(dims)
+    V = int(np.prod(dims))
+    rng = np.random.default_rng(24)
+    for Ls, b, bs, al in ((4, 1.3, None, 0.5), (6, 1.0, (1.2, 0.9, 1.1, 1.0, 0.8, 1.3), 0.7), (4, 1.0, None, 1.0),
+                          (2, 1.1, None, 0.6)):
+        p = oracle.Params(dims=dims, Ls=Ls, M0=1.8, m=0.03, b=b, c=0.0, alpha=al, bs=bs)
+        n = Ls * V * 12
+        idx = np.arange(n).reshape(Ls, V, 12)
+        p5 = (par4[None, :] + np.arange(Ls)[:, None]) & 1
+        i5e, i5o = idx[p5 == 0].reshape(-1), idx[p5 == 1].reshape(-1)
+        D = _dense(lambda e: oracle.dwf_apply(p, U, e.reshape(Ls, V, 4, 3)), n)
+        S5 = _schur(D, i5e, i5o)
+        x = (rng.standard_normal(n) + 1j * rng.standard_normal(n)).reshape(Ls, V, 4, 3)
+        xe = x.reshape(-1)[i5e]
+        for dag, S in ((False, S5), (True, S5.conj().T)):
+            y = eo5.dhat5(p, U, x, dagger=dag).reshape(-1)
+            ref = S @ xe
+            assert np.abs(y[i5e] - ref).max() < 1e-12 * np.abs(ref).max()
+            assert np.abs(y[i5o]).max() == 0.0
+
+
+def test_dhat5_helper_rejects_c_and_odd_ls():
+    """c != 0 puts D_W into D_- (D_ee not local); for odd Ls the mass term
+    couples slices of one 5D parity: the dense D_ee then has off-diagonal
+    entries, and the helper refuses both cases."""
+    from oracle import eo5
+    p = oracle.Params(dims=(2, 2, 2, 2), Ls=4, M0=1.8, m=0.03, b=1.5, c=0.5, alpha=1.0)
+    with pytest.raises(ValueError):
+        eo5.diagonal(p)
+    dims, Ls = (2, 2, 2, 2), 3
+    p = oracle.Params(dims=dims, Ls=Ls, M0=1.8, m=0.03, b=1.0, c=0.0, alpha=1.0)
+    with pytest.raises(ValueError):
+        eo5.diagonal(p)
+    U = dwfgen.random_su3_links(dims, 0.5, 25)
+    V = int(np.prod(dims))
+    n = Ls * V * 12
+    D = _dense(lambda e: oracle.dwf_apply(p, U, e.reshape(Ls, V, 4, 3)), n)
+    e = eo5.even_mask(oracle.Params(dims=dims, Ls=Ls, M0=1.8, m=0.03)).repeat(12, axis=1).reshape(-1)
+    Dee = D[np.ix_(e, e)]
+    assert np.abs(Dee - np.diag(np.diag(Dee))).max() == pytest.approx(0.03)
