@@ -469,19 +469,38 @@ __global__ void cg_px_kernel(void* x, void* p, const void* r, long n, const doub
 //  mode 3 (beta after replacing r): s[RRNEW] = s[RR] = sum; s[BETA] = sum / s[RROLD]
 // In modes 1-3 a non-finite sum sets s[NANFLAG] = 1.
 // alpha_copy (mode 1, or nullptr): also receives the new alpha.
-__global__ void finalize_kernel(const double* partial, int nparts, int stride, double* out, int mode,
-                                double* alpha_copy) {
-    __shared__ double red[BLAS_THREADS];
-    double acc = 0.0;
-    for (int i = threadIdx.x; i < nparts; i += blockDim.x) acc += partial[(long)i * stride];
-    red[threadIdx.x] = acc;
+// One block of FIN_THREADS sums the partials in a fixed order (four
+// interleaved accumulators per thread, so that four loads per thread are in
+// flight, then wave shuffles and one wave over the per-wave sums): the same
+// bits on every run, no atomics.  With one accumulator per thread and 256
+// threads the loop issued its loads one after another (32 us for 20 736
+// partials on MI355X).
+constexpr int FIN_THREADS = 1024;
+__global__ __launch_bounds__(FIN_THREADS) void finalize_kernel(const double* partial, int nparts, int stride,
+                                                               double* out, int mode, double* alpha_copy) {
+    __shared__ double red[FIN_THREADS / 64];
+    double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
+    int i = threadIdx.x;
+    for (; i + 3 * FIN_THREADS < nparts; i += 4 * FIN_THREADS) {
+        a0 += partial[(long)i * stride];
+        a1 += partial[(long)(i + FIN_THREADS) * stride];
+        a2 += partial[(long)(i + 2 * FIN_THREADS) * stride];
+        a3 += partial[(long)(i + 3 * FIN_THREADS) * stride];
+    }
+    for (; i < nparts; i += FIN_THREADS) a0 += partial[(long)i * stride];
+    double acc = (a0 + a1) + (a2 + a3);
+#pragma unroll
+    for (int off = 32; off >= 1; off >>= 1) acc += __shfl_xor(acc, off, 64);
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = acc;
     __syncthreads();
-    for (int h = blockDim.x / 2; h >= 1; h >>= 1) {
-        if ((int)threadIdx.x < h) red[threadIdx.x] += red[threadIdx.x + h];
-        __syncthreads();
+    if (threadIdx.x < 64) {
+        double w = threadIdx.x < FIN_THREADS / 64 ? red[threadIdx.x] : 0.0;
+#pragma unroll
+        for (int off = 32; off >= 1; off >>= 1) w += __shfl_xor(w, off, 64);
+        acc = w;
     }
     if (threadIdx.x == 0) {
-        const double sum = red[0];
+        const double sum = acc;
         // modes 1-3 address a whole CG scalar block; mode 0 writes out[0] only
         // (a non-finite sum is visible in the value itself)
         if (mode != 0 && !isfinite(sum)) out[CG_NANFLAG] = 1.0;
@@ -823,7 +842,7 @@ void random_fill_f64(void* v, long rows, long Vh, long Vhp, unsigned long long s
 
 void finalize(const double* partial, int nparts, int stride, double* out, int mode, hipStream_t st,
               double* alpha_copy) {
-    hipLaunchKernelGGL(finalize_kernel, dim3(1), dim3(BLAS_THREADS), 0, st, partial, nparts, stride, out, mode,
+    hipLaunchKernelGGL(finalize_kernel, dim3(1), dim3(FIN_THREADS), 0, st, partial, nparts, stride, out, mode,
                        alpha_copy);
     DWF_HIP(hipGetLastError());
 }

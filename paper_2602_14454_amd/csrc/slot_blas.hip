@@ -160,9 +160,17 @@ __global__ __launch_bounds__(BT) void bfinalize_kernel(const double* partial, lo
     }
     const int np = from_hop ? d.nhop : d.nb;
     const double* pp = partial + (long)v * pstride;
-    double acc = 0.0;
-    for (int i = threadIdx.x; i < np; i += BT) acc += pp[i];
-    red[threadIdx.x] = acc;
+    // four interleaved accumulators (four loads in flight per thread), fixed order
+    double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
+    int i = threadIdx.x;
+    for (; i + 3 * BT < np; i += 4 * BT) {
+        a0 += pp[i];
+        a1 += pp[i + BT];
+        a2 += pp[i + 2 * BT];
+        a3 += pp[i + 3 * BT];
+    }
+    for (; i < np; i += BT) a0 += pp[i];
+    red[threadIdx.x] = (a0 + a1) + (a2 + a3);
     __syncthreads();
     for (int h = BT / 2; h >= 1; h >>= 1) {
         if ((int)threadIdx.x < h) red[threadIdx.x] += red[threadIdx.x + h];
