@@ -5,6 +5,8 @@
 // (wavefront __shfl_xor tree, then the block's waves in order); a single
 // block then sums the partials in a fixed order.  No floating-point atomics,
 // so results are bit-reproducible run to run.
+#include <type_traits>
+
 #include "blas.h"
 #include "dwf_internal.h"
 #include "precision.h"
@@ -275,6 +277,56 @@ __global__ void cg_accx_kernel(void* x, const void* ring, const double* alpha, i
         cstore<SX>(x, i, xr, xi);
     }
 }
+// FP32 x and FP32 ring: two complex numbers (16 bytes) per lane, the loads of
+// every ring term issued before the updates, which then run in the order of
+// cg_accx_kernel (x rounded after each term: the same bits).  One step per
+// lane (no grid-stride loop).
+__global__ __launch_bounds__(256) void cg_accx_f32_kernel(float4* __restrict__ x, const float4* __restrict__ ring,
+                                                          const double* __restrict__ alpha, int cnt, long n2) {
+    const long i = (long)blockIdx.x * 256 + threadIdx.x;
+    if (i >= n2) return;
+    constexpr int QMAX = 16;
+    float4 p[QMAX];
+#pragma unroll
+    for (int q = 0; q < QMAX; ++q)
+        if (q < cnt) p[q] = ring[(long)q * n2 + i];
+    float4 v = x[i];
+#pragma unroll
+    for (int q = 0; q < QMAX; ++q) {
+        if (q < cnt) {
+            const float a = (float)alpha[q];
+            v.x = v.x + a * p[q].x;
+            v.y = v.y + a * p[q].y;
+            v.z = v.z + a * p[q].z;
+            v.w = v.w + a * p[q].w;
+        }
+    }
+    x[i] = v;
+}
+
+// FP32 p_dst = r + beta p_src, 2 x 16 bytes per lane, all loads first
+__global__ __launch_bounds__(256) void cg_p2_f32_kernel(float4* __restrict__ pd, const float4* __restrict__ ps,
+                                                        const float4* __restrict__ r, long n2, const double* beta) {
+    const long i0 = (long)blockIdx.x * 512 + threadIdx.x;
+    const float b = (float)*beta;
+    float4 rv[2], pv[2];
+#pragma unroll
+    for (int k = 0; k < 2; ++k) {
+        const long i = i0 + k * 256;
+        if (i < n2) {
+            rv[k] = r[i];
+            pv[k] = ps[i];
+        }
+    }
+#pragma unroll
+    for (int k = 0; k < 2; ++k) {
+        const long i = i0 + k * 256;
+        if (i < n2)
+            pd[i] = make_float4(rv[k].x + b * pv[k].x, rv[k].y + b * pv[k].y, rv[k].z + b * pv[k].z,
+                                rv[k].w + b * pv[k].w);
+    }
+}
+
 template <class SX, class SP>
 __global__ void cg_accx_remap_kernel(void* x, const void* ring, const double* alpha, int cnt, long n, long nquads,
                                      long Vhp) {
@@ -773,6 +825,15 @@ void cg_update_px(int kx, int kp, void* x, void* p, const void* r, long n, const
 
 template <class SR, class SP>
 static void cg_p2_t2(void* pd, const void* ps, const void* r, long n, long Vhp, const double* beta, hipStream_t st) {
+    if constexpr (std::is_same<SR, float>::value && std::is_same<SP, float>::value) {
+        if (n % 2 == 0) {
+            const long n2 = n / 2;
+            hipLaunchKernelGGL(cg_p2_f32_kernel, dim3((unsigned)((n2 + 511) / 512)), dim3(256), 0, st,
+                               static_cast<float4*>(pd), static_cast<const float4*>(ps), static_cast<const float4*>(r),
+                               n2, beta);
+            return;
+        }
+    }
     if (fpack<SR>() == fpack<SP>())
         hipLaunchKernelGGL((cg_p2_kernel<SR, SP>), dim3(blas_grid(n)), dim3(BLAS_THREADS), 0, st, pd, ps, r, n, beta);
     else
@@ -799,6 +860,14 @@ void cg_update_p2(int kr, int kp, void* p_dst, const void* p_src, const void* r,
 
 template <class SX, class SP>
 static void cg_accx_t2(void* x, const void* ring, const double* alpha, int cnt, long n, long Vhp, hipStream_t st) {
+    if constexpr (std::is_same<SX, float>::value && std::is_same<SP, float>::value) {
+        if (n % 2 == 0 && cnt <= 16) {
+            const long n2 = n / 2;
+            hipLaunchKernelGGL(cg_accx_f32_kernel, dim3((unsigned)((n2 + 255) / 256)), dim3(256), 0, st,
+                               static_cast<float4*>(x), static_cast<const float4*>(ring), alpha, cnt, n2);
+            return;
+        }
+    }
     if (fpack<SX>() == fpack<SP>())
         hipLaunchKernelGGL((cg_accx_kernel<SX, SP>), dim3(blas_grid(n)), dim3(BLAS_THREADS), 0, st, x, ring, alpha,
                            cnt, n);

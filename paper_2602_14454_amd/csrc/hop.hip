@@ -94,6 +94,19 @@ namespace dwf {
 #ifndef DWF_HOP_PREFETCH64
 #define DWF_HOP_PREFETCH64 0
 #endif
+// Cache policy of the streamed accesses (the outputs, the local term and
+// the fused update, each touched once): 0 default, 2 non-temporal, so that
+// they do not displace the neighbour lines that later tiles re-read from L2.
+#ifndef DWF_HOP_NT_STORE
+#define DWF_HOP_NT_STORE 2
+#endif
+#ifndef DWF_HOP_NT_LOAD
+#define DWF_HOP_NT_LOAD 2
+#endif
+// the tile's links and neighbour indices (each read by one block only)
+#ifndef DWF_HOP_NT_LINK
+#define DWF_HOP_NT_LINK 0
+#endif
 // Load the phase-2 MFMA A operands once per wave (see hop_tile): 1 when all
 // its components share a chirality, 2 also when they straddle the two.
 #ifndef DWF_HOP_COEF_HOIST
@@ -592,13 +605,15 @@ __device__ __forceinline__ void hop_tile(const HopParams& P, long tile, int rhs,
             const int dg = e >> 4, jj = e & 15;
             const long se = tile * 16 + jj;
             const unsigned sxe = (unsigned)(se < Vh ? se : Vh - 1);
-            lnk[e] = __builtin_amdgcn_raw_buffer_load_b128(R_.links, sxe * 16u + (unsigned)dg * Vhp * 16u, 0u, 0);
+            lnk[e] = __builtin_amdgcn_raw_buffer_load_b128(R_.links, sxe * 16u + (unsigned)dg * Vhp * 16u, 0u,
+                                                           DWF_HOP_NT_LINK);
         }
         for (int e = threadIdx.x; e < 128; e += blockDim.x) {
             const int d = e >> 4, jj = e & 15;
             const long se = tile * 16 + jj;
             const unsigned sxe = (unsigned)(se < Vh ? se : Vh - 1);
-            lnbr[e] = __builtin_amdgcn_raw_buffer_load_b32(R_.nbr, sxe * 4u + (unsigned)d * Vhp * 4u, 0u, 0);
+            lnbr[e] = __builtin_amdgcn_raw_buffer_load_b32(R_.nbr, sxe * 4u + (unsigned)d * Vhp * 4u, 0u,
+                                                           DWF_HOP_NT_LINK);
         }
     }
     if constexpr (L::LOC) {
@@ -610,7 +625,8 @@ __device__ __forceinline__ void hop_tile(const HopParams& P, long tile, int rhs,
                 const long se = tile * 16 + jj;
                 const unsigned sxe = (unsigned)(se < Vh ? se : Vh - 1);
                 u32x4 v = {0u, 0u, 0u, 0u};
-                if (g < Ls * L::NGR) v = __builtin_amdgcn_raw_buffer_load_b128(R_.loc, sxe * 16u + (unsigned)g * gb, 0u, 0);
+                if (g < Ls * L::NGR)
+                    v = __builtin_amdgcn_raw_buffer_load_b128(R_.loc, sxe * 16u + (unsigned)g * gb, 0u, DWF_HOP_NT_LOAD);
                 locT[e] = v;
             }
         }
@@ -739,6 +755,13 @@ __device__ __forceinline__ void hop_tile(const HopParams& P, long tile, int rhs,
     const bool chain = has_out2 && P.chain2 != 0;
     const R lscale = R(P.loc_scale);
     constexpr int CPW = 12 / hop_waves(KK, sizeof(S) == 8);
+    // per-component accesses: one instruction covers whole lines only in FP64
+    // (one complex per 16-byte group); in FP32/BF16 a group holds several
+    // components, read or written by different instructions, and a
+    // non-temporal line can leave L2 before the second one (measured: the
+    // FP32 solve 2 % slower with it)
+    constexpr int WAUX = sizeof(S) == 8 ? DWF_HOP_NT_LOAD : 0;
+    constexpr int SAUX = sizeof(S) == 8 ? DWF_HOP_NT_STORE : 0;
 
     // FP32/BF16: the primary output (out, else out2) goes through LDS; a
     // second output, if any, is stored directly
@@ -835,7 +858,7 @@ __device__ __forceinline__ void hop_tile(const HopParams& P, long tile, int rhs,
                         li[kk] = bf16_to_f32(v >> 16);
                     }
                 } else {
-                    if (s < Ls) bload<S>(R_.loc, coff(s, cp), 0u, lr[kk], li[kk]);
+                    if (s < Ls) bload<S, WAUX>(R_.loc, coff(s, cp), 0u, lr[kk], li[kk]);
                 }
             }
         }
@@ -915,16 +938,16 @@ __device__ __forceinline__ void hop_tile(const HopParams& P, long tile, int rhs,
                 if (!tile_out) {
                     if (upd) {   // FP64: upd has the layout of out
                         R ur, ui;
-                        bload<S>(R_.upd, coff(s, cp), 0u, ur, ui);
+                        bload<S, WAUX>(R_.upd, coff(s, cp), 0u, ur, ui);
                         ur -= ua * cr[i];
                         ui -= ua * ci[i];
-                        bstore<S>(R_.upd, coff(s, cp), 0u, ur, ui);
+                        bstore<S, SAUX>(R_.upd, coff(s, cp), 0u, ur, ui);
                         if (P.reduce == 3) nrm += double(ur) * double(ur) + double(ui) * double(ui);
                     }
-                    if (P.out) bstore<S>(R_.out, coff(s, cp), 0u, cr[i], ci[i]);
-                    if (has_out2) bstore<S>(R_.out2, coff(s, cp), 0u, dr[i], di[i]);
+                    if (P.out) bstore<S, SAUX>(R_.out, coff(s, cp), 0u, cr[i], ci[i]);
+                    if (has_out2) bstore<S, SAUX>(R_.out2, coff(s, cp), 0u, dr[i], di[i]);
                 } else if (P.out && has_out2) {
-                    bstore<S>(R_.out2, coff(s, cp), 0u, dr[i], di[i]);
+                    bstore<S, SAUX>(R_.out2, coff(s, cp), 0u, dr[i], di[i]);
                 }
             }
         }
@@ -965,12 +988,12 @@ __device__ __forceinline__ void hop_tile(const HopParams& P, long tile, int rhs,
                 const float2 b = *reinterpret_cast<const float2*>(run0 + (2 * (2 * q2 + 1)) * 64);
                 if (se < Vh) {
                     const unsigned off = (unsigned)se * 16u + (unsigned)g * gbu;
-                    const u32x4 u = __builtin_amdgcn_raw_buffer_load_b128(R_.upd, off, 0u, 0);
+                    const u32x4 u = __builtin_amdgcn_raw_buffer_load_b128(R_.upd, off, 0u, DWF_HOP_NT_LOAD);
                     float v0 = __uint_as_float(u.x) - ua * a.x, v1 = __uint_as_float(u.y) - ua * a.y;
                     float v2 = __uint_as_float(u.z) - ua * b.x, v3 = __uint_as_float(u.w) - ua * b.y;
                     u32x4 o;
                     o.x = __float_as_uint(v0); o.y = __float_as_uint(v1); o.z = __float_as_uint(v2); o.w = __float_as_uint(v3);
-                    __builtin_amdgcn_raw_buffer_store_b128(o, R_.upd, off, 0u, 0);
+                    __builtin_amdgcn_raw_buffer_store_b128(o, R_.upd, off, 0u, DWF_HOP_NT_STORE);
                     if (P.reduce == 3)
                         nrm += double(v0) * double(v0) + double(v1) * double(v1) + double(v2) * double(v2) +
                                double(v3) * double(v3);
@@ -997,7 +1020,9 @@ __device__ __forceinline__ void hop_tile(const HopParams& P, long tile, int rhs,
                     v.z = r[(2 * (4 * q + 2)) * 64];
                     v.w = r[(2 * (4 * q + 3)) * 64];
                 }
-                if (se < Vh) __builtin_amdgcn_raw_buffer_store_b128(v, dst, (unsigned)se * 16u + (unsigned)g * gb, 0u, 0);
+                if (se < Vh)
+                    __builtin_amdgcn_raw_buffer_store_b128(v, dst, (unsigned)se * 16u + (unsigned)g * gb, 0u,
+                                                           DWF_HOP_NT_STORE);
             }
         }
     }

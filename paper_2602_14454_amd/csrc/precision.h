@@ -139,25 +139,25 @@ __device__ __forceinline__ __amdgpu_buffer_rsrc_t make_rsrc(const void* p, unsig
     return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(p), (short)0, (int)nbytes, 0x00020000);
 }
 
-template <class S>
+template <class S, int AUX = 0>
 __device__ __forceinline__ void bload(__amdgpu_buffer_rsrc_t r, unsigned voff, unsigned soff,
                                       typename Traits<S>::R& re, typename Traits<S>::R& im) {
     if constexpr (sizeof(S) == 8) {
-        u32x4 v = __builtin_amdgcn_raw_buffer_load_b128(r, voff, soff, 0);
+        u32x4 v = __builtin_amdgcn_raw_buffer_load_b128(r, voff, soff, AUX);
         re = __hiloint2double(v.y, v.x);
         im = __hiloint2double(v.w, v.z);
     } else if constexpr (sizeof(S) == 4) {
-        u32x2 v = __builtin_amdgcn_raw_buffer_load_b64(r, voff, soff, 0);
+        u32x2 v = __builtin_amdgcn_raw_buffer_load_b64(r, voff, soff, AUX);
         re = __uint_as_float(v.x);
         im = __uint_as_float(v.y);
     } else {
-        unsigned v = __builtin_amdgcn_raw_buffer_load_b32(r, voff, soff, 0);
+        unsigned v = __builtin_amdgcn_raw_buffer_load_b32(r, voff, soff, AUX);
         re = bf16_to_f32(v & 0xffffu);
         im = bf16_to_f32(v >> 16);
     }
 }
 
-template <class S>
+template <class S, int AUX = 0>
 __device__ __forceinline__ void bstore(__amdgpu_buffer_rsrc_t r, unsigned voff, unsigned soff,
                                        typename Traits<S>::R re, typename Traits<S>::R im) {
     if constexpr (sizeof(S) == 8) {
@@ -166,14 +166,14 @@ __device__ __forceinline__ void bstore(__amdgpu_buffer_rsrc_t r, unsigned voff, 
         v.y = (unsigned)__double2hiint(re);
         v.z = (unsigned)__double2loint(im);
         v.w = (unsigned)__double2hiint(im);
-        __builtin_amdgcn_raw_buffer_store_b128(v, r, voff, soff, 0);
+        __builtin_amdgcn_raw_buffer_store_b128(v, r, voff, soff, AUX);
     } else if constexpr (sizeof(S) == 4) {
         u32x2 v;
         v.x = __float_as_uint(re);
         v.y = __float_as_uint(im);
-        __builtin_amdgcn_raw_buffer_store_b64(v, r, voff, soff, 0);
+        __builtin_amdgcn_raw_buffer_store_b64(v, r, voff, soff, AUX);
     } else {
-        __builtin_amdgcn_raw_buffer_store_b32(pack_bf16(re, im), r, voff, soff, 0);
+        __builtin_amdgcn_raw_buffer_store_b32(pack_bf16(re, im), r, voff, soff, AUX);
     }
 }
 
