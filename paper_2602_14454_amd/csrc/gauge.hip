@@ -31,6 +31,10 @@ namespace dwf {
 namespace {
 
 constexpr int GT = 256;
+// the update kernels: one thread per link of one direction and parity (V/2
+// threads, 128 blocks of 256 on 16^4, half the 256 CUs); 64-thread blocks put
+// work on every CU
+constexpr int GU = 64;
 constexpr unsigned long long GOLD = 0x9E3779B97F4A7C15ull;
 constexpr unsigned long long GK1 = 0x2545F4914F6CDD1Dull;
 constexpr unsigned long long GK2 = 0x632BE59BD9B4E019ull;
@@ -137,10 +141,10 @@ __device__ inline void apply_rows(M3& m, int i, int j, const double2 R[4]) {
     }
 }
 
-__global__ __launch_bounds__(GT) void gauge_update_kernel(double2* __restrict__ U, Geo g, int mu, int parity,
+__global__ __launch_bounds__(GU) void gauge_update_kernel(double2* __restrict__ U, Geo g, int mu, int parity,
                                                           double beta, unsigned long long key, int heatbath,
                                                           long Vh) {
-    const long i = (long)blockIdx.x * GT + threadIdx.x;
+    const long i = (long)blockIdx.x * GU + threadIdx.x;
     if (i >= Vh) return;
     const long x = site_of(g, i, parity);
     int c[4];
@@ -298,10 +302,10 @@ void gauge_sweep(void* U, const int dims[4], double beta, unsigned long long see
     const long V = (long)dims[0] * dims[1] * dims[2] * dims[3], Vh = V / 2;
     const Geo g = geo_of(dims);
     const unsigned long long key = mix64(seed * GK1 + (unsigned long long)sweep_index * GK2);
-    const unsigned blocks = (unsigned)((Vh + GT - 1) / GT);
+    const unsigned blocks = (unsigned)((Vh + GU - 1) / GU);
     for (int mu = 0; mu < 4; ++mu)
         for (int p = 0; p < 2; ++p) {
-            hipLaunchKernelGGL(gauge_update_kernel, dim3(blocks), dim3(GT), 0, st, static_cast<double2*>(U), g, mu, p,
+            hipLaunchKernelGGL(gauge_update_kernel, dim3(blocks), dim3(GU), 0, st, static_cast<double2*>(U), g, mu, p,
                                beta, key, heatbath ? 1 : 0, Vh);
             DWF_HIP(hipGetLastError());
         }
