@@ -30,6 +30,7 @@
 // dense s-mixing C = A * h reads each operand with one LDS load per MFMA.
 // After the MFMA a lane holds rows s = 4*sc + i, i = 0..3, of the result for
 // its site (f32); the f64 MFMA leaves rows sc + 4*i instead (see out_row).
+#include <type_traits>
 #include "dwf_internal.h"
 #include "hop.h"
 #include "precision.h"
@@ -555,23 +556,37 @@ template <class S, int KK> struct HopSmem {
     static constexpr unsigned bytes(bool has_loc) { return loc_off + (has_loc ? loc_b : 0u); }
 };
 
+// A block may hold several such tiles of one item, one per right-hand side
+// (the shared-link work-list kernel): group `sub` of NW waves computes
+// right-hand side `rhs` in its own shared-memory region smem + sub * region,
+// while the tile's links and neighbour indices are staged once, by every
+// thread of the block, into the first region.  An inactive group (a
+// right-hand side past the item's count or already converged) runs the same
+// code, barriers included, on zero-size buffer descriptors: its loads read
+// zeros and its stores are dropped.  The reduction runs when P.partial is set
+// (the same for every group of a block); part_out = nullptr skips the write.
 template <class S, int KK, int PM = -1>
 __device__ __forceinline__ void hop_tile(const HopParams& P, long tile, int rhs, double* part_out,
-                                         unsigned char* smem) {
+                                         unsigned char* smem, int sub = 0, unsigned region = 0,
+                                         bool active = true) {
     using R = typename Traits<S>::R;
     using V = typename Vec4<R>::T;
     using L = HopSmem<S, KK>;
-    R* hs = reinterpret_cast<R*>(smem);   // hs[kk][r][lane] at kk * HSK + r * 64 + lane
+    constexpr int NW = hop_waves(KK, sizeof(S) == 8);
+    constexpr int NTHR = 64 * NW;
+    unsigned char* own = smem + (size_t)sub * region;
+    R* hs = reinterpret_cast<R*>(own);   // hs[kk][r][lane] at kk * HSK + r * 64 + lane
     constexpr int HSK = L::HSK;
     u32x4* lnk = reinterpret_cast<u32x4*>(smem);
     unsigned* lnbr = reinterpret_cast<unsigned*>(smem + lnk_entries<S>() * 16);
-    double* red = reinterpret_cast<double*>(smem + L::red_off);
-    u32x4* locT = reinterpret_cast<u32x4*>(smem + L::loc_off);
+    double* red = reinterpret_cast<double*>(own + L::red_off);
+    u32x4* locT = reinterpret_cast<u32x4*>(own + L::loc_off);
     const int lane = threadIdx.x & 63;
+    const int tid = (int)threadIdx.x - sub * NTHR;   // thread index within the group
 #if DWF_HOP_W_UNIFORM
-    const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);   // wave-uniform, in a scalar register
+    const int w = __builtin_amdgcn_readfirstlane(((int)threadIdx.x >> 6) - sub * NW);   // wave-uniform
 #else
-    const int w = threadIdx.x >> 6;
+    const int w = ((int)threadIdx.x >> 6) - sub * NW;
 #endif
     const int j = lane & 15, sc = lane >> 4;
     const long Vh = P.Vh;
@@ -583,17 +598,19 @@ __device__ __forceinline__ void hop_tile(const HopParams& P, long tile, int rhs,
     constexpr unsigned PK = fpack<S>();
     const unsigned gb = (unsigned)P.Vhp * PK * CB;             // bytes of one group row (PK components of a slice)
     const unsigned fieldb = (unsigned)Ls * (12u / PK) * gb;    // bytes of one right-hand side
+    const unsigned fieldb_a = active ? fieldb : 0u;             // zero-size descriptors when inactive
     const size_t rhsb = (size_t)rhs * fieldb;                  // bytes of the preceding RHS
     const unsigned sxb = (unsigned)sx * PK * CB;               // this site's offset in a group row
     HopRes R_;
-    R_.in = make_rsrc(static_cast<const char*>(P.in) + rhsb, fieldb);
-    R_.loc = make_rsrc(P.loc ? static_cast<const char*>(P.loc) + rhsb : nullptr, P.loc ? fieldb : 0u);
-    R_.out = make_rsrc(P.out ? static_cast<const char*>(P.out) + rhsb : nullptr, P.out ? fieldb : 0u);
-    R_.out2 = make_rsrc(P.out2 ? static_cast<const char*>(P.out2) + rhsb : nullptr, P.out2 ? fieldb : 0u);
+    R_.in = make_rsrc(static_cast<const char*>(P.in) + rhsb, fieldb_a);
+    R_.loc = make_rsrc(P.loc ? static_cast<const char*>(P.loc) + rhsb : nullptr, P.loc ? fieldb_a : 0u);
+    R_.out = make_rsrc(P.out ? static_cast<const char*>(P.out) + rhsb : nullptr, P.out ? fieldb_a : 0u);
+    R_.out2 = make_rsrc(P.out2 ? static_cast<const char*>(P.out2) + rhsb : nullptr, P.out2 ? fieldb_a : 0u);
     // fused CG update target: compute type in its own layout
     constexpr unsigned PKU = fpack<typename std::conditional<sizeof(R) == 8, double, float>::type>();
     const unsigned fieldu = (unsigned)Ls * 12u * (unsigned)P.Vhp * 2u * (unsigned)sizeof(R);
-    R_.upd = make_rsrc(P.upd ? static_cast<char*>(P.upd) + (size_t)rhs * fieldu : nullptr, P.upd ? fieldu : 0u);
+    R_.upd = make_rsrc(P.upd ? static_cast<char*>(P.upd) + (size_t)rhs * fieldu : nullptr,
+                       (P.upd && active) ? fieldu : 0u);
     R_.links = make_rsrc(P.links, 8u * link_ng(CB) * (unsigned)P.Vhp * link_lp(CB) * CB);
     R_.nbr = make_rsrc(P.nbr, 8u * (unsigned)P.Vhp * 4u);
 
@@ -620,7 +637,7 @@ __device__ __forceinline__ void hop_tile(const HopParams& P, long tile, int rhs,
         // local-term tile: group (s, q) of site jj at locT[(s * NGR + q) * 16 + jj];
         // slices s >= Ls are zero (they meet zero columns of the local mixes)
         if (P.loc != nullptr) {
-            for (int e = threadIdx.x; e < KK * 4 * L::NGR * 16; e += blockDim.x) {
+            for (int e = tid; e < KK * 4 * L::NGR * 16; e += NTHR) {
                 const int jj = e & 15, g = e >> 4;
                 const long se = tile * 16 + jj;
                 const unsigned sxe = (unsigned)(se < Vh ? se : Vh - 1);
@@ -979,7 +996,7 @@ __device__ __forceinline__ void hop_tile(const HopParams& P, long tile, int rhs,
             static_assert(PKU == 2, "fused update expects FP32 fields in component pairs");
             __syncthreads();
             const unsigned gbu = (unsigned)P.Vhp * 16u;
-            for (int e = threadIdx.x; e < Ls * 6 * 16; e += blockDim.x) {
+            for (int e = tid; e < Ls * 6 * 16; e += NTHR) {
                 const int jj = e & 15, g = e >> 4;
                 const int sl = g / 6, q2 = g - sl * 6;
                 const long se = tile * 16 + jj;
@@ -1003,7 +1020,7 @@ __device__ __forceinline__ void hop_tile(const HopParams& P, long tile, int rhs,
             // whole 16-byte groups of 16 consecutive sites
             __syncthreads();
             const __amdgpu_buffer_rsrc_t dst = P.out ? R_.out : R_.out2;
-            for (int e = threadIdx.x; e < Ls * L::NGR * 16; e += blockDim.x) {
+            for (int e = tid; e < Ls * L::NGR * 16; e += NTHR) {
                 const int jj = e & 15, g = e >> 4;
                 const int sl = g / L::NGR, q = g - sl * L::NGR;
                 const long se = tile * 16 + jj;
@@ -1027,14 +1044,14 @@ __device__ __forceinline__ void hop_tile(const HopParams& P, long tile, int rhs,
         }
     }
 
-    if (part_out) {
+    if (P.partial) {
 #pragma unroll
         for (int off = 32; off >= 1; off >>= 1) nrm += __shfl_xor(nrm, off, 64);
         if (lane == 0) red[w] = nrm;
         __syncthreads();
-        if (threadIdx.x == 0) {
+        if (tid == 0 && part_out) {
             double t = 0.0;
-            for (int ww = 0; ww < hop_waves(KK, sizeof(S) == 8); ++ww) t += red[ww];
+            for (int ww = 0; ww < NW; ++ww) t += red[ww];
             *part_out = t;
         }
     }
@@ -1143,6 +1160,41 @@ void hop_batch1_kernel(const HopParams* __restrict__ items, const int* __restric
         return;
     }
     hop_tile<S, KK, PM>(P, tile, r, part, reinterpret_cast<unsigned char*>(hop_smem));
+}
+
+// The work list with NR right-hand sides per block sharing the tile's
+// staged links and neighbour indices: group r of the block's NR groups of
+// hop_waves(KK) waves computes right-hand side chunk * NR + r of the tile in
+// its own shared-memory region (`region` bytes each).  Block -> (tile,
+// chunk) as in hop_batch1_kernel with chunks of NR right-hand sides.
+template <class S, int KK, int PM, int NR>
+__global__ __launch_bounds__(1024)
+__attribute__((amdgpu_waves_per_eu(hop_batch1_waves_per_eu<S, PM>())))
+void hop_multi_kernel(const HopParams* __restrict__ items, const int* __restrict__ meta, int nitems, int order,
+                      unsigned region) {
+    extern __shared__ u32x4 hop_smem[];
+    const int b = xcd_block(blockIdx.x, gridDim.x);
+    int i = 0;
+    while (i + 1 < nitems && b >= meta[i + 1]) ++i;
+    const HopParams& P = items[i];
+    const int nrhs = meta[nitems + 1 + i];
+    const int tiles = (int)((P.Vh + 15) / 16);
+    const int chunks = (nrhs + NR - 1) / NR;
+    int tile = b - meta[i], chunk = 0;
+    if (order == 0) {
+        while (tile >= tiles) { tile -= tiles; ++chunk; }
+    } else {
+        chunk = tile % chunks;
+        tile /= chunks;
+    }
+    const int sub = (int)threadIdx.x / (64 * hop_waves(KK, sizeof(S) == 8));   // wave-uniform
+    const int r = chunk * NR + sub;
+    const bool in_range = r < nrhs;
+    const int rr = in_range ? r : nrhs - 1;   // scalar reads of an out-of-range group stay in bounds
+    const bool active = in_range && !(P.done && P.done[(long)rr * P.done_stride] != 0.0);
+    // a converged right-hand side writes a zero partial (its loads read zeros)
+    double* part = (P.partial && in_range) ? P.partial + (long)rr * P.pstride + tile : nullptr;
+    hop_tile<S, KK, PM>(P, tile, rr, part, reinterpret_cast<unsigned char*>(hop_smem), sub, region, active);
 }
 
 // ---------------------------------------------------------------------
@@ -1281,9 +1333,59 @@ static void launch_hop_batchn_pm(int KK, dim3 grid, dim3 block, unsigned smem_b,
     }
 }
 
+template <class S, int PM, int NR>
+static void launch_hop_multi_pm(int KK, dim3 grid, unsigned region, const HopParams* items, const int* meta,
+                                int nitems, int order, hipStream_t st) {
+    const dim3 block(64 * hop_waves(KK, sizeof(S) == 8) * NR);
+    const unsigned smem_b = region * NR;
+    switch (KK) {
+        case 1: hipLaunchKernelGGL((hop_multi_kernel<S, 1, PM, NR>), grid, block, smem_b, st, items, meta, nitems, order, region); break;
+        case 2: hipLaunchKernelGGL((hop_multi_kernel<S, 2, PM, NR>), grid, block, smem_b, st, items, meta, nitems, order, region); break;
+        case 3: hipLaunchKernelGGL((hop_multi_kernel<S, 3, PM, NR>), grid, block, smem_b, st, items, meta, nitems, order, region); break;
+        case 4: hipLaunchKernelGGL((hop_multi_kernel<S, 4, PM, NR>), grid, block, smem_b, st, items, meta, nitems, order, region); break;
+        default: throw Error{DWF_EDIMS, "Ls > 16 not supported by the fused hop"};
+    }
+}
+
+// shared-link kernel for FP32 with 2 or 4 right-hand sides per block when
+// the block (<= 1024 threads) and its shared memory fit; false otherwise
+template <class S>
+static bool launch_hop_multi(int KK, int blocks, int nrb, int order, bool loc, int pm, const HopParams* items,
+                             const int* meta, int nitems, hipStream_t st) {
+    if constexpr (!std::is_same<S, float>::value) {
+        return false;
+    } else {
+        if (nrb != 2 && nrb != 4) return false;
+        if (64 * hop_waves(KK, false) * nrb > 1024) return false;
+        static const int max_lds = [] {
+            int dev = 0, v = 65536;
+            if (hipGetDevice(&dev) == hipSuccess &&
+                hipDeviceGetAttribute(&v, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) != hipSuccess)
+                v = 65536;
+            return v;
+        }();
+        const unsigned region = (hop_smem_bytes<S>(KK, loc) + 15u) & ~15u;
+        if ((long)region * nrb > (long)max_lds) return false;
+        const dim3 grid(blocks);
+#define DWF_MULTI(PMV)                                                                                   \
+    (nrb == 2 ? launch_hop_multi_pm<S, PMV, 2>(KK, grid, region, items, meta, nitems, order, st)        \
+              : launch_hop_multi_pm<S, PMV, 4>(KK, grid, region, items, meta, nitems, order, st))
+        switch (pm) {
+            case 0: DWF_MULTI(0); break;
+            case 1: DWF_MULTI(1); break;
+            case 2: DWF_MULTI(2); break;
+            default: DWF_MULTI(-1); break;
+        }
+#undef DWF_MULTI
+        DWF_HIP(hipGetLastError());
+        return true;
+    }
+}
+
 template <class S>
 static void launch_hop_batch_t(int KK, const HopParams* items, const int* meta, int nitems, int blocks, int nrb,
                                int order, bool loc, int pm, hipStream_t st) {
+    if (launch_hop_multi<S>(KK, blocks, nrb, order, loc, pm, items, meta, nitems, st)) return;
     dim3 grid(blocks), block(64 * hop_waves(KK, sizeof(S) == 8));
     const unsigned smem_b = hop_smem_bytes<S>(KK, loc);
     if (nrb == 1) {

@@ -1,4 +1,6 @@
 // Slot-aware vector kernels for batched solves; see slot_blas.h.
+#include <type_traits>
+
 #include "slot_blas.h"
 #include "blas.h"
 #include "dwf_internal.h"
@@ -58,7 +60,26 @@ __global__ __launch_bounds__(BT) void bcg_p2_kernel(void* pd, const void* ps, co
     if (sv[CG_DONE] != 0.0) return;   // block-uniform
     using RP = typename Traits<SP>::R;
     const RP be = RP(sv[CG_BETA]);
-    if constexpr (fpack<SR>() == fpack<SP>()) {
+    if constexpr (std::is_same<SR, float>::value && std::is_same<SP, float>::value) {
+        // FP32: two complex numbers (16 bytes) per lane, two steps with all
+        // loads issued first (slot offsets and sizes are even)
+        const float4* r4 = reinterpret_cast<const float4*>(static_cast<const float2*>(r) + d.off);
+        const float4* s4 = reinterpret_cast<const float4*>(static_cast<const float2*>(ps) + d.off);
+        float4* d4 = reinterpret_cast<float4*>(static_cast<float2*>(pd) + d.off);
+        const long n2 = d.n / 2, stride = (long)d.nb * BT;
+        for (long i = (long)b * BT + threadIdx.x; i < n2; i += 2 * stride) {
+            const long i1 = i + stride;
+            const bool two = i1 < n2;
+            const float4 ra = r4[i], pa = s4[i];
+            float4 rb = ra, pb = pa;
+            if (two) {
+                rb = r4[i1];
+                pb = s4[i1];
+            }
+            d4[i] = make_float4(ra.x + be * pa.x, ra.y + be * pa.y, ra.z + be * pa.z, ra.w + be * pa.w);
+            if (two) d4[i1] = make_float4(rb.x + be * pb.x, rb.y + be * pb.y, rb.z + be * pb.z, rb.w + be * pb.w);
+        }
+    } else if constexpr (fpack<SR>() == fpack<SP>()) {
         for (long i = (long)b * BT + threadIdx.x; i < d.n; i += (long)d.nb * BT) {
             const long k = d.off + i;
             typename Traits<SR>::R rr, ri;
@@ -100,7 +121,32 @@ __global__ __launch_bounds__(BT) void bcg_accx_kernel(void* x, const void* ring,
     using RX = typename Traits<SX>::R;
     using RP = typename Traits<SP>::R;
     const size_t qb = (size_t)N * cbytes<SP>();   // bytes of one ring slot
-    if constexpr (fpack<SX>() == fpack<SP>()) {
+    if constexpr (std::is_same<SX, float>::value && std::is_same<SP, float>::value) {
+        // FP32: 16 bytes per lane, the loads of every ring term first, the
+        // updates in ring order (x rounded after each term: the same bits)
+        constexpr int QMAX = 16;
+        float4* x4 = reinterpret_cast<float4*>(static_cast<float2*>(x) + d.off);
+        const float4* p4 = reinterpret_cast<const float4*>(static_cast<const float2*>(ring) + d.off);
+        const long n2 = d.n / 2, q2 = N / 2;
+        for (long i = (long)b * BT + threadIdx.x; i < n2; i += (long)d.nb * BT) {
+            float4 p[QMAX];
+#pragma unroll
+            for (int q = 0; q < QMAX; ++q)
+                if (q < cnt && al[q] != 0.0) p[q] = p4[(long)q * q2 + i];
+            float4 v = x4[i];
+#pragma unroll
+            for (int q = 0; q < QMAX; ++q) {
+                if (q < cnt && al[q] != 0.0) {
+                    const float a = (float)al[q];
+                    v.x = v.x + a * p[q].x;
+                    v.y = v.y + a * p[q].y;
+                    v.z = v.z + a * p[q].z;
+                    v.w = v.w + a * p[q].w;
+                }
+            }
+            x4[i] = v;
+        }
+    } else if constexpr (fpack<SX>() == fpack<SP>()) {
         for (long i = (long)b * BT + threadIdx.x; i < d.n; i += (long)d.nb * BT) {
             const long k = d.off + i;
             RX xr, xi;
@@ -273,7 +319,8 @@ static void bcg_accx_t1(int kp, void* x, const void* ring, long N, const double*
 }
 void bcg_accx(int kx, int kp, void* x, const void* ring, long N, const double* alpha, int astride, int cnt,
               const SlotDesc* slots, int nslots, int blocks, hipStream_t st) {
-    DWF_REQUIRE(cnt >= 1 && cnt <= astride, DWF_EINVAL, "ring count out of range");
+    DWF_REQUIRE(cnt >= 1 && cnt <= astride && cnt <= 16, DWF_EINVAL, "ring count out of range");
+    DWF_REQUIRE(N % 2 == 0, DWF_EINVAL, "batch vectors hold an even number of complex numbers");
     BDISPATCH1(kx, bcg_accx_t1, kp, x, ring, N, alpha, astride, cnt, slots, nslots, blocks, st);
     DWF_HIP(hipGetLastError());
 }
