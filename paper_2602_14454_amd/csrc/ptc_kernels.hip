@@ -17,6 +17,9 @@
 namespace dwf {
 
 constexpr int PT = 256;
+#ifndef DWF_PTC_COMMUTE
+#define DWF_PTC_COMMUTE 1
+#endif
 
 __device__ __forceinline__ float2 cmul(float2 a, float2 b) {
     return make_float2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
@@ -119,7 +122,11 @@ __device__ __forceinline__ bool path_input(const PtcLayerParams& P, int q, int b
 // path loop is outside the channel loop: a hop path's link (9 complex) and
 // neighbour index are loaded once per thread and serve every input channel,
 // and the weights of a path are read with wave-uniform addresses.
-template <int AC>
+// COMMUTE: the spin weights act on spin and the link on colour, so
+//   sum_b W^{ab} L v^b = L (sum_b W^{ab} v^b);
+// with more input than output channels (the second layer, 8 -> 1) the
+// channels are combined first and transported once per output channel.
+template <int AC, bool COMMUTE>
 __global__ __launch_bounds__(PT) void ptc_layer_kernel(PtcLayerParams P) {
     const long i = (long)blockIdx.x * PT + threadIdx.x;
     if (i >= P.Vh) return;
@@ -162,21 +169,44 @@ __global__ __launch_bounds__(PT) void ptc_layer_kernel(PtcLayerParams P) {
 #pragma unroll
                 for (int e = 0; e < 9; ++e) L[e] = P.links[lidx(d, e, i, Vhp, 8)];
             }
-            for (int b = 0; b < P.B; ++b) {
-                float2 v[12], t[12];
-                load12(P.in_hop, ((long)b * P.Ls + s) * 12, y, Vhp, v);
-#pragma unroll
-                for (int sp = 0; sp < 4; ++sp)
-#pragma unroll
-                    for (int a = 0; a < 3; ++a) {
-                        float2 c = make_float2(0.f, 0.f);
-#pragma unroll
-                        for (int bb = 0; bb < 3; ++bb) cfma(c, L[a * 3 + bb], v[sp * 3 + bb]);
-                        t[sp * 3 + a] = c;
-                    }
+            if constexpr (COMMUTE) {
+                float2 m[AC][12];
 #pragma unroll
                 for (int a = 0; a < AC; ++a)
-                    spin_apply(P.W + (((long)(1 + d) * P.A + a0 + a) * P.B + b) * 16, t, acc[a]);
+#pragma unroll
+                    for (int k = 0; k < 12; ++k) m[a][k] = make_float2(0.f, 0.f);
+                for (int b = 0; b < P.B; ++b) {
+                    float2 v[12];
+                    load12(P.in_hop, ((long)b * P.Ls + s) * 12, y, Vhp, v);
+#pragma unroll
+                    for (int a = 0; a < AC; ++a)
+                        spin_apply(P.W + (((long)(1 + d) * P.A + a0 + a) * P.B + b) * 16, v, m[a]);
+                }
+#pragma unroll
+                for (int a = 0; a < AC; ++a)
+#pragma unroll
+                    for (int sp = 0; sp < 4; ++sp)
+#pragma unroll
+                        for (int c3 = 0; c3 < 3; ++c3)
+#pragma unroll
+                            for (int bb = 0; bb < 3; ++bb) cfma(acc[a][sp * 3 + c3], L[c3 * 3 + bb], m[a][sp * 3 + bb]);
+            } else {
+                for (int b = 0; b < P.B; ++b) {
+                    float2 v[12], t[12];
+                    load12(P.in_hop, ((long)b * P.Ls + s) * 12, y, Vhp, v);
+#pragma unroll
+                    for (int sp = 0; sp < 4; ++sp)
+#pragma unroll
+                        for (int a = 0; a < 3; ++a) {
+                            float2 c = make_float2(0.f, 0.f);
+#pragma unroll
+                            for (int bb = 0; bb < 3; ++bb) cfma(c, L[a * 3 + bb], v[sp * 3 + bb]);
+                            t[sp * 3 + a] = c;
+                        }
+#pragma unroll
+                    for (int a = 0; a < AC; ++a)
+                        spin_apply(P.W + (((long)(1 + d) * P.A + a0 + a) * P.B + b) * 16, t, acc[a]);
+                }
             }
         }
     }
@@ -395,9 +425,17 @@ void ptc_layer(const PtcLayerParams& P, hipStream_t st) {
     DWF_REQUIRE(P.A >= 1 && P.B >= 1 && P.Ls >= 1 && P.Vh >= 1, DWF_EINVAL, "bad PTC layer shape");
     const int ac = P.A % 4 == 0 ? 4 : (P.A % 2 == 0 ? 2 : 1);
     dim3 grid((unsigned)((P.Vh + PT - 1) / PT), (unsigned)P.Ls, (unsigned)(P.A / ac));
-    if (ac == 4) hipLaunchKernelGGL(ptc_layer_kernel<4>, grid, dim3(PT), 0, st, P);
-    else if (ac == 2) hipLaunchKernelGGL(ptc_layer_kernel<2>, grid, dim3(PT), 0, st, P);
-    else hipLaunchKernelGGL(ptc_layer_kernel<1>, grid, dim3(PT), 0, st, P);
+    const bool commute = DWF_PTC_COMMUTE && P.B > ac;   // fewer transports when the channels are combined first
+    if (ac == 4) {
+        if (commute) hipLaunchKernelGGL((ptc_layer_kernel<4, true>), grid, dim3(PT), 0, st, P);
+        else hipLaunchKernelGGL((ptc_layer_kernel<4, false>), grid, dim3(PT), 0, st, P);
+    } else if (ac == 2) {
+        if (commute) hipLaunchKernelGGL((ptc_layer_kernel<2, true>), grid, dim3(PT), 0, st, P);
+        else hipLaunchKernelGGL((ptc_layer_kernel<2, false>), grid, dim3(PT), 0, st, P);
+    } else {
+        if (commute) hipLaunchKernelGGL((ptc_layer_kernel<1, true>), grid, dim3(PT), 0, st, P);
+        else hipLaunchKernelGGL((ptc_layer_kernel<1, false>), grid, dim3(PT), 0, st, P);
+    }
     DWF_HIP(hipGetLastError());
 }
 
