@@ -38,6 +38,8 @@ sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0   # MI355X HBM3E, published
 
+# Workloads by label: c1 a 4^4, Ls = 8 lattice small enough for the oracle's
+# solve; c2 16^3x32, Ls = 16; c3 24^3x48, Ls = 16 (the default).
 CONFIGS = {
     "c2": dict(dims=(16, 16, 16, 32), Ls=16, M0=1.6, m=0.01, b=1.0, c=0.0, alpha=0.5, eps=0.5,
                seed=11, src_seed=12, nsmear=3, rho=0.1),

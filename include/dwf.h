@@ -98,11 +98,11 @@ typedef struct {
                              DWF_EINVAL otherwise) */
 } dwf_solve_params;
 
-/* Solve report.  Against the survey's sketch of this struct: `iters` is the
- * total of inner CG iterations over all defect-correction steps (what the
- * sketch calls inner_iters_total; for plain FP64 CGNR the two counts
- * coincide), and the 4D residual is not a field because dwf_solve receives
- * b5 only: it comes from dwf_residual_4d(x4, b4) after dwf_project_4d. */
+/* Solve report.  `iters` is the total of inner CG iterations over all
+ * defect-correction steps (the total inner count; for plain FP64 CGNR it is
+ * the CGNR iteration count).  The 4D residual is not a field because
+ * dwf_solve receives b5 only: it comes from dwf_residual_4d(x4, b4) after
+ * dwf_project_4d. */
 typedef struct {
     int    iters;              /* total CG iterations (each = one D^ and one D^dag) */
     int    outer_iters;        /* defect-correction steps */
