@@ -95,6 +95,29 @@ namespace dwf {
 #ifndef DWF_HOP_PREFETCH64
 #define DWF_HOP_PREFETCH64 0
 #endif
+// Pipelined loop: request the first two directions' neighbour spinors in the
+// block prologue, together with the link staging loads, instead of after the
+// block barrier that publishes the staged tables.  Measured slower (FP32 hop
+// 409 -> 419 us on 24^3x48, Ls = 16): off.
+#ifndef DWF_HOP_EARLY
+#define DWF_HOP_EARLY 0
+#endif
+// Staging of the tile's links and neighbour indices with every load issued
+// before the first LDS write (1), or as a loop over the block's threads (0:
+// the loop waits for each load in turn).  FP32 hop on 24^3x48, Ls = 16:
+// 422 -> 409 us; FP64 869 -> 881 us, so FP64 keeps the loop.
+#ifndef DWF_HOP_STAGE_BATCH
+#define DWF_HOP_STAGE_BATCH 1
+#endif
+#ifndef DWF_HOP_STAGE_BATCH64
+#define DWF_HOP_STAGE_BATCH64 0
+#endif
+// FP32: the hop results (hs) in LDS of their own rather than over the staged
+// links (4 blocks of 35.6 KB per CU still fit), which saves one block
+// barrier.  Measured without gain (409 vs 408 us): off.
+#ifndef DWF_HOP_HS_SEP32
+#define DWF_HOP_HS_SEP32 0
+#endif
 // Cache policy of the streamed accesses (the outputs, the local term and
 // the fused update, each touched once): 0 default, 2 non-temporal, so that
 // they do not displace the neighbour lines that later tiles re-read from L2.
@@ -420,15 +443,14 @@ __device__ __forceinline__ void decode_group(u32x4 w, typename Traits<S>::R (&v)
     }
 }
 
+// neighbour site index y given (hop_fetch_at) or read from the staged table
 template <class S, int G>
-__device__ __forceinline__ void hop_fetch(const HopParams& P, const HopRes& R_, unsigned gb, int D, const int (&s)[G],
-                                          const unsigned* lnbr, int j, u32x4 (&raw)[G][12 / fpack<S>()],
-                                          unsigned& yg) {
+__device__ __forceinline__ void hop_fetch_at(const HopParams& P, const HopRes& R_, unsigned gb, unsigned y,
+                                             const int (&s)[G], u32x4 (&raw)[G][12 / fpack<S>()], unsigned& yg) {
     constexpr unsigned CB = cbytes<S>();
     constexpr int PK = fpack<S>();
     constexpr int NGR = 12 / PK;
     static_assert(PK * CB == 16, "16-byte field groups expected");
-    const unsigned y = lnbr[D * 16 + j];
     yg = y * (unsigned)PK * CB;
 #pragma unroll
     for (int g = 0; g < G; ++g) {
@@ -437,6 +459,13 @@ __device__ __forceinline__ void hop_fetch(const HopParams& P, const HopRes& R_, 
 #pragma unroll
         for (int q = 0; q < NGR; ++q) raw[g][q] = __builtin_amdgcn_raw_buffer_load_b128(R_.in, vb, (unsigned)q * gb, 0);
     }
+}
+
+template <class S, int G>
+__device__ __forceinline__ void hop_fetch(const HopParams& P, const HopRes& R_, unsigned gb, int D, const int (&s)[G],
+                                          const unsigned* lnbr, int j, u32x4 (&raw)[G][12 / fpack<S>()],
+                                          unsigned& yg) {
+    hop_fetch_at<S, G>(P, R_, gb, lnbr[D * 16 + j], s, raw, yg);
 }
 
 template <class S, int G, int PM>
@@ -548,7 +577,11 @@ template <class S, int KK> struct HopSmem {
     static constexpr int HSK = 24 * 64 + (sizeof(R) == 4 ? 16 : 8);
     static constexpr unsigned hs_b = KK * HSK * sizeof(R);
     static constexpr unsigned lnk_b = lnk_entries<S>() * 16 + 128 * 4;
-    static constexpr unsigned mx = hs_b > lnk_b ? hs_b : lnk_b;
+    // SEP: hs after the staged tables instead of over them (no block
+    // barrier between the last link read and the first hs write)
+    static constexpr bool SEP = sizeof(S) == 4 && DWF_HOP_HS_SEP32;
+    static constexpr unsigned hs_off = SEP ? ((lnk_b + 15u) & ~15u) : 0u;
+    static constexpr unsigned mx = SEP ? hs_off + hs_b : (hs_b > lnk_b ? hs_b : lnk_b);
     static constexpr unsigned r0 = (mx + 15u) & ~15u;
     static constexpr unsigned red_off = r0;
     static constexpr unsigned loc_off = r0 + 32;
@@ -575,7 +608,7 @@ __device__ __forceinline__ void hop_tile(const HopParams& P, long tile, int rhs,
     constexpr int NW = hop_waves(KK, sizeof(S) == 8);
     constexpr int NTHR = 64 * NW;
     unsigned char* own = smem + (size_t)sub * region;
-    R* hs = reinterpret_cast<R*>(own);   // hs[kk][r][lane] at kk * HSK + r * 64 + lane
+    R* hs = reinterpret_cast<R*>(own + L::hs_off);   // hs[kk][r][lane] at kk * HSK + r * 64 + lane
     constexpr int HSK = L::HSK;
     u32x4* lnk = reinterpret_cast<u32x4*>(smem);
     unsigned* lnbr = reinterpret_cast<unsigned*>(smem + lnk_entries<S>() * 16);
@@ -614,9 +647,86 @@ __device__ __forceinline__ void hop_tile(const HopParams& P, long tile, int rhs,
     R_.links = make_rsrc(P.links, 8u * link_ng(CB) * (unsigned)P.Vhp * link_lp(CB) * CB);
     R_.nbr = make_rsrc(P.nbr, 8u * (unsigned)P.Vhp * 4u);
 
-    if constexpr (DWF_HOP_LDS_LINKS) {
-        // the tile's links (16-byte groups) and neighbour indices, once per block;
-        // every lane-dependent offset is in the vector operand
+    // Slice groups of this wave, and the pipelined loop's first two
+    // directions (EARLY: their neighbour spinors are requested before the
+    // block barrier, with the neighbour indices read per lane).
+    constexpr int G = hop_kpw(KK, sizeof(S) == 8);
+    constexpr int PF = PM < 0 ? 0 : (sizeof(S) == 8 ? DWF_HOP_PREFETCH64 : DWF_HOP_PREFETCH);
+    constexpr bool EARLY = DWF_HOP_EARLY && PF == 2 && DWF_HOP_LDS_LINKS &&
+                           (sizeof(S) == 8 ? DWF_HOP_STAGE_BATCH64 : DWF_HOP_STAGE_BATCH);
+    constexpr int NGR_ = 12 / fpack<S>();
+    int sg[G];
+#pragma unroll
+    for (int g = 0; g < G; ++g) sg[g] = 4 * (w * G + g) + sc;
+    u32x4 ra[G][NGR_], rb[G][NGR_];
+    unsigned ya = 0, yb = 0;
+    // pre-mix coefficients of the wave's slices (read before the tile's
+    // loads, so that waiting for them does not wait for the spinors)
+    R pd[G][2], pe[G][2], kr[G];
+    {
+        const R* pre = static_cast<const R*>(P.pre);
+#pragma unroll
+        for (int g = 0; g < G; ++g) {
+            const int sc_ = min(sg[g], LS_MAX - 1);
+            pd[g][0] = pre ? pre[0 * 16 + sc_] : R(1);
+            pd[g][1] = pre ? pre[1 * 16 + sc_] : R(1);
+            pe[g][0] = pre ? pre[2 * 16 + sc_] : R(0);
+            pe[g][1] = pre ? pre[3 * 16 + sc_] : R(0);
+            // diagonal pre-mix (mode 1; the host guarantees d_up != 0 on valid
+            // slices): lower/upper ratio inside the projection, d_up at the end
+            kr[g] = (pre_mode_of<PM>(P) == 1 && pd[g][0] != R(0)) ? pd[g][1] / pd[g][0] : R(1);
+        }
+    }
+
+    constexpr bool SBATCH = sizeof(S) == 8 ? DWF_HOP_STAGE_BATCH64 : DWF_HOP_STAGE_BATCH;
+    if constexpr (DWF_HOP_LDS_LINKS && SBATCH) {
+        // the tile's links (16-byte groups) and neighbour indices, once per
+        // block; every lane-dependent offset is in the vector operand.  All
+        // loads are issued before the first LDS write (a loop with a runtime
+        // trip count would wait for each load in turn).  Threads past the
+        // table's end read and rewrite its last entry.
+        const unsigned Vhp = (unsigned)P.Vhp;
+        constexpr int NE = lnk_entries<S>();
+        constexpr int IT = (NE + NTHR - 1) / NTHR;    // blockDim.x >= NTHR
+        constexpr int IB = (128 + NTHR - 1) / NTHR;
+        unsigned y0 = 0, y1 = 0;
+        if constexpr (EARLY) {
+            y0 = __builtin_amdgcn_raw_buffer_load_b32(R_.nbr, (unsigned)sx * 4u, 0u, DWF_HOP_NT_LINK);
+            y1 = __builtin_amdgcn_raw_buffer_load_b32(R_.nbr, (unsigned)sx * 4u, Vhp * 4u, DWF_HOP_NT_LINK);
+        }
+        u32x4 lv[IT];
+        unsigned nv[IB];
+#pragma unroll
+        for (int i = 0; i < IT; ++i) {
+            const int e = min((int)threadIdx.x + i * (int)blockDim.x, NE - 1);
+            const int dg = e >> 4, jj = e & 15;
+            const long se = tile * 16 + jj;
+            const unsigned sxe = (unsigned)(se < Vh ? se : Vh - 1);
+            lv[i] = __builtin_amdgcn_raw_buffer_load_b128(R_.links, sxe * 16u + (unsigned)dg * Vhp * 16u, 0u,
+                                                          DWF_HOP_NT_LINK);
+        }
+#pragma unroll
+        for (int i = 0; i < IB; ++i) {
+            const int e = min((int)threadIdx.x + i * (int)blockDim.x, 127);
+            const int d = e >> 4, jj = e & 15;
+            const long se = tile * 16 + jj;
+            const unsigned sxe = (unsigned)(se < Vh ? se : Vh - 1);
+            nv[i] = __builtin_amdgcn_raw_buffer_load_b32(R_.nbr, sxe * 4u + (unsigned)d * Vhp * 4u, 0u,
+                                                         DWF_HOP_NT_LINK);
+        }
+        if constexpr (EARLY) {
+            hop_fetch_at<S, G>(P, R_, gb, y0, sg, ra, ya);
+            hop_fetch_at<S, G>(P, R_, gb, y1, sg, rb, yb);
+        }
+        // unconditional stores (a guarded store lets the compiler sink its
+        // load behind the guard and wait for it there)
+#pragma unroll
+        for (int i = 0; i < IT; ++i) lnk[min((int)threadIdx.x + i * (int)blockDim.x, NE - 1)] = lv[i];
+#pragma unroll
+        for (int i = 0; i < IB; ++i) lnbr[min((int)threadIdx.x + i * (int)blockDim.x, 127)] = nv[i];
+    }
+    if constexpr (DWF_HOP_LDS_LINKS && !SBATCH) {
+        // the same tables, one entry per thread and step
         const unsigned Vhp = (unsigned)P.Vhp;
         for (int e = threadIdx.x; e < lnk_entries<S>(); e += blockDim.x) {
             const int dg = e >> 4, jj = e & 15;
@@ -637,39 +747,34 @@ __device__ __forceinline__ void hop_tile(const HopParams& P, long tile, int rhs,
         // local-term tile: group (s, q) of site jj at locT[(s * NGR + q) * 16 + jj];
         // slices s >= Ls are zero (they meet zero columns of the local mixes)
         if (P.loc != nullptr) {
-            for (int e = tid; e < KK * 4 * L::NGR * 16; e += NTHR) {
+            constexpr int NL = KK * 4 * L::NGR * 16;
+            constexpr int IL = (NL + NTHR - 1) / NTHR;
+            u32x4 lt[IL];
+#pragma unroll
+            for (int i = 0; i < IL; ++i) {
+                const int e = min(tid + i * NTHR, NL - 1);
                 const int jj = e & 15, g = e >> 4;
                 const long se = tile * 16 + jj;
                 const unsigned sxe = (unsigned)(se < Vh ? se : Vh - 1);
-                u32x4 v = {0u, 0u, 0u, 0u};
-                if (g < Ls * L::NGR)
-                    v = __builtin_amdgcn_raw_buffer_load_b128(R_.loc, sxe * 16u + (unsigned)g * gb, 0u, DWF_HOP_NT_LOAD);
-                locT[e] = v;
+                const int gc = g < Ls * L::NGR ? g : 0;
+                lt[i] = __builtin_amdgcn_raw_buffer_load_b128(R_.loc, sxe * 16u + (unsigned)gc * gb, 0u, DWF_HOP_NT_LOAD);
+            }
+#pragma unroll
+            for (int i = 0; i < IL; ++i) {
+                const int e = min(tid + i * NTHR, NL - 1);
+                const u32x4 z = {0u, 0u, 0u, 0u};
+                locT[e] = (e >> 4) < Ls * L::NGR ? lt[i] : z;
             }
         }
     }
     if constexpr (DWF_HOP_LDS_LINKS || L::LOC) __syncthreads();
 
+    R h[G][24];
     {
-        constexpr int G = hop_kpw(KK, sizeof(S) == 8);
-        R h[G][24];
-        int sg[G];
-        R pd[G][2], pe[G][2], kr[G];
-        const R* pre = static_cast<const R*>(P.pre);
 #pragma unroll
-        for (int g = 0; g < G; ++g) {
-            sg[g] = 4 * (w * G + g) + sc;
-            const int sc_ = min(sg[g], LS_MAX - 1);
-            pd[g][0] = pre ? pre[0 * 16 + sc_] : R(1);
-            pd[g][1] = pre ? pre[1 * 16 + sc_] : R(1);
-            pe[g][0] = pre ? pre[2 * 16 + sc_] : R(0);
-            pe[g][1] = pre ? pre[3 * 16 + sc_] : R(0);
-            // diagonal pre-mix (mode 1; the host guarantees d_up != 0 on valid
-            // slices): lower/upper ratio inside the projection, d_up at the end
-            kr[g] = (pre_mode_of<PM>(P) == 1 && pd[g][0] != R(0)) ? pd[g][1] / pd[g][0] : R(1);
+        for (int g = 0; g < G; ++g)
 #pragma unroll
             for (int k = 0; k < 24; ++k) h[g][k] = 0;
-        }
         // Loop over the 8 hop directions.  Its unrolling (DWF_HOP_UNROLL)
         // trades registers for loads in flight: with 1, nothing of direction
         // d+1 (its links in particular) is hoisted above direction d.
@@ -679,16 +784,14 @@ __device__ __forceinline__ void hop_tile(const HopParams& P, long tile, int rhs,
             ynb[d] = (DWF_HOP_NBR_PRELOAD && !DWF_HOP_LDS_LINKS)
                          ? __builtin_amdgcn_raw_buffer_load_b32(R_.nbr, (unsigned)sx * 4u, (unsigned)d * (unsigned)P.Vhp * 4u, 0)
                          : 0u;
-        constexpr int PF = PM < 0 ? 0 : (sizeof(S) == 8 ? DWF_HOP_PREFETCH64 : DWF_HOP_PREFETCH);
         if constexpr (PF == 2 && DWF_HOP_LDS_LINKS) {
             // fully unrolled, double-buffered: direction d is a compile-time
             // constant in each step (its spin structure folds), and the loads
             // of d+1 are issued before the arithmetic of d
-            constexpr int NGR = 12 / fpack<S>();
-            u32x4 ra[G][NGR], rb[G][NGR];
-            unsigned ya, yb;
-            hop_fetch<S, G>(P, R_, gb, 0, sg, lnbr, j, ra, ya);
-            hop_fetch<S, G>(P, R_, gb, 1, sg, lnbr, j, rb, yb);
+            if constexpr (!EARLY) {
+                hop_fetch<S, G>(P, R_, gb, 0, sg, lnbr, j, ra, ya);
+                hop_fetch<S, G>(P, R_, gb, 1, sg, lnbr, j, rb, yb);
+            }
             __builtin_amdgcn_sched_barrier(0);
             hop_apply<S, G, PM>(P, R_, gb, 0, sg, pd, pe, kr, h, lnk, ra, ya, j);
             hop_fetch<S, G>(P, R_, gb, 2, sg, lnbr, j, ra, ya);
@@ -714,9 +817,6 @@ __device__ __forceinline__ void hop_tile(const HopParams& P, long tile, int rhs,
         } else if constexpr (PF == 1 && DWF_HOP_LDS_LINKS) {
             // ping-pong over two raw buffers: the loads of the next direction
             // are in flight while the current one is computed
-            constexpr int NGR = 12 / fpack<S>();
-            u32x4 ra[G][NGR], rb[G][NGR];
-            unsigned ya, yb;
             hop_fetch<S, G>(P, R_, gb, 0, sg, lnbr, j, ra, ya);
 #pragma unroll 1
             for (int d = 0; d < 8; d += 2) {
@@ -750,12 +850,13 @@ __device__ __forceinline__ void hop_tile(const HopParams& P, long tile, int rhs,
 #pragma unroll
             for (int k = 0; k < 24; ++k) h[g][k] = inval ? R(0) : h[g][k];
         }
-        __syncthreads();   // hs shares storage with the staged links
-#pragma unroll
-        for (int g = 0; g < G; ++g)
-#pragma unroll
-            for (int k = 0; k < 24; ++k) hs[(w * G + g) * HSK + k * 64 + lane] = h[g][k];
     }
+    if constexpr (!L::SEP) __syncthreads();   // hs shares storage with the staged links
+
+#pragma unroll
+    for (int g = 0; g < G; ++g)
+#pragma unroll
+        for (int k = 0; k < 24; ++k) hs[(w * G + g) * HSK + k * 64 + lane] = h[g][k];
     __syncthreads();
 
     // A operands: A[m][k] = MAT[chi][row m = j][col 4*kk + sc].  A dense
@@ -996,16 +1097,35 @@ __device__ __forceinline__ void hop_tile(const HopParams& P, long tile, int rhs,
             static_assert(PKU == 2, "fused update expects FP32 fields in component pairs");
             __syncthreads();
             const unsigned gbu = (unsigned)P.Vhp * 16u;
-            for (int e = tid; e < Ls * 6 * 16; e += NTHR) {
+            // every LDS and global read of the thread first, then the
+            // updates (a loop with a runtime trip count would wait for each
+            // iteration's reads in turn); threads past the end read the last
+            // entry again and store nothing
+            const int nU = Ls * 6 * 16;
+            constexpr int IU = (4 * KK * 6 * 16 + NTHR - 1) / NTHR;
+            float2 av[IU], bv[IU];
+            u32x4 uv[IU];
+#pragma unroll
+            for (int i = 0; i < IU; ++i) {
+                const int e = min(tid + i * NTHR, nU - 1);
                 const int jj = e & 15, g = e >> 4;
                 const int sl = g / 6, q2 = g - sl * 6;
                 const long se = tile * 16 + jj;
                 const float* run0 = hs + (sl >> 2) * HSK + 2 * ((sl & 3) * 16 + jj);
-                const float2 a = *reinterpret_cast<const float2*>(run0 + (2 * (2 * q2)) * 64);
-                const float2 b = *reinterpret_cast<const float2*>(run0 + (2 * (2 * q2 + 1)) * 64);
-                if (se < Vh) {
+                av[i] = *reinterpret_cast<const float2*>(run0 + (2 * (2 * q2)) * 64);
+                bv[i] = *reinterpret_cast<const float2*>(run0 + (2 * (2 * q2 + 1)) * 64);
+                const unsigned sxe = (unsigned)(se < Vh ? se : Vh - 1);
+                uv[i] = __builtin_amdgcn_raw_buffer_load_b128(R_.upd, sxe * 16u + (unsigned)g * gbu, 0u, DWF_HOP_NT_LOAD);
+            }
+#pragma unroll
+            for (int i = 0; i < IU; ++i) {
+                const int e = tid + i * NTHR;
+                const int jj = e & 15, g = e >> 4;
+                const long se = tile * 16 + jj;
+                if (e < nU && se < Vh) {
                     const unsigned off = (unsigned)se * 16u + (unsigned)g * gbu;
-                    const u32x4 u = __builtin_amdgcn_raw_buffer_load_b128(R_.upd, off, 0u, DWF_HOP_NT_LOAD);
+                    const u32x4 u = uv[i];
+                    const float2 a = av[i], b = bv[i];
                     float v0 = __uint_as_float(u.x) - ua * a.x, v1 = __uint_as_float(u.y) - ua * a.y;
                     float v2 = __uint_as_float(u.z) - ua * b.x, v3 = __uint_as_float(u.w) - ua * b.y;
                     u32x4 o;
@@ -1020,25 +1140,35 @@ __device__ __forceinline__ void hop_tile(const HopParams& P, long tile, int rhs,
             // whole 16-byte groups of 16 consecutive sites
             __syncthreads();
             const __amdgpu_buffer_rsrc_t dst = P.out ? R_.out : R_.out2;
-            for (int e = tid; e < Ls * L::NGR * 16; e += NTHR) {
+            // all LDS reads first, then the stores (as in the update above)
+            const int nO = Ls * L::NGR * 16;
+            constexpr int IO = (4 * KK * L::NGR * 16 + NTHR - 1) / NTHR;
+            u32x4 vv[IO];
+#pragma unroll
+            for (int i = 0; i < IO; ++i) {
+                const int e = min(tid + i * NTHR, nO - 1);
                 const int jj = e & 15, g = e >> 4;
                 const int sl = g / L::NGR, q = g - sl * L::NGR;
-                const long se = tile * 16 + jj;
                 const R* run0 = hs + (sl >> 2) * HSK + (sl & 3) * 16 * (int)(CB / 4) + jj * (int)(CB / 4);
-                u32x4 v;
                 if constexpr (sizeof(S) == 4) {
                     const u32x2 a = *reinterpret_cast<const u32x2*>(run0 + (2 * (2 * q)) * 64);
                     const u32x2 b = *reinterpret_cast<const u32x2*>(run0 + (2 * (2 * q + 1)) * 64);
-                    v.x = a.x; v.y = a.y; v.z = b.x; v.w = b.y;
+                    vv[i].x = a.x; vv[i].y = a.y; vv[i].z = b.x; vv[i].w = b.y;
                 } else {
                     const unsigned* r = reinterpret_cast<const unsigned*>(run0);
-                    v.x = r[(2 * (4 * q)) * 64];
-                    v.y = r[(2 * (4 * q + 1)) * 64];
-                    v.z = r[(2 * (4 * q + 2)) * 64];
-                    v.w = r[(2 * (4 * q + 3)) * 64];
+                    vv[i].x = r[(2 * (4 * q)) * 64];
+                    vv[i].y = r[(2 * (4 * q + 1)) * 64];
+                    vv[i].z = r[(2 * (4 * q + 2)) * 64];
+                    vv[i].w = r[(2 * (4 * q + 3)) * 64];
                 }
-                if (se < Vh)
-                    __builtin_amdgcn_raw_buffer_store_b128(v, dst, (unsigned)se * 16u + (unsigned)g * gb, 0u,
+            }
+#pragma unroll
+            for (int i = 0; i < IO; ++i) {
+                const int e = tid + i * NTHR;
+                const int jj = e & 15, g = e >> 4;
+                const long se = tile * 16 + jj;
+                if (e < nO && se < Vh)
+                    __builtin_amdgcn_raw_buffer_store_b128(vv[i], dst, (unsigned)se * 16u + (unsigned)g * gb, 0u,
                                                            DWF_HOP_NT_STORE);
             }
         }
