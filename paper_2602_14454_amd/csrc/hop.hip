@@ -112,6 +112,12 @@ namespace dwf {
 #ifndef DWF_HOP_STAGE_BATCH64
 #define DWF_HOP_STAGE_BATCH64 0
 #endif
+// FP32: stage the dense s-mix matrices in LDS with the links (the second
+// phase then reads them from LDS instead of waiting for L2 after the block
+// barriers).
+#ifndef DWF_HOP_COEF_LDS32
+#define DWF_HOP_COEF_LDS32 1
+#endif
 // FP32: the hop results (hs) in LDS of their own rather than over the staged
 // links (4 blocks of 35.6 KB per CU still fit), which saves one block
 // barrier.  Measured without gain (409 vs 408 us): off.
@@ -584,7 +590,12 @@ template <class S, int KK> struct HopSmem {
     static constexpr unsigned mx = SEP ? hs_off + hs_b : (hs_b > lnk_b ? hs_b : lnk_b);
     static constexpr unsigned r0 = (mx + 15u) & ~15u;
     static constexpr unsigned red_off = r0;
-    static constexpr unsigned loc_off = r0 + 32;
+    // FP32: the dense s-mixes (POST, LOCMIX, POST2, LOCMIX2; [2][16][16]
+    // each) staged with the links, read back in the second phase
+    static constexpr bool CST = sizeof(S) == 4 && DWF_HOP_COEF_LDS32 && DWF_HOP_STAGE_BATCH && DWF_HOP_LDS_LINKS;
+    static constexpr unsigned cst_off = r0 + 32;
+    static constexpr unsigned cst_b = CST ? 4u * MAT_ELEMS * 4u : 0u;
+    static constexpr unsigned loc_off = cst_off + cst_b;
     static constexpr unsigned loc_b = LOC ? KK * 4 * NGR * 16 * 16 : 0u;
     static constexpr unsigned bytes(bool has_loc) { return loc_off + (has_loc ? loc_b : 0u); }
 };
@@ -714,6 +725,23 @@ __device__ __forceinline__ void hop_tile(const HopParams& P, long tile, int rhs,
             nv[i] = __builtin_amdgcn_raw_buffer_load_b32(R_.nbr, sxe * 4u + (unsigned)d * Vhp * 4u, 0u,
                                                          DWF_HOP_NT_LINK);
         }
+        // dense s-mixes (FP32): 4 x 128 groups of 16 bytes; a missing matrix
+        // reads POST instead (never used)
+        constexpr int IC = L::CST ? (4 * MAT_ELEMS / 4 + NTHR - 1) / NTHR : 1;
+        u32x4 cv[IC];
+        if constexpr (L::CST) {
+            const u32x4* m0 = static_cast<const u32x4*>(P.post);
+            const u32x4* m1 = P.locmix ? static_cast<const u32x4*>(P.locmix) : m0;
+            const u32x4* m2 = P.post2 ? static_cast<const u32x4*>(P.post2) : m0;
+            const u32x4* m3 = P.locmix2 ? static_cast<const u32x4*>(P.locmix2) : m0;
+#pragma unroll
+            for (int i = 0; i < IC; ++i) {
+                const int e = min((int)threadIdx.x + i * (int)blockDim.x, 4 * MAT_ELEMS / 4 - 1);
+                const int m = e >> 7;   // MAT_ELEMS / 4 = 128 groups per matrix
+                const u32x4* src = m == 0 ? m0 : (m == 1 ? m1 : (m == 2 ? m2 : m3));
+                cv[i] = src[e & 127];
+            }
+        }
         if constexpr (EARLY) {
             hop_fetch_at<S, G>(P, R_, gb, y0, sg, ra, ya);
             hop_fetch_at<S, G>(P, R_, gb, y1, sg, rb, yb);
@@ -724,6 +752,11 @@ __device__ __forceinline__ void hop_tile(const HopParams& P, long tile, int rhs,
         for (int i = 0; i < IT; ++i) lnk[min((int)threadIdx.x + i * (int)blockDim.x, NE - 1)] = lv[i];
 #pragma unroll
         for (int i = 0; i < IB; ++i) lnbr[min((int)threadIdx.x + i * (int)blockDim.x, 127)] = nv[i];
+        if constexpr (L::CST) {
+            u32x4* cdst = reinterpret_cast<u32x4*>(smem + L::cst_off);
+#pragma unroll
+            for (int i = 0; i < IC; ++i) cdst[min((int)threadIdx.x + i * (int)blockDim.x, 4 * MAT_ELEMS / 4 - 1)] = cv[i];
+        }
     }
     if constexpr (DWF_HOP_LDS_LINKS && !SBATCH) {
         // the same tables, one entry per thread and step
@@ -902,14 +935,22 @@ __device__ __forceinline__ void hop_tile(const HopParams& P, long tile, int rhs,
     // loads a second set and each component selects its own.
     constexpr bool CHI_W = DWF_HOP_COEF_HOIST && (6 % CPW) == 0;
     constexpr bool CHI_2 = DWF_HOP_COEF_HOIST >= 2 && !CHI_W;
+    const R* cst = reinterpret_cast<const R*>(smem + L::cst_off);   // block-wide (region 0)
     auto load_a = [&](int chi, R (&ap)[KK], R (&al)[KK], R (&ap2)[KK], R (&al2)[KK]) {
 #pragma unroll
         for (int kk = 0; kk < KK; ++kk) {
             const int idx = (chi * 16 + j) * 16 + 4 * kk + sc;
-            ap[kk] = post[idx];
-            al[kk] = dense_loc ? lmix[idx] : ((has_loc && !L::LOC && j == 4 * kk + sc) ? lscale : R(0));
-            ap2[kk] = has_out2 ? post2[idx] : R(0);
-            al2[kk] = (has_out2 && has_loc && !chain) ? lmix2[idx] : R(0);
+            if constexpr (L::CST) {
+                ap[kk] = cst[idx];
+                al[kk] = dense_loc ? cst[MAT_ELEMS + idx] : ((has_loc && !L::LOC && j == 4 * kk + sc) ? lscale : R(0));
+                ap2[kk] = has_out2 ? cst[2 * MAT_ELEMS + idx] : R(0);
+                al2[kk] = (has_out2 && has_loc && !chain) ? cst[3 * MAT_ELEMS + idx] : R(0);
+            } else {
+                ap[kk] = post[idx];
+                al[kk] = dense_loc ? lmix[idx] : ((has_loc && !L::LOC && j == 4 * kk + sc) ? lscale : R(0));
+                ap2[kk] = has_out2 ? post2[idx] : R(0);
+                al2[kk] = (has_out2 && has_loc && !chain) ? lmix2[idx] : R(0);
+            }
         }
     };
     R apw[KK], alw[KK], ap2w[KK], al2w[KK];
