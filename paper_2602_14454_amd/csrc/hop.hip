@@ -112,6 +112,12 @@ namespace dwf {
 #ifndef DWF_HOP_STAGE_BATCH64
 #define DWF_HOP_STAGE_BATCH64 0
 #endif
+// Single-lattice launches of the fused CG stages use kernels compiled for
+// their epilogue kind (epilogue_kind below); 0: every launch tests its flags
+// at run time.
+#ifndef DWF_HOP_EK
+#define DWF_HOP_EK 1
+#endif
 // FP32: stage the dense s-mix matrices in LDS with the links (the second
 // phase then reads them from LDS instead of waiting for L2 after the block
 // barriers).
@@ -562,6 +568,19 @@ __host__ __device__ constexpr int hop_waves(int KK, bool f64) { return KK / hop_
 // norm.  Both kernels below call it.
 template <class S> constexpr int lnk_entries() { return 8 * link_ng(cbytes<S>()) * 16; }
 
+// Epilogue kinds compiled with their flags as constants: the fused stages of
+// the CG iteration (the generic kernel, EK = -1, tests every flag at run
+// time).  EK_PLAIN: out only.  EK_CHAIN: the D^ stage, out2 = POST2 . (POST .
+// H + loc_scale loc) with |first result|^2 reduced.  EK_UPD: the last stage,
+// upd -= alpha (POST . H + LOCMIX . loc) with |upd|^2 reduced.
+constexpr int EK_PLAIN = 1, EK_CHAIN = 2, EK_UPD = 3;
+inline int epilogue_kind(const HopParams& P) {
+    if (P.out && !P.loc && !P.out2 && !P.upd && !P.partial && P.reduce == 0) return EK_PLAIN;
+    if (!P.out && P.loc && !P.locmix && P.out2 && P.chain2 && !P.upd && P.partial && P.reduce == 1) return EK_CHAIN;
+    if (!P.out && P.loc && P.locmix && !P.out2 && P.upd && P.partial && P.reduce == 3) return EK_UPD;
+    return -1;
+}
+
 // Shared memory of one block (dynamic, bytes from the host):
 //   [0, r0)       phase 1: the tile's links and neighbour indices;
 //                 then hs, the hop result (MFMA B operand), hs[kk][r][lane]
@@ -609,13 +628,24 @@ template <class S, int KK> struct HopSmem {
 // code, barriers included, on zero-size buffer descriptors: its loads read
 // zeros and its stores are dropped.  The reduction runs when P.partial is set
 // (the same for every group of a block); part_out = nullptr skips the write.
-template <class S, int KK, int PM = -1>
+template <class S, int KK, int PM = -1, int EK = -1>
 __device__ __forceinline__ void hop_tile(const HopParams& P, long tile, int rhs, double* part_out,
                                          unsigned char* smem, int sub = 0, unsigned region = 0,
                                          bool active = true) {
     using R = typename Traits<S>::R;
     using V = typename Vec4<R>::T;
     using L = HopSmem<S, KK>;
+    // which outputs, local terms and reductions the launch has: compile-time
+    // constants for the epilogue kinds below, else read from P
+    constexpr bool EKC = EK >= 0;
+    const bool f_out = EKC ? EK == EK_PLAIN : P.out != nullptr;
+    const bool f_loc = EKC ? (EK == EK_CHAIN || EK == EK_UPD) : P.loc != nullptr;
+    const bool f_dense = EKC ? EK == EK_UPD : (P.loc != nullptr && P.locmix != nullptr);
+    const bool f_out2 = EKC ? EK == EK_CHAIN : P.out2 != nullptr;
+    const bool f_chain = EKC ? EK == EK_CHAIN : (P.out2 != nullptr && P.chain2 != 0);
+    const bool f_upd = EKC ? EK == EK_UPD : P.upd != nullptr;
+    const int f_reduce = EKC ? (EK == EK_CHAIN ? 1 : (EK == EK_UPD ? 3 : 0)) : P.reduce;
+    const bool f_partial = EKC ? EK != EK_PLAIN : P.partial != nullptr;
     constexpr int NW = hop_waves(KK, sizeof(S) == 8);
     constexpr int NTHR = 64 * NW;
     unsigned char* own = smem + (size_t)sub * region;
@@ -779,7 +809,7 @@ __device__ __forceinline__ void hop_tile(const HopParams& P, long tile, int rhs,
     if constexpr (L::LOC) {
         // local-term tile: group (s, q) of site jj at locT[(s * NGR + q) * 16 + jj];
         // slices s >= Ls are zero (they meet zero columns of the local mixes)
-        if (P.loc != nullptr) {
+        if (f_loc) {
             constexpr int NL = KK * 4 * L::NGR * 16;
             constexpr int IL = (NL + NTHR - 1) / NTHR;
             u32x4 lt[IL];
@@ -900,10 +930,10 @@ __device__ __forceinline__ void hop_tile(const HopParams& P, long tile, int rhs,
     const R* lmix = static_cast<const R*>(P.locmix);
     const R* post2 = static_cast<const R*>(P.post2);
     const R* lmix2 = static_cast<const R*>(P.locmix2);
-    const bool has_loc = P.loc != nullptr;
-    const bool dense_loc = has_loc && lmix != nullptr;
-    const bool has_out2 = P.out2 != nullptr;
-    const bool chain = has_out2 && P.chain2 != 0;
+    const bool has_loc = f_loc;
+    const bool dense_loc = f_dense;
+    const bool has_out2 = f_out2;
+    const bool chain = f_chain;
     const R lscale = R(P.loc_scale);
     constexpr int CPW = 12 / hop_waves(KK, sizeof(S) == 8);
     // per-component accesses: one instruction covers whole lines only in FP64
@@ -916,9 +946,9 @@ __device__ __forceinline__ void hop_tile(const HopParams& P, long tile, int rhs,
 
     // FP32/BF16: the primary output (out, else out2) goes through LDS; a
     // second output, if any, is stored directly
-    const bool upd = P.upd != nullptr;
+    const bool upd = f_upd;
     const R ua = upd ? R(P.upd_alpha[(long)rhs * P.upd_stride]) : R(0);
-    const bool tile_out = L::TIO && (P.out != nullptr || has_out2 || upd);
+    const bool tile_out = L::TIO && (f_out || has_out2 || upd);
     // byte offset of component cp of slice s of this lane's site; the whole
     // offset goes to the vector operand (cp depends on the wave index, which
     // the compiler does not treat as uniform: a scalar operand would be
@@ -1092,8 +1122,8 @@ __device__ __forceinline__ void hop_tile(const HopParams& P, long tile, int rhs,
         for (int i = 0; i < 4; ++i) {
             const int s = out_row<R>(sc, i);
             if (valid && s < Ls) {
-                if (P.reduce == 1) nrm += double(cr[i]) * double(cr[i]) + double(ci[i]) * double(ci[i]);
-                if (P.reduce == 2) nrm += double(dr[i]) * double(dr[i]) + double(di[i]) * double(di[i]);
+                if (f_reduce == 1) nrm += double(cr[i]) * double(cr[i]) + double(ci[i]) * double(ci[i]);
+                if (f_reduce == 2) nrm += double(dr[i]) * double(dr[i]) + double(di[i]) * double(di[i]);
                 if (!tile_out) {
                     if (upd) {   // FP64: upd has the layout of out
                         R ur, ui;
@@ -1101,11 +1131,11 @@ __device__ __forceinline__ void hop_tile(const HopParams& P, long tile, int rhs,
                         ur -= ua * cr[i];
                         ui -= ua * ci[i];
                         bstore<S, SAUX>(R_.upd, coff(s, cp), 0u, ur, ui);
-                        if (P.reduce == 3) nrm += double(ur) * double(ur) + double(ui) * double(ui);
+                        if (f_reduce == 3) nrm += double(ur) * double(ur) + double(ui) * double(ui);
                     }
-                    if (P.out) bstore<S, SAUX>(R_.out, coff(s, cp), 0u, cr[i], ci[i]);
+                    if (f_out) bstore<S, SAUX>(R_.out, coff(s, cp), 0u, cr[i], ci[i]);
                     if (has_out2) bstore<S, SAUX>(R_.out2, coff(s, cp), 0u, dr[i], di[i]);
-                } else if (P.out && has_out2) {
+                } else if (f_out && has_out2) {
                     bstore<S, SAUX>(R_.out2, coff(s, cp), 0u, dr[i], di[i]);
                 }
             }
@@ -1119,8 +1149,8 @@ __device__ __forceinline__ void hop_tile(const HopParams& P, long tile, int rhs,
                 for (int i = 0; i < 4; ++i) {
                     const int s = out_row<R>(sc, i);
                     if (s >= Ls) continue;   // rows past Ls: zero columns, and past the hs runs when KK < 4
-                    const R orr = (P.out || upd) ? cr[i] : dr[i];
-                    const R oi = (P.out || upd) ? ci[i] : di[i];
+                    const R orr = (f_out || upd) ? cr[i] : dr[i];
+                    const R oi = (f_out || upd) ? ci[i] : di[i];
                     R* run = hs + (s >> 2) * HSK + (2 * cp) * 64;
                     if (sizeof(S) == 4 || upd) {   // FP32 values (the update needs them unrounded)
                         reinterpret_cast<float2*>(run)[(s & 3) * 16 + j] = make_float2(orr, oi);
@@ -1172,7 +1202,7 @@ __device__ __forceinline__ void hop_tile(const HopParams& P, long tile, int rhs,
                     u32x4 o;
                     o.x = __float_as_uint(v0); o.y = __float_as_uint(v1); o.z = __float_as_uint(v2); o.w = __float_as_uint(v3);
                     __builtin_amdgcn_raw_buffer_store_b128(o, R_.upd, off, 0u, DWF_HOP_NT_STORE);
-                    if (P.reduce == 3)
+                    if (f_reduce == 3)
                         nrm += double(v0) * double(v0) + double(v1) * double(v1) + double(v2) * double(v2) +
                                double(v3) * double(v3);
                 }
@@ -1180,7 +1210,7 @@ __device__ __forceinline__ void hop_tile(const HopParams& P, long tile, int rhs,
         } else if (tile_out) {
             // whole 16-byte groups of 16 consecutive sites
             __syncthreads();
-            const __amdgpu_buffer_rsrc_t dst = P.out ? R_.out : R_.out2;
+            const __amdgpu_buffer_rsrc_t dst = f_out ? R_.out : R_.out2;
             // all LDS reads first, then the stores (as in the update above)
             const int nO = Ls * L::NGR * 16;
             constexpr int IO = (4 * KK * L::NGR * 16 + NTHR - 1) / NTHR;
@@ -1215,7 +1245,7 @@ __device__ __forceinline__ void hop_tile(const HopParams& P, long tile, int rhs,
         }
     }
 
-    if (P.partial) {
+    if (f_partial) {
 #pragma unroll
         for (int off = 32; off >= 1; off >>= 1) nrm += __shfl_xor(nrm, off, 64);
         if (lane == 0) red[w] = nrm;
@@ -1239,12 +1269,12 @@ constexpr int hop_waves_per_eu() {
     return DWF_HOP_WAVES_PER_EU;
 }
 
-template <class S, int KK, int TAG = 0, int PM = 1>
+template <class S, int KK, int TAG = 0, int PM = 1, int EK = -1>
 __global__ __launch_bounds__(256)
 __attribute__((amdgpu_waves_per_eu(hop_waves_per_eu<S, PM>())))
 void hop_mfma_kernel(HopParams P) {
     extern __shared__ u32x4 hop_smem[];
-    hop_tile<S, KK, PM>(P, xcd_block(blockIdx.x, gridDim.x), blockIdx.y,
+    hop_tile<S, KK, PM, EK>(P, xcd_block(blockIdx.x, gridDim.x), blockIdx.y,
                     P.partial ? P.partial + (long)blockIdx.y * gridDim.x + blockIdx.x : nullptr,
                     reinterpret_cast<unsigned char*>(hop_smem));
 }
@@ -1455,19 +1485,42 @@ static unsigned hop_min_lds() {
     return v;
 }
 
-template <class S, int TAG, int PM>
-static void launch_hop_pm(const HopParams& P, int nrhs, hipStream_t st) {
+template <class S, int TAG, int PM, int EK>
+static void launch_hop_ek(const HopParams& P, int nrhs, hipStream_t st) {
     const int KK = (P.Ls + 3) / 4;
     dim3 grid(hop_grid_blocks(P.Vh), nrhs), block(64 * hop_waves(KK, sizeof(S) == 8));
     const unsigned smem_b = std::max(hop_smem_bytes<S>(KK, P.loc != nullptr), hop_min_lds());
     switch (KK) {
-        case 1: hipLaunchKernelGGL((hop_mfma_kernel<S, 1, TAG, PM>), grid, block, smem_b, st, P); break;
-        case 2: hipLaunchKernelGGL((hop_mfma_kernel<S, 2, TAG, PM>), grid, block, smem_b, st, P); break;
-        case 3: hipLaunchKernelGGL((hop_mfma_kernel<S, 3, TAG, PM>), grid, block, smem_b, st, P); break;
-        case 4: hipLaunchKernelGGL((hop_mfma_kernel<S, 4, TAG, PM>), grid, block, smem_b, st, P); break;
+        // Ls <= 4: the generic kernel (the specialised chained stage spills there)
+        case 1: hipLaunchKernelGGL((hop_mfma_kernel<S, 1, TAG, PM, -1>), grid, block, smem_b, st, P); break;
+        case 2: hipLaunchKernelGGL((hop_mfma_kernel<S, 2, TAG, PM, EK>), grid, block, smem_b, st, P); break;
+        case 3: hipLaunchKernelGGL((hop_mfma_kernel<S, 3, TAG, PM, EK>), grid, block, smem_b, st, P); break;
+        case 4: hipLaunchKernelGGL((hop_mfma_kernel<S, 4, TAG, PM, EK>), grid, block, smem_b, st, P); break;
         default: throw Error{DWF_EDIMS, "Ls > 16 not supported by the fused hop"};
     }
     DWF_HIP(hipGetLastError());
+}
+
+// Epilogue kinds compiled per pre-mix mode: the plain hop for every mode of
+// the solver's launches, the chained and update stages for mode 0 (they
+// never pre-mix); the stand-alone benchmark instance only as the plain
+// mode-1 hop it times.
+template <class S, int TAG, int PM>
+static void launch_hop_pm(const HopParams& P, int nrhs, hipStream_t st) {
+    const int ek = DWF_HOP_EK ? epilogue_kind(P) : -1;
+    if constexpr (TAG == 1 && PM != 1) {
+        launch_hop_ek<S, TAG, PM, -1>(P, nrhs, st);
+    } else if constexpr (TAG == 1 || PM != 0) {
+        if (ek == EK_PLAIN) launch_hop_ek<S, TAG, PM, EK_PLAIN>(P, nrhs, st);
+        else launch_hop_ek<S, TAG, PM, -1>(P, nrhs, st);
+    } else {
+        switch (ek) {
+            case EK_PLAIN: launch_hop_ek<S, TAG, PM, EK_PLAIN>(P, nrhs, st); break;
+            case EK_CHAIN: launch_hop_ek<S, TAG, PM, EK_CHAIN>(P, nrhs, st); break;
+            case EK_UPD: launch_hop_ek<S, TAG, PM, EK_UPD>(P, nrhs, st); break;
+            default: launch_hop_ek<S, TAG, PM, -1>(P, nrhs, st); break;
+        }
+    }
 }
 
 template <class S, int TAG>
