@@ -112,6 +112,11 @@ namespace dwf {
 #ifndef DWF_HOP_STAGE_BATCH64
 #define DWF_HOP_STAGE_BATCH64 0
 #endif
+// FP32 chained and update stages: request the local term right after the
+// direction loop, before the block barriers (see hop_tile).
+#ifndef DWF_HOP_LOC_EARLY32
+#define DWF_HOP_LOC_EARLY32 1
+#endif
 // Single-lattice launches of the fused CG stages use kernels compiled for
 // their epilogue kind (epilogue_kind below); 0: every launch tests its flags
 // at run time.
@@ -832,6 +837,14 @@ __device__ __forceinline__ void hop_tile(const HopParams& P, long tile, int rhs,
     }
     if constexpr (DWF_HOP_LDS_LINKS || L::LOC) __syncthreads();
 
+    // FP32 local term of the chained and update stages (per-component global
+    // reads, not tiled in LDS): requested right after the direction loop, so
+    // that the reads are in flight across the block barriers instead of
+    // after them.  Compiled only for those epilogue kinds (a no-local-term
+    // launch would still issue the reads).
+    constexpr int CPW_ = 12 / hop_waves(KK, sizeof(S) == 8);
+    constexpr bool LOCE = DWF_HOP_LOC_EARLY32 && sizeof(S) == 4 && !L::LOC && (EK == EK_CHAIN || EK == EK_UPD);
+    R lre[LOCE ? CPW_ : 1][LOCE ? KK : 1], lie[LOCE ? CPW_ : 1][LOCE ? KK : 1];
     R h[G][24];
     {
 #pragma unroll
@@ -913,6 +926,22 @@ __device__ __forceinline__ void hop_tile(const HopParams& P, long tile, int rhs,
 #pragma unroll
             for (int k = 0; k < 24; ++k) h[g][k] = inval ? R(0) : h[g][k];
         }
+    }
+    if constexpr (LOCE) {
+        // slices past Ls read slice 0 and are zeroed (branch-free: measured,
+        // a branch among these reads made the register allocator spill
+        // across the direction loop)
+#pragma unroll
+        for (int q = 0; q < CPW_; ++q)
+#pragma unroll
+            for (int kk = 0; kk < KK; ++kk) {
+                const int cp = w * CPW_ + q, s_ = sc + 4 * kk;
+                const unsigned off = sxb + (unsigned)(s_ < Ls ? s_ : 0) * (12u / PK) * gb +
+                                     (unsigned)(cp / PK) * gb + (unsigned)(cp % PK) * CB;
+                const u32x2 v = __builtin_amdgcn_raw_buffer_load_b64(R_.loc, off, 0u, 0);
+                lre[q][kk] = s_ < Ls ? __uint_as_float(v.x) : R(0);
+                lie[q][kk] = s_ < Ls ? __uint_as_float(v.y) : R(0);
+            }
     }
     if constexpr (!L::SEP) __syncthreads();   // hs shares storage with the staged links
 
@@ -1046,6 +1075,9 @@ __device__ __forceinline__ void hop_tile(const HopParams& P, long tile, int rhs,
                         lr[kk] = bf16_to_f32(v & 0xffffu);
                         li[kk] = bf16_to_f32(v >> 16);
                     }
+                } else if constexpr (LOCE) {
+                    lr[kk] = lre[q][kk];
+                    li[kk] = lie[q][kk];
                 } else {
                     if (s < Ls) bload<S, WAUX>(R_.loc, coff(s, cp), 0u, lr[kk], li[kk]);
                 }
