@@ -117,6 +117,10 @@ namespace dwf {
 #ifndef DWF_HOP_LOC_EARLY32
 #define DWF_HOP_LOC_EARLY32 1
 #endif
+// ... and the update stage its old residual values as well
+#ifndef DWF_HOP_UPD_EARLY32
+#define DWF_HOP_UPD_EARLY32 1
+#endif
 // Single-lattice launches of the fused CG stages use kernels compiled for
 // their epilogue kind (epilogue_kind below); 0: every launch tests its flags
 // at run time.
@@ -845,6 +849,11 @@ __device__ __forceinline__ void hop_tile(const HopParams& P, long tile, int rhs,
     constexpr int CPW_ = 12 / hop_waves(KK, sizeof(S) == 8);
     constexpr bool LOCE = DWF_HOP_LOC_EARLY32 && sizeof(S) == 4 && !L::LOC && (EK == EK_CHAIN || EK == EK_UPD);
     R lre[LOCE ? CPW_ : 1][LOCE ? KK : 1], lie[LOCE ? CPW_ : 1][LOCE ? KK : 1];
+    // the update stage's old values (its 16-byte groups of this thread),
+    // requested with the local term
+    constexpr bool UPDE = LOCE && DWF_HOP_UPD_EARLY32 && EK == EK_UPD;
+    constexpr int IUE = UPDE ? (4 * KK * 6 * 16 + NTHR - 1) / NTHR : 1;
+    u32x4 uve[IUE];
     R h[G][24];
     {
 #pragma unroll
@@ -942,6 +951,18 @@ __device__ __forceinline__ void hop_tile(const HopParams& P, long tile, int rhs,
                 lre[q][kk] = s_ < Ls ? __uint_as_float(v.x) : R(0);
                 lie[q][kk] = s_ < Ls ? __uint_as_float(v.y) : R(0);
             }
+        if constexpr (UPDE) {
+            const unsigned gbu = (unsigned)P.Vhp * 16u;
+            const int nU = Ls * 6 * 16;
+#pragma unroll
+            for (int i = 0; i < IUE; ++i) {
+                const int e = min(tid + i * NTHR, nU - 1);
+                const int jj = e & 15, g = e >> 4;
+                const long se = tile * 16 + jj;
+                const unsigned sxe = (unsigned)(se < Vh ? se : Vh - 1);
+                uve[i] = __builtin_amdgcn_raw_buffer_load_b128(R_.upd, sxe * 16u + (unsigned)g * gbu, 0u, DWF_HOP_NT_LOAD);
+            }
+        }
     }
     if constexpr (!L::SEP) __syncthreads();   // hs shares storage with the staged links
 
@@ -1218,7 +1239,11 @@ __device__ __forceinline__ void hop_tile(const HopParams& P, long tile, int rhs,
                 av[i] = *reinterpret_cast<const float2*>(run0 + (2 * (2 * q2)) * 64);
                 bv[i] = *reinterpret_cast<const float2*>(run0 + (2 * (2 * q2 + 1)) * 64);
                 const unsigned sxe = (unsigned)(se < Vh ? se : Vh - 1);
-                uv[i] = __builtin_amdgcn_raw_buffer_load_b128(R_.upd, sxe * 16u + (unsigned)g * gbu, 0u, DWF_HOP_NT_LOAD);
+                if constexpr (UPDE)
+                    uv[i] = uve[i];
+                else
+                    uv[i] = __builtin_amdgcn_raw_buffer_load_b128(R_.upd, sxe * 16u + (unsigned)g * gbu, 0u,
+                                                                  DWF_HOP_NT_LOAD);
             }
 #pragma unroll
             for (int i = 0; i < IU; ++i) {
