@@ -1559,13 +1559,14 @@ static void launch_hop_ek(const HopParams& P, int nrhs, hipStream_t st) {
 }
 
 // Epilogue kinds compiled per pre-mix mode: the plain hop for every mode of
-// the solver's launches, the chained and update stages for mode 0 (they
-// never pre-mix); the stand-alone benchmark instance only as the plain
-// mode-1 hop it times.
+// the solver's launches (FP64: mode 0 only), the chained and update stages
+// for mode 0 (they never pre-mix); the stand-alone benchmark instance only as
+// the plain mode-1 hop it times.
 template <class S, int TAG, int PM>
 static void launch_hop_pm(const HopParams& P, int nrhs, hipStream_t st) {
     const int ek = DWF_HOP_EK ? epilogue_kind(P) : -1;
-    if constexpr (TAG == 1 && PM != 1) {
+    if constexpr ((TAG == 1 && PM != 1) || (sizeof(S) == 8 && PM != 0)) {
+        // (FP64 pre-mixing hops: the specialised plain form spills one value)
         launch_hop_ek<S, TAG, PM, -1>(P, nrhs, st);
     } else if constexpr (TAG == 1 || PM != 0) {
         if (ek == EK_PLAIN) launch_hop_ek<S, TAG, PM, EK_PLAIN>(P, nrhs, st);

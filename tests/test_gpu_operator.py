@@ -154,7 +154,7 @@ def test_free_field_plane_wave_eigen():
 R_TOL = {0: 1e-13, 1: 1e-5, 2: 3e-2}
 
 
-@pytest.mark.parametrize("case", CASES[:4])
+@pytest.mark.parametrize("case", CASES[:5])
 @pytest.mark.parametrize("prec", [0, 1, 2])
 def test_cg_residual_update(case, prec):
     """The fused CGNR step (r -= alpha D^dag D^ p inside the last hop, |r|^2
