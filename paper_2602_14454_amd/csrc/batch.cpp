@@ -129,6 +129,7 @@ struct HopClass {
     int KK;
     std::vector<int> items;   // indices into Batch::items
     int pm[4] = {-1, -1, -1, -1};   // per stage: the items' common pre-mix mode, -1 if mixed
+    int ek[4] = {-1, -1, -1, -1};   // per stage: the items' common epilogue kind, -1 if mixed
 };
 
 struct Stream {
@@ -256,6 +257,8 @@ struct NormalHops {
                 for (int k = 0; k < 4; ++k) {
                     int& pm = c.pm[k];
                     pm = q == 0 ? sp[k]->pre_mode : (pm == sp[k]->pre_mode ? pm : -1);
+                    const int e = hop_epilogue_kind(*sp[k]);
+                    c.ek[k] = q == 0 ? e : (c.ek[k] == e ? e : -1);
                 }
                 for (int q = 0; q < ring; ++q) {
                     const size_t shift = (size_t)q * ring_bytes;
@@ -284,7 +287,7 @@ struct NormalHops {
             const HopParams* it = items_dev.as<HopParams>() + table(sidx, q) * per_stage + first;
             const int* m = meta_dev.as<int>() + ci * meta_per_class;
             launch_hop_batch(kind, classes[ci].KK, it, m, (int)classes[ci].items.size(), blocks[ci], nrb, order,
-                             stage_loc[sidx], classes[ci].pm[sidx], st);
+                             stage_loc[sidx], classes[ci].pm[sidx], classes[ci].ek[sidx], st);
             first += classes[ci].items.size();
         }
     }

@@ -63,9 +63,13 @@ void launch_hop(int kind, const HopParams& P, int nrhs, hipStream_t st, int benc
 // ceil(Ls/4) = KK for all) with block prefix sums and RHS counts in `meta`
 // (device, 2 * nitems + 1 ints); `blocks` = meta[nitems].  has_loc: the
 // items carry a local term (all or none of them).  pm: the pre-mix mode
-// every item has (0, 1, 2), or -1 when they differ.
+// every item has (0, 1, 2), or -1 when they differ.  ek: the epilogue kind
+// every item has (hop_epilogue_kind), or -1 when they differ.
 void launch_hop_batch(int kind, int KK, const HopParams* items, const int* meta, int nitems, int blocks, int nrb,
-                      int order, bool has_loc, int pm, hipStream_t st);
+                      int order, bool has_loc, int pm, int ek, hipStream_t st);
+// The epilogue kind of a launch that the hop kernels are compiled for (the
+// fused stages of the CG iteration), or -1 (flags tested at run time).
+int hop_epilogue_kind(const HopParams& P);
 void launch_copy(void* dst, const void* src, size_t bytes, hipStream_t st);
 void launch_mix(int kind, const MixParams& P, int nrhs, hipStream_t st);
 

@@ -1391,7 +1391,7 @@ constexpr int hop_batch1_waves_per_eu() {
     return sizeof(S) == 8 ? DWF_HOP_WAVES_PER_EU64_BATCH : DWF_HOP_BATCH1_WPE;
 }
 
-template <class S, int KK, int PM>
+template <class S, int KK, int PM, int EK = -1>
 __global__ __launch_bounds__(256)
 __attribute__((amdgpu_waves_per_eu(hop_batch1_waves_per_eu<S, PM>())))
 void hop_batch1_kernel(const HopParams* __restrict__ items, const int* __restrict__ meta, int nitems, int order) {
@@ -1417,7 +1417,7 @@ void hop_batch1_kernel(const HopParams* __restrict__ items, const int* __restric
         if (part && threadIdx.x == 0) *part = 0.0;
         return;
     }
-    hop_tile<S, KK, PM>(P, tile, r, part, reinterpret_cast<unsigned char*>(hop_smem));
+    hop_tile<S, KK, PM, EK>(P, tile, r, part, reinterpret_cast<unsigned char*>(hop_smem));
 }
 
 // The work list with NR right-hand sides per block sharing the tile's
@@ -1591,15 +1591,37 @@ static void launch_hop_t(const HopParams& P, int nrhs, hipStream_t st) {
     }
 }
 
-template <class S, int PM>
-static void launch_hop_batch1_pm(int KK, dim3 grid, dim3 block, unsigned smem_b, const HopParams* items,
+template <class S, int PM, int EK>
+static void launch_hop_batch1_ek(int KK, dim3 grid, dim3 block, unsigned smem_b, const HopParams* items,
                                  const int* meta, int nitems, int order, hipStream_t st) {
     switch (KK) {
-        case 1: hipLaunchKernelGGL((hop_batch1_kernel<S, 1, PM>), grid, block, smem_b, st, items, meta, nitems, order); break;
-        case 2: hipLaunchKernelGGL((hop_batch1_kernel<S, 2, PM>), grid, block, smem_b, st, items, meta, nitems, order); break;
-        case 3: hipLaunchKernelGGL((hop_batch1_kernel<S, 3, PM>), grid, block, smem_b, st, items, meta, nitems, order); break;
-        case 4: hipLaunchKernelGGL((hop_batch1_kernel<S, 4, PM>), grid, block, smem_b, st, items, meta, nitems, order); break;
+        // Ls <= 4: the generic kernel, as for single lattices
+        case 1: hipLaunchKernelGGL((hop_batch1_kernel<S, 1, PM, -1>), grid, block, smem_b, st, items, meta, nitems, order); break;
+        case 2: hipLaunchKernelGGL((hop_batch1_kernel<S, 2, PM, EK>), grid, block, smem_b, st, items, meta, nitems, order); break;
+        case 3: hipLaunchKernelGGL((hop_batch1_kernel<S, 3, PM, EK>), grid, block, smem_b, st, items, meta, nitems, order); break;
+        case 4: hipLaunchKernelGGL((hop_batch1_kernel<S, 4, PM, EK>), grid, block, smem_b, st, items, meta, nitems, order); break;
         default: throw Error{DWF_EDIMS, "Ls > 16 not supported by the fused hop"};
+    }
+}
+
+// ek: the items' common epilogue kind (-1: mixed or none), compiled in on
+// the same terms as for single-lattice launches
+template <class S, int PM>
+static void launch_hop_batch1_pm(int KK, dim3 grid, dim3 block, unsigned smem_b, const HopParams* items,
+                                 const int* meta, int nitems, int order, int ek, hipStream_t st) {
+    if (!DWF_HOP_EK) ek = -1;
+    if constexpr (PM < 0 || (sizeof(S) == 8 && PM != 0)) {
+        launch_hop_batch1_ek<S, PM, -1>(KK, grid, block, smem_b, items, meta, nitems, order, st);
+    } else if constexpr (PM != 0) {
+        if (ek == EK_PLAIN) launch_hop_batch1_ek<S, PM, EK_PLAIN>(KK, grid, block, smem_b, items, meta, nitems, order, st);
+        else launch_hop_batch1_ek<S, PM, -1>(KK, grid, block, smem_b, items, meta, nitems, order, st);
+    } else {
+        switch (ek) {
+            case EK_PLAIN: launch_hop_batch1_ek<S, PM, EK_PLAIN>(KK, grid, block, smem_b, items, meta, nitems, order, st); break;
+            case EK_CHAIN: launch_hop_batch1_ek<S, PM, EK_CHAIN>(KK, grid, block, smem_b, items, meta, nitems, order, st); break;
+            case EK_UPD: launch_hop_batch1_ek<S, PM, EK_UPD>(KK, grid, block, smem_b, items, meta, nitems, order, st); break;
+            default: launch_hop_batch1_ek<S, PM, -1>(KK, grid, block, smem_b, items, meta, nitems, order, st); break;
+        }
     }
 }
 
@@ -1666,16 +1688,16 @@ static bool launch_hop_multi(int KK, int blocks, int nrb, int order, bool loc, i
 
 template <class S>
 static void launch_hop_batch_t(int KK, const HopParams* items, const int* meta, int nitems, int blocks, int nrb,
-                               int order, bool loc, int pm, hipStream_t st) {
+                               int order, bool loc, int pm, int ek, hipStream_t st) {
     if (launch_hop_multi<S>(KK, blocks, nrb, order, loc, pm, items, meta, nitems, st)) return;
     dim3 grid(blocks), block(64 * hop_waves(KK, sizeof(S) == 8));
     const unsigned smem_b = hop_smem_bytes<S>(KK, loc);
     if (nrb == 1) {
         switch (pm) {
-            case 0: launch_hop_batch1_pm<S, 0>(KK, grid, block, smem_b, items, meta, nitems, order, st); break;
-            case 1: launch_hop_batch1_pm<S, 1>(KK, grid, block, smem_b, items, meta, nitems, order, st); break;
-            case 2: launch_hop_batch1_pm<S, 2>(KK, grid, block, smem_b, items, meta, nitems, order, st); break;
-            default: launch_hop_batch1_pm<S, -1>(KK, grid, block, smem_b, items, meta, nitems, order, st); break;
+            case 0: launch_hop_batch1_pm<S, 0>(KK, grid, block, smem_b, items, meta, nitems, order, ek, st); break;
+            case 1: launch_hop_batch1_pm<S, 1>(KK, grid, block, smem_b, items, meta, nitems, order, ek, st); break;
+            case 2: launch_hop_batch1_pm<S, 2>(KK, grid, block, smem_b, items, meta, nitems, order, ek, st); break;
+            default: launch_hop_batch1_pm<S, -1>(KK, grid, block, smem_b, items, meta, nitems, order, ek, st); break;
         }
         DWF_HIP(hipGetLastError());
         return;
@@ -1689,13 +1711,15 @@ static void launch_hop_batch_t(int KK, const HopParams* items, const int* meta, 
     DWF_HIP(hipGetLastError());
 }
 
+int hop_epilogue_kind(const HopParams& P) { return epilogue_kind(P); }
+
 void launch_hop_batch(int kind, int KK, const HopParams* items, const int* meta, int nitems, int blocks, int nrb,
-                      int order, bool has_loc, int pm, hipStream_t st) {
+                      int order, bool has_loc, int pm, int ek, hipStream_t st) {
     if (blocks <= 0) return;
     switch (kind) {
-        case ST_F64: launch_hop_batch_t<double>(KK, items, meta, nitems, blocks, nrb, order, has_loc, pm, st); break;
-        case ST_F32: launch_hop_batch_t<float>(KK, items, meta, nitems, blocks, nrb, order, has_loc, pm, st); break;
-        case ST_BF16: launch_hop_batch_t<bf16s>(KK, items, meta, nitems, blocks, nrb, order, has_loc, pm, st); break;
+        case ST_F64: launch_hop_batch_t<double>(KK, items, meta, nitems, blocks, nrb, order, has_loc, pm, ek, st); break;
+        case ST_F32: launch_hop_batch_t<float>(KK, items, meta, nitems, blocks, nrb, order, has_loc, pm, ek, st); break;
+        case ST_BF16: launch_hop_batch_t<bf16s>(KK, items, meta, nitems, blocks, nrb, order, has_loc, pm, ek, st); break;
         default: throw Error{DWF_EINVAL, "bad storage kind"};
     }
 }
