@@ -58,6 +58,14 @@ CgWork::CgWork(const dwf_op* op, int kx_, int kp_, int nrhs_) : kx(kx_), kp(kp_)
     scal.alloc(CG_NSLOTS * sizeof(double));
 }
 
+int next_check_gap(int k, double rr, int k0, double rr0, double stop, int every) {
+    if (every <= 1 || k <= k0 || !(rr > stop) || !(rr0 > rr)) return every;
+    const double per_iter = std::log(rr / rr0) / (double)(k - k0);   // < 0
+    const double todo = std::log(stop / rr) / per_iter;                // > 0
+    if (!(todo > 0.0)) return every;
+    return (int)std::max(1.0, std::min((double)every, std::ceil(todo)));
+}
+
 int cgnr(const dwf_op* op, CgWork& W, const void* b_kp, double tol_rel, int maxiter, int check_every,
          hipStream_t st, double* final_rel, bool* nan_seen, const IterHook& on_iter) {
     const long n = W.n;
@@ -97,6 +105,8 @@ int cgnr(const dwf_op* op, CgWork& W, const void* b_kp, double tol_rel, int maxi
     double rr = rr0;
     int cur = 0, pend = 0;   // ring slot of p_k; slots [0, pend) hold directions not yet in x
     double* alphas = W.alphas.as<double>();
+    int next_check = check_every, k_prev = 0;
+    double rr_prev = rr0;
     while (k < maxiter) {
         // alpha, then r -= alpha D^dag D^ p inside the last hop (|r|^2 partials)
         void* pk = ring ? slot(cur) : W.p.p;
@@ -121,7 +131,7 @@ int cgnr(const dwf_op* op, CgWork& W, const void* b_kp, double tol_rel, int maxi
         }
         ++k;
         if (on_iter) on_iter(k, W.x.p);
-        if (k % check_every == 0 || k == maxiter) {
+        if (k == next_check || k == maxiter) {
             read_scalars(scal, hs, st);
             rr = hs.h[CG_RR];
             if (hs.h[CG_NANFLAG] != 0.0 || !std::isfinite(rr)) {
@@ -129,6 +139,9 @@ int cgnr(const dwf_op* op, CgWork& W, const void* b_kp, double tol_rel, int maxi
                 break;
             }
             if (rr <= stop) break;
+            next_check = k + next_check_gap(k, rr, k_prev, rr_prev, stop, check_every);
+            k_prev = k;
+            rr_prev = rr;
         }
     }
     if (ring) cg_accumulate_x(W.kx, W.kp, W.x.p, W.ring.p, alphas, pend, n, st, Vhp);
@@ -179,6 +192,8 @@ static int cgnr_right(const dwf_op* op, CgWork& W, const void* b_kp, double tol_
     const double stop = tol_rel * tol_rel * rr0;
     double rr = rr0;
     int k = 0;
+    int next_check = check_every, k_prev = 0;
+    double rr_prev = rr0;
     while (k < maxiter) {
         // q = D_R p = M D^ M^-1 p, alpha = rr / |q|^2
         mix(op, W.kp, W.p.p, ra, MAT_MINV, nullptr, 1, st);
@@ -193,7 +208,7 @@ static int cgnr_right(const dwf_op* op, CgWork& W, const void* b_kp, double tol_
         finalize(partial, blas_grid(n), 1, scal, 2, st);
         cg_update_p(W.kx, W.kp, W.p.p, W.r.p, n, scal + CG_BETA, st, Vhp);
         ++k;
-        if (k % check_every == 0 || k == maxiter) {
+        if (k == next_check || k == maxiter) {
             read_scalars(scal, hs, st);
             rr = hs.h[CG_RR];
             if (hs.h[CG_NANFLAG] != 0.0 || !std::isfinite(rr)) {
@@ -201,6 +216,9 @@ static int cgnr_right(const dwf_op* op, CgWork& W, const void* b_kp, double tol_
                 break;
             }
             if (rr <= stop) break;
+            next_check = k + next_check_gap(k, rr, k_prev, rr_prev, stop, check_every);
+            k_prev = k;
+            rr_prev = rr;
         }
     }
     if (final_rel) *final_rel = std::sqrt(rr / rr0);
