@@ -119,8 +119,6 @@ int cgnr5(const dwf_op* op, Eo5Cg& W, const double* coef, double tol_rel, int ma
     const double stop = tol_rel * tol_rel * rr0;
     double rr = rr0;
     int k = 0;
-    int next_check = check_every, k_prev = 0;   // the checks of cgnr (next_check_gap)
-    double rr_prev = rr0;
     while (k < maxiter) {
         eo5_dhat(op, kp, 0, W.q.p, W.p.p, W.to.p, coef, st);              // q = D^5 p
         norm2_partial(kp, W.q.p, n, partial, st);
@@ -130,7 +128,7 @@ int cgnr5(const dwf_op* op, Eo5Cg& W, const double* coef, double tol_rel, int ma
         finalize(partial, blas_grid(n), 1, scal, 2, st);                   // beta, |r|^2
         cg_update_p(kp, kp, W.p.p, W.r.p, n, scal + CG_BETA, st);
         ++k;
-        if (k == next_check || k == maxiter) {
+        if (k % check_every == 0 || k == maxiter) {
             read_back(scal, hs, st);
             rr = hs.h[CG_RR];
             if (hs.h[CG_NANFLAG] != 0.0 || !std::isfinite(rr)) {
@@ -138,9 +136,6 @@ int cgnr5(const dwf_op* op, Eo5Cg& W, const double* coef, double tol_rel, int ma
                 break;
             }
             if (rr <= stop) break;
-            next_check = k + next_check_gap(k, rr, k_prev, rr_prev, stop, check_every);
-            k_prev = k;
-            rr_prev = rr;
         }
     }
     *final_rel = std::sqrt(rr / rr0);

@@ -42,16 +42,13 @@ int ring_slots(size_t slot_bytes);
 // Result in W.x.  Returns the iteration count.
 // on_iter (optional) is called after iteration k with the device pointer of x_k.
 using IterHook = std::function<void(int, const void*)>;
-// Iterations from check k (|r|^2 = rr; the previous check at k0 read rr0)
-// until the next host convergence check: `every`, or fewer when the decrease
-// since k0, taken as geometric, predicts that |r|^2 reaches `stop` sooner.  It
-// only brings a check forward, so a solve never runs more iterations past its
-// target than with the fixed period, and on average fewer (the fixed period
-// stops half a period late).
-int next_check_gap(int k, double rr, int k0, double rr0, double stop, int every);
-
+// predict_checks: the host convergence check comes at most check_every
+// iterations after the previous one, sooner where the decrease of |r|^2 since
+// that check, taken as geometric, predicts the target (see next_check_gap in
+// solver.cpp); false: every check_every iterations.
 int cgnr(const dwf_op* op, CgWork& W, const void* b_kp, double tol_rel, int maxiter, int check_every,
-         hipStream_t st, double* final_rel, bool* nan_seen, const IterHook& on_iter = IterHook());
+         hipStream_t st, double* final_rel, bool* nan_seen, const IterHook& on_iter = IterHook(),
+         bool predict_checks = false);
 
 // defect-correction inner target and step ratio (solver.cpp); DWF_TRACE in
 // the environment prints one line per outer step to stderr
