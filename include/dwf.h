@@ -78,8 +78,9 @@ typedef struct {
     int      inner_prec;  /* dwf_prec of the inner CG for DWF_ALGO_DC (F32 or BF16) */
     double   inner_tol;   /* relative reduction asked of each inner solve (DC) */
     int      check_every; /* host convergence check period of the CG loop (>= 1); the FP32 inner
-                             steps of DWF_ALGO_DC check sooner where the decrease of the residual
-                             since the previous check predicts the target (never later) */
+                             step of DWF_ALGO_DC meant to reach tol checks sooner where the
+                             decrease of the residual since the previous check predicts its
+                             target (never later) */
     int      paper_mode;  /* 1: plain CGNR in inner_prec stopping at |r|^2/|D^dag b~|^2 < 1e-14
                              (Sec. 3.2 criterion), no defect correction; iteration counting only.
                              Returns DWF_NOT_CONVERGED (converged = 0) if maxiter stops it first. */

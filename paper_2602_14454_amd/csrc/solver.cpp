@@ -330,10 +330,11 @@ bool trace_on() {
 // that brings the 5D residual to tol/2; a step that cannot (the reduction
 // would be below what the inner precision resolves) takes the precision's
 // standard reduction.  FP64 restarts of plain CGNR use the same rule.
-double dc_target(double tol, double rel5, int kp, double standard, double f) {
+double dc_target(double tol, double rel5, int kp, double standard, double f, bool* last) {
     const double floor = kp == ST_F64 ? 1e-15 : (kp == ST_F32 ? 1e-6 : 1e-2);
     const double need = 0.5 * tol / std::max(rel5, 1e-300);
     const double want = need >= floor ? need : standard;
+    if (last) *last = need >= floor;
     return std::min(0.5, std::max(1e-13, want / f));
 }
 
@@ -463,7 +464,8 @@ int solve(const dwf_op* op, void* x5, const void* b5, const dwf_solve_params* pr
         convert(kp, ST_F64, rin.p, rh.p, n, st, Vhp);
         // FP64: the first step is the textbook CGNR stop; restarts are calibrated
         const bool plain = prm->paper_mode || (kp == ST_F64 && outer == 0);
-        const double itol = plain ? inner_tol : dc_target(tol, rel5, kp, inner_tol, f_ratio);
+        bool last_step = false;
+        const double itol = plain ? inner_tol : dc_target(tol, rel5, kp, inner_tol, f_ratio, &last_step);
         int it = 0;
         const void* xin = nullptr;
         if (use_fgcr) {
@@ -489,14 +491,14 @@ int solve(const dwf_op* op, void* x5, const void* b5, const dwf_solve_params* pr
             mix(op, ST_F64, te.p, to.p, MAT_MINV, nullptr, 1, st);
             xin = to.p;
         } else {
-            // FP32 inner steps check where the target is predicted: each is
-            // long against the period, so stopping at the target saves the
-            // last step's overshoot.  Measured on 24^3x48 (period 8): DC-FP32
-            // 376 -> 366 iterations, but FP64 CGNR 360 -> 406 (its first stop,
-            // the normal-equation test, then misses the 5D target and
-            // restarts) and DC-BF16 416 -> 429 (its short steps gain from the
-            // overshoot), which keep the fixed period.
-            const bool predict = kp == ST_F32 && !prm->paper_mode;
+            // The FP32 step meant to reach tol checks where its target is
+            // predicted (iterations past it are waste); earlier steps keep the
+            // fixed period, whose overshoot is progress that a later step
+            // would otherwise have to make after a restart (predicted checks
+            // in every FP32 step took one 16^3x32 point source 200 -> 220
+            // iterations; in every CG loop, FP64 CGNR 360 -> 406 and DC-BF16
+            // 416 -> 429 on 24^3x48).
+            const bool predict = kp == ST_F32 && !prm->paper_mode && last_step;
             it = cgnr(op, *W, rin.p, itol, maxiter - total, prm->check_every, st, &last_inner_rel, &nan_seen,
                       IterHook(), predict);
             total += it;

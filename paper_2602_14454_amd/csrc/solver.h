@@ -52,7 +52,9 @@ int cgnr(const dwf_op* op, CgWork& W, const void* b_kp, double tol_rel, int maxi
 
 // defect-correction inner target and step ratio (solver.cpp); DWF_TRACE in
 // the environment prints one line per outer step to stderr
-double dc_target(double tol, double rel5, int kp, double standard, double f);
+// *last (optional): the step asks for what reaching tol needs (the intended
+// last step) rather than the standard reduction
+double dc_target(double tol, double rel5, int kp, double standard, double f, bool* last = nullptr);
 double dc_ratio(double achieved, double requested);
 bool trace_on();
 
