@@ -134,10 +134,14 @@ namespace dwf {
 #define DWF_HOP_COEF_LDS32 1
 #endif
 // FP32: the hop results (hs) in LDS of their own rather than over the staged
-// links (4 blocks of 35.6 KB per CU still fit), which saves one block
-// barrier.  Measured without gain (409 vs 408 us): off.
+// links, which saves one block barrier.  With the staged s-mix matrices a
+// block then takes 42.8 KB of LDS, so 3 blocks (12 waves) fit per CU instead
+// of 4.  Measured on 24^3x48, Ls = 16: the plain hop unchanged (390 us), the
+// DC-FP32 solve 2-3 % faster; the same 3-block cap without the separate
+// region gives most of that (the fused CG stages run better with fewer blocks
+// in flight per CU), the saved barrier the rest.
 #ifndef DWF_HOP_HS_SEP32
-#define DWF_HOP_HS_SEP32 0
+#define DWF_HOP_HS_SEP32 1
 #endif
 // Cache policy of the streamed accesses (the outputs, the local term and
 // the fused update, each touched once): 0 default, 2 non-temporal, so that
