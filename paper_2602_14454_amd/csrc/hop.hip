@@ -139,7 +139,9 @@ namespace dwf {
 // of 4.  Measured on 24^3x48, Ls = 16: the plain hop unchanged (390 us), the
 // DC-FP32 solve 2-3 % faster; the same 3-block cap without the separate
 // region gives most of that (the fused CG stages run better with fewer blocks
-// in flight per CU), the saved barrier the rest.
+// in flight per CU), the saved barrier the rest.  Ls = 16 (4-wave blocks)
+// only: with 3-wave blocks (Ls = 12) it takes 5 blocks per CU down to 4, and
+// a batch of 12 Ls = 12 solves was 2 % slower.
 #ifndef DWF_HOP_HS_SEP32
 #define DWF_HOP_HS_SEP32 1
 #endif
@@ -617,7 +619,7 @@ template <class S, int KK> struct HopSmem {
     static constexpr unsigned lnk_b = lnk_entries<S>() * 16 + 128 * 4;
     // SEP: hs after the staged tables instead of over them (no block
     // barrier between the last link read and the first hs write)
-    static constexpr bool SEP = sizeof(S) == 4 && DWF_HOP_HS_SEP32;
+    static constexpr bool SEP = sizeof(S) == 4 && DWF_HOP_HS_SEP32 && KK == 4;
     static constexpr unsigned hs_off = SEP ? ((lnk_b + 15u) & ~15u) : 0u;
     static constexpr unsigned mx = SEP ? hs_off + hs_b : (hs_b > lnk_b ? hs_b : lnk_b);
     static constexpr unsigned r0 = (mx + 15u) & ~15u;
